@@ -1,0 +1,266 @@
+"""Pins for the CPU oracle: hand-worked values, brute force, identities and library routines.
+
+Nothing here compares the oracle with itself alone: each test checks it against a value
+worked by hand from the paper's definitions, an exhaustive enumeration, an identity that
+follows from Eq. (1), numpy's Philox, or an independent numpy re-simulation of the rules.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_11248_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def np_cost(F, D, p):
+    p = np.asarray(p)
+    return int((F[p][:, p].astype(np.int64) * D).sum())
+
+
+def np_all_swap_deltas(F, D, p):
+    """Brute force: cost of every exchanged permutation minus the cost of p, packed order."""
+    n = len(p)
+    z = np_cost(F, D, p)
+    out = []
+    for r in range(n):
+        for s in range(r + 1, n):
+            q = np.array(p).copy()
+            q[r], q[s] = q[s], q[r]
+            out.append(np_cost(F, D, q) - z)
+    return np.array(out, dtype=np.int64)
+
+
+def np_brute_force_optimum(F, D):
+    n = F.shape[0]
+    P = np.array(list(itertools.permutations(range(n))), dtype=np.int64)
+    best = None
+    for chunk in np.array_split(P, max(1, len(P) // 20000)):
+        c = (F[chunk[:, :, None], chunk[:, None, :]].astype(np.int64) * D[None]).sum(axis=(1, 2))
+        m = int(c.min())
+        best = m if best is None else min(best, m)
+    return best
+
+
+def test_worked_example_by_hand():
+    g = json.load(open(os.path.join(GOLD, "worked_n3.json")))
+    F, D, p = np.array(g["F"]), np.array(g["D"]), np.array(g["perm"])
+    assert oracle.cost(F, D, p) == g["cost"]
+    assert list(oracle.delta_table(F, D, p)) == g["deltas_packed"]
+    for key, c in g["all_costs"].items():
+        assert oracle.cost(F, D, [int(x) for x in key.split(",")]) == c
+    q, c, steps, _ = oracle.two_opt(F, D, p)
+    assert list(q) == g["two_opt_perm"] and c == g["two_opt_cost"] and steps == g["two_opt_steps"]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_cost_matches_numpy(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 40))
+    F, D = W.random_instance(rng, n, 0, 999, diag=True)
+    for _ in range(5):
+        p = rng.permutation(n)
+        assert oracle.cost(F, D, p) == np_cost(F, D, p)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_delta_exhaustive_small_with_diagonals(n):
+    """Eq. (2) + diagonal term equals z(swap) - z for every permutation and pair (n <= 5)."""
+    rng = np.random.default_rng(100 + n)
+    F, D = W.random_instance(rng, n, -20, 50, diag=True)
+    for p in itertools.permutations(range(n)):
+        assert list(oracle.delta_table(F, D, p)) == list(np_all_swap_deltas(F, D, p))
+
+
+def test_delta_exhaustive_n6():
+    rng = np.random.default_rng(7)
+    F, D = W.random_instance(rng, 6, 0, 9, diag=True)
+    for p in itertools.permutations(range(6)):
+        assert list(oracle.delta_table(F, D, p)) == list(np_all_swap_deltas(F, D, p))
+
+
+@pytest.mark.parametrize("n", [7, 16, 33, 64])
+def test_delta_random_larger(n):
+    rng = np.random.default_rng(n)
+    F, D = W.random_instance(rng, n, 0, 255, diag=True)
+    p = rng.permutation(n)
+    assert (oracle.delta_table(F, D, p) == np_all_swap_deltas(F, D, p)).all()
+
+
+def test_printed_eq2_needs_diagonal_term():
+    """With non-zero diagonals the term for d_rr, d_ss matters: some delta differs from the
+    version without it, and only the version with it satisfies the z(swap) - z identity."""
+    rng = np.random.default_rng(3)
+    F, D = W.random_instance(rng, 5, 1, 9, diag=True)
+    p = np.arange(5)
+    full = oracle.delta_table(F, D, p)
+    diag_term = []
+    for r in range(5):
+        for s in range(r + 1, 5):
+            diag_term.append((D[s, s] - D[r, r]) * (F[p[r], p[r]] - F[p[s], p[s]]))
+    assert (full == np_all_swap_deltas(F, D, p)).all()
+    assert any(t != 0 for t in diag_term)
+
+
+@pytest.mark.parametrize("seed,n,sym", [(0, 8, False), (1, 13, True), (2, 24, False), (3, 31, False)])
+def test_incremental_update_matches_fresh_table(seed, n, sym):
+    """Taillard's O(1) update + recompute of the rows of r and s reproduces a fresh table
+    after every move of a random walk; the pair (r, s) flips sign."""
+    rng = np.random.default_rng(seed)
+    F, D = W.random_instance(rng, n, 0, 99, symmetric=sym, diag=True)
+    p = rng.permutation(n).astype(np.int32)
+    tab = oracle.delta_table(F, D, p)
+    for _ in range(40):
+        r, s = sorted(rng.choice(n, 2, replace=False))
+        idx = r * n - r * (r + 1) // 2 + (s - r - 1)
+        new = oracle.delta_update(F, D, p, r, s, tab)
+        assert new[idx] == -tab[idx]
+        p[r], p[s] = p[s], p[r]
+        assert (new == np_all_swap_deltas(F, D, p)).all()
+        tab = new
+
+
+def test_philox_matches_numpy():
+    """Philox4x64-10 against numpy's implementation of the same generator.  numpy advances
+    its 256-bit counter before each block, so block c comes from counter c - 1."""
+    for key in [0, 5, 2**63 + 12345, 2**64 - 1]:
+        for it, start in [(1, 0), (2, 7), (20000, 4095), (2**40 + 3, 2**33)]:
+            ours = oracle.philox([it, start, 0, 0], [key, 0])
+            ref = np.random.Philox(key=key, counter=it + (start << 64) - 1).random_raw(4)
+            assert (ours == ref).all()
+
+
+def test_tenure_range_and_mapping():
+    """t = lo + ((x >> 32) * span) >> 32 on numpy's Philox word, every value in [lo, hi],
+    every value reached, roughly uniform."""
+    seed, lo, hi = 99, 57, 70
+    counts = np.zeros(hi - lo + 1, dtype=np.int64)
+    for it in range(1, 3001):
+        x = int(np.random.Philox(key=seed, counter=it + (3 << 64) - 1).random_raw(1)[0])
+        expect = lo + (((x >> 32) * (hi - lo + 1)) >> 32)
+        t = oracle.tenure(seed, it, 3, lo, hi)
+        assert t == expect and lo <= t <= hi
+        counts[t - lo] += 1
+    assert counts.min() > 0.5 * counts.mean()
+
+
+def test_constant_cost_trajectories_by_hand():
+    g = json.load(open(os.path.join(GOLD, "tabu_constant_cost.json")))
+    for case in g["cases"]:
+        n = case["n"]
+        F = (np.ones((n, n), dtype=np.int32) - np.eye(n, dtype=np.int32))
+        D = W.grid_manhattan(n)
+        p0 = np.arange(n, dtype=np.int32)[::-1].copy()
+        z = np_cost(F, D, p0)
+        for mode in (0, 1):
+            bp, bc, done, tr = oracle.tabu(F, D, p0, case["iters"], case["lo"], case["hi"], 17, 0,
+                                           mode=mode, trace_cap=64)
+            assert done == case["iters_done"]
+            assert [list(map(int, row[:2])) for row in tr] == case["moves"]
+            assert (tr[:, 2] == 0).all() and (tr[:, 3] == z).all()
+            assert bc == z and list(bp) == list(p0)
+
+
+def py_tabu(F, D, p0, iters, lo, hi, seed, start):
+    """Independent numpy re-simulation of the tabu rules on tiny inputs: every neighbourhood
+    by full recomputation of Eq. (1), tenure from numpy's Philox."""
+    n = len(p0)
+    p = np.array(p0).copy()
+    cur = np_cost(F, D, p)
+    best, bestp = cur, p.copy()
+    until = {}
+    moves = []
+    for it in range(1, iters + 1):
+        deltas = np_all_swap_deltas(F, D, p)
+        pick = None
+        k = 0
+        for r in range(n):
+            for s in range(r + 1, n):
+                d = int(deltas[k])
+                if until.get(k, 0) <= it or cur + d < best:
+                    if pick is None or d < pick[0]:
+                        pick = (d, k, r, s)
+                k += 1
+        if pick is None:
+            break
+        d, k, r, s = pick
+        p[r], p[s] = p[s], p[r]
+        cur += d
+        if cur < best:
+            best, bestp = cur, p.copy()
+        x = int(np.random.Philox(key=seed, counter=it + (start << 64) - 1).random_raw(1)[0])
+        until[k] = it + lo + (((x >> 32) * (hi - lo + 1)) >> 32)
+        moves.append((r, s, d, cur))
+    return bestp, best, len(moves), moves
+
+
+@pytest.mark.parametrize("seed,n,lo,hi,iters", [(0, 5, 1, 3, 40), (1, 6, 2, 4, 60), (2, 7, 3, 6, 60),
+                                               (3, 8, 5, 9, 50), (4, 4, 6, 6, 12)])
+def test_tabu_matches_numpy_resimulation(seed, n, lo, hi, iters):
+    rng = np.random.default_rng(seed)
+    F, D = W.random_instance(rng, n, 0, 20, diag=(seed % 2 == 1))
+    p0 = rng.permutation(n).astype(np.int32)
+    ebp, ebc, edone, emoves = py_tabu(F, D, p0, iters, lo, hi, 1000 + seed, seed)
+    for mode in (0, 1):
+        bp, bc, done, tr = oracle.tabu(F, D, p0, iters, lo, hi, 1000 + seed, seed, mode=mode,
+                                       trace_cap=iters)
+        assert (bc, done) == (ebc, edone)
+        assert list(bp) == list(ebp)
+        assert [tuple(map(int, row)) for row in tr] == emoves
+
+
+@pytest.mark.parametrize("seed,n", [(0, 6), (1, 7), (2, 8), (3, 9)])
+def test_two_opt_local_optimum_and_brute_force(seed, n):
+    rng = np.random.default_rng(seed)
+    F, D = W.random_instance(rng, n, 0, 30)
+    opt = np_brute_force_optimum(F, D)
+    for _ in range(3):
+        p0 = rng.permutation(n)
+        for mode in (0, 1):
+            q, c, steps, tr = oracle.two_opt(F, D, p0, mode=mode, trace_cap=1000)
+            assert c == np_cost(F, D, q)
+            assert (np_all_swap_deltas(F, D, q) >= 0).all()
+            assert c >= opt
+            assert (tr[:, 2] < 0).all()
+            assert (np.diff(np.concatenate([[np_cost(F, D, p0)], tr[:, 3]])) < 0).all()
+
+
+def test_two_opt_modes_agree_and_cap():
+    rng = np.random.default_rng(11)
+    F, D = W.random_instance(rng, 30, 0, 99)
+    p0 = rng.permutation(30)
+    a = oracle.two_opt(F, D, p0, mode=0, trace_cap=500)
+    b = oracle.two_opt(F, D, p0, mode=1, trace_cap=500)
+    assert (a[0] == b[0]).all() and a[1:3] == b[1:3] and (a[3] == b[3]).all()
+    c = oracle.two_opt(F, D, p0, max_iters=3, mode=1, trace_cap=10)
+    assert c[2] == min(3, b[2]) and (c[3] == b[3][:c[2]]).all()
+
+
+def test_tabu_invariants_and_brute_force_small():
+    """best == cost(best_perm), best is the running minimum of the trajectory, and for n <= 8
+    the search is expected to reach the brute-force optimum (a warning if it does not)."""
+    import warnings
+    rng = np.random.default_rng(5)
+    for n in (6, 7, 8):
+        F, D = W.random_instance(rng, n, 0, 50)
+        opt = np_brute_force_optimum(F, D)
+        p0 = rng.permutation(n)
+        lo, hi = max(1, n // 3), max(1, n // 2)
+        bp, bc, done, tr = oracle.tabu(F, D, p0, 300, lo, hi, 7, 0, mode=1, trace_cap=300)
+        assert bc == np_cost(F, D, bp)
+        assert bc == min(np_cost(F, D, p0), int(tr[:, 3].min()))
+        assert bc >= opt
+        if bc != opt:
+            warnings.warn("tabu did not reach the optimum for n=%d (%d vs %d)" % (n, bc, opt))
+
+
+def test_tabu_premature_stop_forced():
+    rng = np.random.default_rng(9)
+    F, D = W.random_instance(rng, 3, 0, 9)
+    for mode in (0, 1):
+        _, _, done, _ = oracle.tabu(F, D, [2, 0, 1], 10, 50, 50, 1, 0, mode=mode)
+        assert done <= 3
