@@ -1,0 +1,183 @@
+/*
+ * qap.h -- C ABI of libqap, the MI355X (gfx950) hot path of the pairwise-exchange
+ * heuristics for the Quadratic Assignment Problem of Novoa & Qasem,
+ * "GPU-accelerated Parallel Solutions to the Quadratic Assignment Problem"
+ * (arXiv 2307.11248).
+ *
+ * Notation (Sec. 2.1 of the paper, restated 0-based):
+ *   n        problem size: n units are assigned to n locations.
+ *   F        flows between units,     row-major n x n int32: F[k*n + l].
+ *   D        distances between locations, row-major n x n int32: D[i*n + j].
+ *   perm     perm[i] is the unit stored in location i (a permutation of 0..n-1).
+ *   cost     Eq. (1): z = sum_i sum_j F[perm[i]][perm[j]] * D[i][j], as int64.
+ *   move     (r, s), r < s: exchange the contents of locations r and s (Sec. 4.1).
+ *   packed   moves are numbered in packed upper-triangle order
+ *              idx(r, s) = r*n - r*(r+1)/2 + (s - r - 1),
+ *            which is lexicographic (r, s) order; ties between equal deltas always go
+ *            to the lowest idx.
+ *
+ * Buffers: every pointer is owned by the caller.  "host" pointers are ordinary CPU
+ * memory; "device" pointers are HIP device memory of the GPU the handle was created
+ * on.  Host entry points block until their results are in host memory.  *_async entry
+ * points enqueue work on the HIP stream `stream` (NULL = the default stream), return
+ * without waiting, and neither read nor write their buffers from the host.
+ *
+ * Exactness: all flows and distances must lie in [0, 255].  Then every delta fits in
+ * int32 with a wide margin (|delta| <= (2n-2) * 255 * 255 < 2^26 for n <= 256) and every
+ * cost in int64, and all results are exact integers, identical to a plain CPU
+ * evaluation of the paper's formulas.
+ *
+ * Errors are returned as negative codes (qap_strerror maps them to text).  A call that
+ * fails leaves its output buffers in an unspecified state.  A handle may be used from
+ * one host thread at a time.
+ */
+#ifndef QAP_H_
+#define QAP_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QAP_NMAX 256
+
+enum {
+    QAP_OK = 0,
+    QAP_E_INVALID = -1,   /* null pointer, n < 2, n > QAP_NMAX, k < 0, iters < 0, lo < 0, lo > hi */
+    QAP_E_NOT_PERM = -2,  /* a row of perms is not a permutation of 0..n-1 */
+    QAP_E_RANGE = -3,     /* a flow or distance lies outside [0, 255] */
+    QAP_E_DEVICE = -4,    /* a HIP call failed */
+    QAP_E_NOMEM = -5,     /* host or device allocation failed */
+    QAP_E_UNSUPPORTED = -6 /* valid request this build cannot serve (see the entry point) */
+};
+
+typedef struct qap_ctx *qap_handle;
+
+/* Text for an error code; never NULL. */
+const char *qap_strerror(int code);
+
+/*
+ * Create a handle for one instance (F, D) of size n (Sec. 2.1) on the current HIP
+ * device.  F and D are host pointers, read once and copied; the handle owns its device
+ * copies until qap_destroy.  Returns QAP_E_RANGE if an entry lies outside [0, 255].
+ * Cost and neighbourhood tables serve every n <= QAP_NMAX; the 2opt and tabu entry
+ * points return QAP_E_UNSUPPORTED when no tile shape of the search kernels fits n in
+ * one workgroup (the neighbourhood is held in registers, F, F^T, D, D^T in LDS).
+ */
+int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out);
+
+/* Release a handle and its device memory.  NULL is accepted. */
+int qap_destroy(qap_handle h);
+
+/* n of a handle, or QAP_E_INVALID. */
+int qap_size(qap_handle h);
+
+/*
+ * Eq. (1): costs[j] = z(perms[j]) for j < k.  perms: host int32[k][n]; costs: host
+ * int64[k].  Every row is checked to be a permutation (QAP_E_NOT_PERM otherwise).
+ */
+int qap_cost(qap_handle h, const int32_t *perms, int32_t k, int64_t *costs);
+
+/* Device/stream twin of qap_cost; rows are not checked, and a row that is not a
+ * permutation yields costs[j] = INT64_MIN. */
+int qap_cost_async(qap_handle h, const int32_t *d_perms, int32_t k, int64_t *d_costs,
+                   void *stream);
+
+/*
+ * The whole pairwise-exchange neighbourhood (Sec. 4.1) of each start: for j < k and
+ * every move (r, s), table[j * m + idx(r, s)] = z(perms[j] with r, s exchanged) -
+ * z(perms[j]), m = n(n-1)/2, i.e. Eq. (2) with the diagonal term that the printed
+ * equation omits (zero when D has a zero diagonal).  perms: host int32[k][n];
+ * table: host int32[k][m].
+ */
+int qap_delta_table(qap_handle h, const int32_t *perms, int32_t k, int32_t *table);
+
+/* Device/stream twin of qap_delta_table (rows are not checked). */
+int qap_delta_table_async(qap_handle h, const int32_t *d_perms, int32_t k, int32_t *d_table,
+                          void *stream);
+
+/*
+ * 2opt (Secs. 4.1-4.2), read as best improvement: from each start, repeatedly take the
+ * move with the lowest delta (lowest idx among equal deltas) while that delta is
+ * negative.  The search stops at a local optimum, or after max_iters moves when
+ * max_iters > 0 (2^20 moves when max_iters <= 0).
+ *   perms     host int32[k][n]: the starts on entry, the final permutations on return.
+ *   costs_out host int64[k]: their costs.
+ *   steps_out host int32[k] or NULL: moves made by each start.
+ */
+int qap_2opt(qap_handle h, int32_t *perms, int32_t k, int32_t max_iters, int64_t *costs_out,
+             int32_t *steps_out);
+
+/* Device/stream twin of qap_2opt.  d_steps may be NULL.  Rows are checked on the device:
+ * a row that is not a permutation is left as it is, with d_steps[j] = QAP_E_NOT_PERM and
+ * d_costs[j] = INT64_MIN. */
+int qap_2opt_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t max_iters,
+                   int64_t *d_costs, int32_t *d_steps, void *stream);
+
+/*
+ * Elementary tabu search with recency memory (Secs. 4.3-4.4), one independent search per
+ * start, iterations it = 1 .. iters:
+ *   - a move is tabu at iteration it iff its Tabuarr entry is > it (entries start at 0);
+ *   - aspiration: a tabu move is allowed if it reaches a cost strictly below the best
+ *     cost found so far;
+ *   - the allowed move with the lowest delta is made, even if it worsens the cost (ties:
+ *     lowest idx); the best permutation is replaced only on a strictly lower cost;
+ *   - after the move (r, s) of iteration it, Tabuarr(r, s) = it + t, with the tenure t
+ *     drawn from [lo, hi] as lo + ((x >> 32) * (hi - lo + 1) >> 32), where x is the first
+ *     word of Philox4x64-10 (Salmon et al., SC'11) with key (seed, 0) and counter
+ *     (it, start_id, 0, 0); start_id = j for the host entry point;
+ *   - if no move is allowed the search stops early (Sec. 4.4).
+ *   perms          host int32[k][n]: the starts on entry, the best permutations on return.
+ *   best_costs_out host int64[k].
+ *   iters_done_out host int32[k] or NULL: moves made (< iters only after an early stop).
+ */
+int qap_tabu(qap_handle h, int32_t *perms, int32_t k, int32_t iters, int32_t lo, int32_t hi,
+             uint64_t seed, int64_t *best_costs_out, int32_t *iters_done_out);
+
+/* Device/stream twin of qap_tabu; start j uses start_id = start_base + j.  d_done may be
+ * NULL.  Rows are checked on the device as in qap_2opt_async. */
+int qap_tabu_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo,
+                   int32_t hi, uint64_t seed, int64_t start_base, int64_t *d_best,
+                   int32_t *d_done, void *stream);
+
+/*
+ * The plain delivery of qap_tabu_async: the same arithmetic and results, but one kernel
+ * launch per start, issued back to back on `stream` (the launch shape the paper uses
+ * for its per-search kernels, Sec. 4.4, one search at a time).  Kept as the baseline
+ * the batched delivery is measured against.
+ */
+int qap_tabu_plain_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo,
+                         int32_t hi, uint64_t seed, int64_t start_base, int64_t *d_best,
+                         int32_t *d_done, void *stream);
+
+/*
+ * The search kernels alone: as qap_2opt_async / qap_tabu_async, but the neighbourhood
+ * of each start is taken from d_table (device int32[k][m], m = n(n-1)/2, packed order)
+ * instead of being computed first; it must be the neighbourhood of d_perms, e.g. from
+ * qap_delta_table_async on the same stream.  d_table is only read.
+ */
+int qap_2opt_with_table_async(qap_handle h, int32_t *d_perms, const int32_t *d_table, int32_t k,
+                              int32_t max_iters, int64_t *d_costs, int32_t *d_steps, void *stream);
+int qap_tabu_with_table_async(qap_handle h, int32_t *d_perms, const int32_t *d_table, int32_t k,
+                              int32_t iters, int32_t lo, int32_t hi, uint64_t seed,
+                              int64_t start_base, int64_t *d_best, int32_t *d_done, void *stream);
+
+/*
+ * Tile shape of the search kernels (the thread-configuration search of Sec. 5.2,
+ * re-done for gfx950): each lane of a search's workgroup holds a block of `rows` x 4
+ * neighbourhood entries in registers, rows in {2, 4, 8, 16}; 0 restores the library's
+ * own choice for this n.  algo: 0 = tabu, 1 = 2opt.  Returns QAP_E_UNSUPPORTED if the
+ * shape needs more than 1024 lanes for this n.
+ */
+int qap_set_tile_rows(qap_handle h, int32_t algo, int32_t rows);
+
+/* Tile rows currently used for algo (0 = tabu, 1 = 2opt), and the lanes per search in
+ * *lanes_out (may be NULL). */
+int qap_get_tile_rows(qap_handle h, int32_t algo, int32_t *lanes_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QAP_H_ */

@@ -1,0 +1,424 @@
+// qap_api.hip -- host side of the C ABI declared in include/qap.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/qap.h"
+#include "qap_internal.h"
+
+using namespace qapk;
+
+namespace {
+
+const int kRowsChoices[4] = {2, 4, 8, 16};
+
+struct TileSet {
+    int32_t *d_tiles = nullptr;
+    int ntiles = 0, ninterior = 0, lanes = 0;
+};
+
+// Tiles of `rows` x 4 that hold at least one move (u < v), interior tiles first, each
+// group in row-major (g, b) order; a tile is interior when no row or column passes n.
+std::vector<int32_t> enumerate_tiles(int n, int rows, int *ninterior) {
+    std::vector<int32_t> inner, outer;
+    const int ng = (n + rows - 1) / rows, nb = (n + TILE_COLS - 1) / TILE_COLS;
+    for (int g = 0; g < ng; ++g)
+        for (int b = 0; b < nb; ++b) {
+            const int ulo = g * rows, vhi = std::min(TILE_COLS * b + TILE_COLS, n) - 1;
+            if (ulo >= vhi) continue;
+            const bool interior = g * rows + rows <= n && TILE_COLS * b + TILE_COLS <= n;
+            (interior ? inner : outer).push_back(g | (b << 16));
+        }
+    *ninterior = (int)inner.size();
+    inner.insert(inner.end(), outer.begin(), outer.end());
+    return inner;
+}
+
+}  // namespace
+
+struct qap_ctx {
+    int n = 0, m = 0, sym = 0, device = 0;
+    size_t max_smem = 0;
+    uint8_t *d_mats = nullptr;       // [F | F^T | D | D^T] u8, n rows of row_stride(n) bytes
+    TileSet tiles[4];                // one per entry of kRowsChoices
+    int rows_choice[2] = {0, 0};     // 0 tabu, 1 2opt: index into kRowsChoices
+    int rows_default[2] = {0, 0};
+};
+
+namespace {
+
+int rows_index(int rows) {
+    for (int i = 0; i < 4; ++i)
+        if (kRowsChoices[i] == rows) return i;
+    return -1;
+}
+
+bool shape_fits(const qap_ctx *h, int ri) {
+    const TileSet &ts = h->tiles[ri];
+    if (ts.lanes < 64 || ts.lanes > search_max_lanes(kRowsChoices[ri])) return false;
+    return search_smem_bytes(h->n, kRowsChoices[ri], ts.lanes, h->sym) <= h->max_smem;
+}
+
+// Default tile shape: the one whose lane count is closest to 256 (four waves per
+// search), larger tiles preferred on ties.
+int default_rows(const qap_ctx *h) {
+    int best = -1, bestd = 1 << 30;
+    for (int i = 3; i >= 0; --i) {
+        if (!shape_fits(h, i)) continue;
+        const int d = std::abs(h->tiles[i].lanes - 256);
+        if (d < bestd) { best = i; bestd = d; }
+    }
+    return best;
+}
+
+// Map a HIP status to a QAP code; with QAP_VERBOSE set in the environment, a failure
+// is also reported on stderr with HIP's own text and the call site.
+int dev_err_at(hipError_t e, const char *where) {
+    if (e == hipSuccess) return QAP_OK;
+    static const bool verbose = std::getenv("QAP_VERBOSE") != nullptr;
+    if (verbose) std::fprintf(stderr, "libqap: %s: %s (%d)\n", where, hipGetErrorString(e), (int)e);
+    return e == hipErrorOutOfMemory ? QAP_E_NOMEM : QAP_E_DEVICE;
+}
+#define dev_err(e) dev_err_at((e), __func__)
+
+bool check_perms(const int32_t *perms, int k, int n) {
+    std::vector<int> seen(n);
+    for (int j = 0; j < k; ++j) {
+        std::fill(seen.begin(), seen.end(), 0);
+        const int32_t *p = perms + (size_t)j * n;
+        for (int i = 0; i < n; ++i) {
+            if (p[i] < 0 || p[i] >= n || seen[p[i]]) return false;
+            seen[p[i]] = 1;
+        }
+    }
+    return true;
+}
+
+// RAII device buffer for the blocking entry points.
+struct DevBuf {
+    void *p = nullptr;
+    hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 16); }
+    ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+SearchArgs base_args(qap_ctx *h, int algo) {
+    const TileSet &ts = h->tiles[h->rows_choice[algo]];
+    SearchArgs a{};
+    a.mats = h->d_mats;
+    a.n = h->n;
+    a.m = h->m;
+    a.tiles = ts.d_tiles;
+    a.ntiles = ts.ntiles;
+    a.ninterior = ts.ninterior;
+    a.sym = h->sym;
+    return a;
+}
+
+// Neighbourhood tables for the starts, in stream-ordered scratch memory.
+int make_tables(qap_ctx *h, const int32_t *d_perms, int k, int32_t **d_table, hipStream_t st) {
+    hipError_t e = report(hipMallocAsync((void **)d_table, (size_t)k * h->m * sizeof(int32_t) + 16, st),
+                          "hipMallocAsync");
+    if (e != hipSuccess) return dev_err(e);
+    TableArgs ta{h->d_mats, d_perms, nullptr, *d_table, h->n, h->m, k};
+    e = launch_table(ta, st);
+    if (e != hipSuccess) { (void)hipFreeAsync(*d_table, st); return dev_err(e); }
+    return QAP_OK;
+}
+
+hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t *d_table, int k, int iters,
+                           int lo, int hi, uint64_t seed, int64_t start_base, int64_t *d_cost, int32_t *d_steps,
+                           hipStream_t st, bool plain) {
+    SearchArgs a = base_args(h, algo);
+    a.table = d_table;
+    a.perms_in = d_perms;
+    a.perm_out = d_perms;
+    a.cost_out = d_cost;
+    a.steps_out = d_steps;
+    a.iters = iters;
+    a.lo = lo;
+    a.hi = hi;
+    a.seed = seed;
+    a.start_base = start_base;
+    const int rows = kRowsChoices[h->rows_choice[algo]];
+    const int lanes = h->tiles[h->rows_choice[algo]].lanes;
+    hipError_t e = hipSuccess;
+    if (plain) {
+        for (int j = 0; j < k && e == hipSuccess; ++j) {
+            a.job0 = j;
+            e = launch_search(rows, algo == 0, a, 1, lanes, st);
+        }
+    } else {
+        a.job0 = 0;
+        e = launch_search(rows, algo == 0, a, k, lanes, st);
+    }
+    return e;
+}
+
+int run_search(qap_ctx *h, int algo, int32_t *d_perms, int k, int iters, int lo, int hi, uint64_t seed,
+               int64_t start_base, int64_t *d_cost, int32_t *d_steps, hipStream_t st, bool plain) {
+    if (h->rows_choice[algo] < 0) return QAP_E_UNSUPPORTED;
+    if (k == 0) return QAP_OK;
+    int32_t *d_table = nullptr;
+    int rc = make_tables(h, d_perms, k, &d_table, st);
+    if (rc != QAP_OK) return rc;
+    hipError_t e = launch_searches(h, algo, d_perms, d_table, k, iters, lo, hi, seed, start_base, d_cost,
+                                   d_steps, st, plain);
+    hipError_t e2 = hipFreeAsync(d_table, st);
+    if (e == hipSuccess) e = e2;
+    return dev_err(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *qap_strerror(int code) {
+    switch (code) {
+        case QAP_OK: return "ok";
+        case QAP_E_INVALID: return "invalid argument";
+        case QAP_E_NOT_PERM: return "a row is not a permutation of 0..n-1";
+        case QAP_E_RANGE: return "a flow or distance lies outside [0, 255]";
+        case QAP_E_DEVICE: return "HIP device error";
+        case QAP_E_NOMEM: return "out of memory";
+        case QAP_E_UNSUPPORTED: return "unsupported by this build";
+        default: return "unknown error";
+    }
+}
+
+int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out) {
+    if (!F || !D || !out || n < 2 || n > QAP_NMAX) return QAP_E_INVALID;
+    *out = nullptr;
+    const size_t nn = (size_t)n * n;
+    bool symF = true, symD = true;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const int32_t f = F[(size_t)i * n + j], d = D[(size_t)i * n + j];
+            if (f < 0 || f > 255 || d < 0 || d > 255) return QAP_E_RANGE;
+            if (f != F[(size_t)j * n + i]) symF = false;
+            if (d != D[(size_t)j * n + i]) symD = false;
+        }
+    qap_ctx *h = new (std::nothrow) qap_ctx;
+    if (!h) return QAP_E_NOMEM;
+    h->n = n;
+    h->m = n * (n - 1) / 2;
+    h->sym = (symF && symD) ? 1 : 0;
+    if (hipGetDevice(&h->device) != hipSuccess) { delete h; return QAP_E_DEVICE; }
+    int smem = 0;
+    if (hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) != hipSuccess) {
+        delete h;
+        return QAP_E_DEVICE;
+    }
+    h->max_smem = (size_t)smem;
+    const int rs = row_stride(n);
+    std::vector<uint8_t> pack((size_t)4 * n * rs, 0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            pack[(size_t)0 * n * rs + (size_t)i * rs + j] = (uint8_t)F[(size_t)i * n + j];
+            pack[(size_t)1 * n * rs + (size_t)i * rs + j] = (uint8_t)F[(size_t)j * n + i];
+            pack[(size_t)2 * n * rs + (size_t)i * rs + j] = (uint8_t)D[(size_t)i * n + j];
+            pack[(size_t)3 * n * rs + (size_t)i * rs + j] = (uint8_t)D[(size_t)j * n + i];
+        }
+    (void)nn;
+    hipError_t e = hipMalloc((void **)&h->d_mats, pack.size());
+    if (e == hipSuccess) e = hipMemcpy(h->d_mats, pack.data(), pack.size(), hipMemcpyHostToDevice);
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+        int ninner = 0;
+        std::vector<int32_t> tl = enumerate_tiles(n, kRowsChoices[i], &ninner);
+        TileSet &ts = h->tiles[i];
+        ts.ntiles = (int)tl.size();
+        ts.ninterior = ninner;
+        ts.lanes = std::max(64, (ts.ntiles + 63) / 64 * 64);
+        e = hipMalloc((void **)&ts.d_tiles, tl.size() * sizeof(int32_t) + 16);
+        if (e == hipSuccess)
+            e = hipMemcpy(ts.d_tiles, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        qap_destroy(h);
+        return dev_err(e);
+    }
+    const int d = default_rows(h);   // -1: no search kernel shape fits this n
+    h->rows_default[0] = h->rows_default[1] = d;
+    h->rows_choice[0] = h->rows_choice[1] = d;
+    *out = h;
+    return QAP_OK;
+}
+
+int qap_destroy(qap_handle h) {
+    if (!h) return QAP_OK;
+    if (h->d_mats) (void)hipFree(h->d_mats);
+    for (auto &ts : h->tiles)
+        if (ts.d_tiles) (void)hipFree(ts.d_tiles);
+    delete h;
+    return QAP_OK;
+}
+
+int qap_size(qap_handle h) { return h ? h->n : QAP_E_INVALID; }
+
+int qap_set_tile_rows(qap_handle h, int32_t algo, int32_t rows) {
+    if (!h || algo < 0 || algo > 1) return QAP_E_INVALID;
+    if (rows == 0) {
+        h->rows_choice[algo] = h->rows_default[algo];
+        return QAP_OK;
+    }
+    const int ri = rows_index(rows);
+    if (ri < 0) return QAP_E_INVALID;
+    if (!shape_fits(h, ri)) return QAP_E_UNSUPPORTED;
+    h->rows_choice[algo] = ri;
+    return QAP_OK;
+}
+
+int qap_get_tile_rows(qap_handle h, int32_t algo, int32_t *lanes_out) {
+    if (!h || algo < 0 || algo > 1) return QAP_E_INVALID;
+    const int ri = h->rows_choice[algo];
+    if (ri < 0) return QAP_E_UNSUPPORTED;
+    if (lanes_out) *lanes_out = h->tiles[ri].lanes;
+    return kRowsChoices[ri];
+}
+
+int qap_cost_async(qap_handle h, const int32_t *d_perms, int32_t k, int64_t *d_costs, void *stream) {
+    if (!h || k < 0 || (k > 0 && (!d_perms || !d_costs))) return QAP_E_INVALID;
+    TableArgs a{h->d_mats, d_perms, d_costs, nullptr, h->n, h->m, k};
+    return dev_err(launch_cost(a, (hipStream_t)stream));
+}
+
+int qap_delta_table_async(qap_handle h, const int32_t *d_perms, int32_t k, int32_t *d_table, void *stream) {
+    if (!h || k < 0 || (k > 0 && (!d_perms || !d_table))) return QAP_E_INVALID;
+    TableArgs a{h->d_mats, d_perms, nullptr, d_table, h->n, h->m, k};
+    return dev_err(launch_table(a, (hipStream_t)stream));
+}
+
+int qap_2opt_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t max_iters, int64_t *d_costs,
+                   int32_t *d_steps, void *stream) {
+    if (!h || k < 0 || (k > 0 && (!d_perms || !d_costs))) return QAP_E_INVALID;
+    return run_search(h, 1, d_perms, k, max_iters, 0, 0, 0, 0, d_costs, d_steps, (hipStream_t)stream, false);
+}
+
+static int tabu_args_ok(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo, int32_t hi,
+                        int64_t *d_best) {
+    return h && k >= 0 && iters >= 0 && lo >= 0 && lo <= hi && (k == 0 || (d_perms && d_best));
+}
+
+int qap_tabu_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo, int32_t hi,
+                   uint64_t seed, int64_t start_base, int64_t *d_best, int32_t *d_done, void *stream) {
+    if (!tabu_args_ok(h, d_perms, k, iters, lo, hi, d_best)) return QAP_E_INVALID;
+    return run_search(h, 0, d_perms, k, iters, lo, hi, seed, start_base, d_best, d_done, (hipStream_t)stream,
+                      false);
+}
+
+int qap_tabu_plain_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo, int32_t hi,
+                         uint64_t seed, int64_t start_base, int64_t *d_best, int32_t *d_done, void *stream) {
+    if (!tabu_args_ok(h, d_perms, k, iters, lo, hi, d_best)) return QAP_E_INVALID;
+    return run_search(h, 0, d_perms, k, iters, lo, hi, seed, start_base, d_best, d_done, (hipStream_t)stream,
+                      true);
+}
+
+int qap_2opt_with_table_async(qap_handle h, int32_t *d_perms, const int32_t *d_table, int32_t k,
+                              int32_t max_iters, int64_t *d_costs, int32_t *d_steps, void *stream) {
+    if (!h || k < 0 || (k > 0 && (!d_perms || !d_costs || !d_table))) return QAP_E_INVALID;
+    if (h->rows_choice[1] < 0) return QAP_E_UNSUPPORTED;
+    if (k == 0) return QAP_OK;
+    return dev_err(launch_searches(h, 1, d_perms, d_table, k, max_iters, 0, 0, 0, 0, d_costs, d_steps,
+                                   (hipStream_t)stream, false));
+}
+
+int qap_tabu_with_table_async(qap_handle h, int32_t *d_perms, const int32_t *d_table, int32_t k,
+                              int32_t iters, int32_t lo, int32_t hi, uint64_t seed, int64_t start_base,
+                              int64_t *d_best, int32_t *d_done, void *stream) {
+    if (!tabu_args_ok(h, d_perms, k, iters, lo, hi, d_best) || (k > 0 && !d_table)) return QAP_E_INVALID;
+    if (h->rows_choice[0] < 0) return QAP_E_UNSUPPORTED;
+    if (k == 0) return QAP_OK;
+    return dev_err(launch_searches(h, 0, d_perms, d_table, k, iters, lo, hi, seed, start_base, d_best, d_done,
+                                   (hipStream_t)stream, false));
+}
+
+// ---- blocking host entry points: validate, copy in, run on a private stream, copy out
+
+namespace {
+
+struct HostCall {
+    hipStream_t st = nullptr;
+    ~HostCall() { if (st) (void)hipStreamDestroy(st); }
+    hipError_t init() { return hipStreamCreateWithFlags(&st, hipStreamNonBlocking); }
+};
+
+}  // namespace
+
+int qap_cost(qap_handle h, const int32_t *perms, int32_t k, int64_t *costs) {
+    if (!h || k < 0 || (k > 0 && (!perms || !costs))) return QAP_E_INVALID;
+    if (!check_perms(perms, k, h->n)) return QAP_E_NOT_PERM;
+    if (k == 0) return QAP_OK;
+    HostCall c;
+    DevBuf dp, dc;
+    hipError_t e = c.init();
+    if (e == hipSuccess) e = dp.alloc((size_t)k * h->n * 4);
+    if (e == hipSuccess) e = dc.alloc((size_t)k * 8);
+    if (e == hipSuccess) e = hipMemcpyAsync(dp.p, perms, (size_t)k * h->n * 4, hipMemcpyHostToDevice, c.st);
+    if (e != hipSuccess) return dev_err(e);
+    int rc = qap_cost_async(h, (const int32_t *)dp.p, k, (int64_t *)dc.p, c.st);
+    if (rc != QAP_OK) return rc;
+    e = hipMemcpyAsync(costs, dc.p, (size_t)k * 8, hipMemcpyDeviceToHost, c.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.st);
+    return dev_err(e);
+}
+
+int qap_delta_table(qap_handle h, const int32_t *perms, int32_t k, int32_t *table) {
+    if (!h || k < 0 || (k > 0 && (!perms || !table))) return QAP_E_INVALID;
+    if (!check_perms(perms, k, h->n)) return QAP_E_NOT_PERM;
+    if (k == 0) return QAP_OK;
+    HostCall c;
+    DevBuf dp, dt;
+    const size_t tb = (size_t)k * h->m * 4;
+    hipError_t e = c.init();
+    if (e == hipSuccess) e = dp.alloc((size_t)k * h->n * 4);
+    if (e == hipSuccess) e = dt.alloc(tb);
+    if (e == hipSuccess) e = hipMemcpyAsync(dp.p, perms, (size_t)k * h->n * 4, hipMemcpyHostToDevice, c.st);
+    if (e != hipSuccess) return dev_err(e);
+    int rc = qap_delta_table_async(h, (const int32_t *)dp.p, k, (int32_t *)dt.p, c.st);
+    if (rc != QAP_OK) return rc;
+    e = hipMemcpyAsync(table, dt.p, tb, hipMemcpyDeviceToHost, c.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.st);
+    return dev_err(e);
+}
+
+static int host_search(qap_handle h, int algo, int32_t *perms, int32_t k, int32_t iters, int32_t lo,
+                       int32_t hi, uint64_t seed, int64_t *costs, int32_t *steps) {
+    if (!check_perms(perms, k, h->n)) return QAP_E_NOT_PERM;
+    if (k == 0) return QAP_OK;
+    HostCall c;
+    DevBuf dp, dc, ds;
+    const size_t pb = (size_t)k * h->n * 4;
+    hipError_t e = c.init();
+    if (e == hipSuccess) e = dp.alloc(pb);
+    if (e == hipSuccess) e = dc.alloc((size_t)k * 8);
+    if (e == hipSuccess) e = ds.alloc((size_t)k * 4);
+    if (e == hipSuccess) e = hipMemcpyAsync(dp.p, perms, pb, hipMemcpyHostToDevice, c.st);
+    if (e != hipSuccess) return dev_err(e);
+    int rc = algo == 0
+        ? qap_tabu_async(h, (int32_t *)dp.p, k, iters, lo, hi, seed, 0, (int64_t *)dc.p, (int32_t *)ds.p, c.st)
+        : qap_2opt_async(h, (int32_t *)dp.p, k, iters, (int64_t *)dc.p, (int32_t *)ds.p, c.st);
+    if (rc != QAP_OK) return rc;
+    e = hipMemcpyAsync(perms, dp.p, pb, hipMemcpyDeviceToHost, c.st);
+    if (e == hipSuccess) e = hipMemcpyAsync(costs, dc.p, (size_t)k * 8, hipMemcpyDeviceToHost, c.st);
+    if (e == hipSuccess && steps) e = hipMemcpyAsync(steps, ds.p, (size_t)k * 4, hipMemcpyDeviceToHost, c.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.st);
+    return dev_err(e);
+}
+
+int qap_2opt(qap_handle h, int32_t *perms, int32_t k, int32_t max_iters, int64_t *costs_out, int32_t *steps_out) {
+    if (!h || k < 0 || (k > 0 && (!perms || !costs_out))) return QAP_E_INVALID;
+    return host_search(h, 1, perms, k, max_iters, 0, 0, 0, costs_out, steps_out);
+}
+
+int qap_tabu(qap_handle h, int32_t *perms, int32_t k, int32_t iters, int32_t lo, int32_t hi, uint64_t seed,
+             int64_t *best_costs_out, int32_t *iters_done_out) {
+    if (!h || k < 0 || iters < 0 || lo < 0 || lo > hi || (k > 0 && (!perms || !best_costs_out)))
+        return QAP_E_INVALID;
+    return host_search(h, 0, perms, k, iters, lo, hi, seed, best_costs_out, iters_done_out);
+}
+
+}  // extern "C"

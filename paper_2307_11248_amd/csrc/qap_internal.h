@@ -1,0 +1,116 @@
+// qap_internal.h -- device helpers, shared-memory plan and launch declarations of libqap.
+// Internal to the library: the public ABI is include/qap.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <cstdio>
+#include <cstdlib>
+
+namespace qapk {
+
+// Delta held by slots that are not moves (the diagonal u == v of a tile and padding
+// beyond n).  Larger than any real delta (|delta| < 2^26 for entries in [0, 255] and
+// n <= 256), so such a slot is never the best candidate, and the incremental update
+// adds exactly 0 to a diagonal slot.
+constexpr int BIG = 0x3FFFFFFF;
+constexpr int KEY_NONE = 0x7FFFFFFF;
+constexpr int TILE_COLS = 4;   // columns of the register tile held by one lane
+// Bound on the moves of one 2opt search run to a local optimum (the cost strictly
+// decreases, so this only bounds a run on inconsistent data).
+constexpr int TWO_OPT_MAX_MOVES = 1 << 20;
+
+// Rows are padded to RS bytes (a multiple of 16) so every row starts 16-byte aligned.
+__host__ __device__ inline int row_stride(int n) { return (n + 15) & ~15; }
+
+// Number of indices (locations or units) addressable by a tile of `rows` x 4.
+__host__ __device__ inline int padded_n(int n, int rows) {
+    int a = ((n + rows - 1) / rows) * rows;
+    int b = ((n + TILE_COLS - 1) / TILE_COLS) * TILE_COLS;
+    int m = a > b ? a : b;
+    return (m + 3) & ~3;
+}
+
+__host__ __device__ inline long long pidx(int n, int r, int s) {
+    return (long long)r * n - (long long)r * (r + 1) / 2 + (s - r - 1);
+}
+
+// Byte offsets of the per-search shared-memory arrays.  The matrices are the u8 copies
+// of F, F^T, D, D^T (only F and D when both are symmetric).
+struct Smem {
+    int mats, x, acbe, rr, p, rd, cd, perm, pinv, bestp, ten, red, total;
+};
+
+__host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym) {
+    const int rs = row_stride(n);
+    Smem s;
+    int o = 0;
+    auto take = [&o](int bytes) { int at = o; o += (bytes + 15) & ~15; return at; };
+    s.mats = take((sym ? 2 : 4) * n * rs);
+    s.x = take(8 * rs);
+    s.acbe = take(np * 8);
+    s.rr = take(np * 8);
+    s.p = take(4 * np * 8);
+    s.rd = take(np * 4);
+    s.cd = take(np * 4);
+    s.perm = take(np * 4);
+    s.pinv = take(np * 4);
+    s.bestp = take(np * 4);
+    s.ten = take(lanes * 4);
+    s.red = take(16 * 8);
+    s.total = o;
+    return s;
+}
+
+// Arguments of the cost and neighbourhood-table kernels.
+struct TableArgs {
+    const uint8_t *mats;     // global [F | F^T | D | D^T], n rows of RS bytes each
+    const int32_t *perms;    // [k][n]
+    int64_t *costs;          // [k] or null
+    int32_t *table;          // [k][m] or null
+    int n, m, k;
+};
+
+// Arguments of the search kernels (2opt and tabu).
+struct SearchArgs {
+    const uint8_t *mats;     // global [F | F^T | D | D^T]
+    const int32_t *table;    // [k][m] neighbourhood of each start
+    const int32_t *perms_in; // [k][n]
+    int32_t *perm_out;       // [k][n]; may alias perms_in
+    int64_t *cost_out;       // [k]
+    int32_t *steps_out;      // [k] or null
+    const int32_t *tiles;    // [ntiles] lane -> tile, g | b << 16, interior tiles first
+    int n, m, ntiles, ninterior;
+    int iters;               // tabu: iterations; 2opt: move cap (<= 0: none)
+    int lo, hi;
+    unsigned long long seed;
+    long long start_base;
+    int sym;
+    int job0;                // search index of block 0
+};
+
+// With QAP_VERBOSE set in the environment, report a failed HIP call on stderr.
+inline hipError_t report(hipError_t e, const char *what) {
+    if (e != hipSuccess && std::getenv("QAP_VERBOSE"))
+        std::fprintf(stderr, "libqap: %s: %s (%d)\n", what, hipGetErrorString(e), (int)e);
+    return e;
+}
+
+// Largest dynamic LDS allocation a workgroup may request on the current device.
+inline size_t max_dyn_smem() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 64 * 1024;
+    return (size_t)v;
+}
+
+hipError_t launch_cost(const TableArgs &a, hipStream_t st);
+hipError_t launch_table(const TableArgs &a, hipStream_t st);
+// rows in {2, 4, 8, 16}; grid = number of searches in this launch; lanes = block size.
+hipError_t launch_search(int rows, bool tabu, const SearchArgs &a, int grid, int lanes,
+                         hipStream_t st);
+size_t search_smem_bytes(int n, int rows, int lanes, int sym);
+int search_max_lanes(int rows);
+
+}  // namespace qapk

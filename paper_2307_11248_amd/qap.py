@@ -1,0 +1,235 @@
+"""Python binding of libqap (the C ABI in include/qap.h): argument marshalling only.
+
+Every computation runs in the HIP library.  If ``libqap.so`` has not been built the
+first call raises ``RuntimeError``; there is no CPU fallback.
+
+Host functions take and return numpy arrays.  The ``*_async`` functions take torch
+tensors that live on the GPU and enqueue work on a torch stream (the current one by
+default); torch is used for device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libqap.so")
+
+QAP_OK = 0
+QAP_E_INVALID = -1
+QAP_E_NOT_PERM = -2
+QAP_E_RANGE = -3
+QAP_E_DEVICE = -4
+QAP_E_NOMEM = -5
+QAP_E_UNSUPPORTED = -6
+QAP_NMAX = 256
+
+EXPORTS = [
+    "qap_strerror", "qap_create", "qap_destroy", "qap_size", "qap_cost", "qap_cost_async",
+    "qap_delta_table", "qap_delta_table_async", "qap_2opt", "qap_2opt_async", "qap_tabu",
+    "qap_tabu_async", "qap_tabu_plain_async", "qap_2opt_with_table_async", "qap_tabu_with_table_async",
+    "qap_set_tile_rows", "qap_get_tile_rows",
+]
+
+_lib = None
+_lock = threading.Lock()
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_vp = ctypes.c_void_p
+
+
+class QapError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, lib().qap_strerror(code).decode(), code))
+
+
+def lib():
+    """Load libqap.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libqap.so is not built: run `python -m paper_2307_11248_amd.build` "
+                                   "(or __graft_entry__.build()) first")
+            L = ctypes.CDLL(LIB_PATH)
+            i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+            sig = {
+                "qap_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+                "qap_create": (ctypes.c_int, [_i32p, _i32p, i32, ctypes.POINTER(_vp)]),
+                "qap_destroy": (ctypes.c_int, [_vp]),
+                "qap_size": (ctypes.c_int, [_vp]),
+                "qap_cost": (ctypes.c_int, [_vp, _i32p, i32, _i64p]),
+                "qap_cost_async": (ctypes.c_int, [_vp, _vp, i32, _vp, _vp]),
+                "qap_delta_table": (ctypes.c_int, [_vp, _i32p, i32, _i32p]),
+                "qap_delta_table_async": (ctypes.c_int, [_vp, _vp, i32, _vp, _vp]),
+                "qap_2opt": (ctypes.c_int, [_vp, _i32p, i32, i32, _i64p, _i32p]),
+                "qap_2opt_async": (ctypes.c_int, [_vp, _vp, i32, i32, _vp, _vp, _vp]),
+                "qap_tabu": (ctypes.c_int, [_vp, _i32p, i32, i32, i32, i32, u64, _i64p, _i32p]),
+                "qap_tabu_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, _vp, _vp, _vp]),
+                "qap_tabu_plain_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, _vp, _vp,
+                                                        _vp]),
+                "qap_2opt_with_table_async": (ctypes.c_int, [_vp, _vp, _vp, i32, i32, _vp, _vp, _vp]),
+                "qap_tabu_with_table_async": (ctypes.c_int, [_vp, _vp, _vp, i32, i32, i32, i32, u64, i64, _vp,
+                                                             _vp, _vp]),
+                "qap_set_tile_rows": (ctypes.c_int, [_vp, i32, i32]),
+                "qap_get_tile_rows": (ctypes.c_int, [_vp, i32, _i32p]),
+            }
+            for name, (res, args) in sig.items():
+                f = getattr(L, name)
+                f.restype, f.argtypes = res, args
+            _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise QapError(rc, what)
+    return rc
+
+
+def _arr(a, dtype, shape=None):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if shape is not None and a.shape != tuple(shape):
+        raise ValueError("expected shape %s, got %s" % (tuple(shape), a.shape))
+    return a
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+def _dptr(t, dtype_name):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != "torch." + dtype_name:
+        raise ValueError("expected a contiguous %s tensor on the GPU" % dtype_name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Handle:
+    """One QAP instance (F, D) copied to the current HIP device (``qap_create``)."""
+
+    def __init__(self, F, D):
+        F = _arr(F, np.int32)
+        n = F.shape[0]
+        D = _arr(D, np.int32, (n, n))
+        if F.shape != (n, n):
+            raise ValueError("F must be square")
+        h = _vp()
+        _check(lib().qap_create(_ptr(F, _i32p), _ptr(D, _i32p), n, ctypes.byref(h)), "qap_create")
+        self._h = h
+        self.n = n
+        self.m = n * (n - 1) // 2
+
+    @property
+    def ptr(self):
+        if self._h is None:
+            raise ValueError("handle is closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().qap_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- tile shape (thread configuration)
+    def set_tile_rows(self, algo: str, rows: int):
+        _check(lib().qap_set_tile_rows(self.ptr, 0 if algo == "tabu" else 1, int(rows)), "qap_set_tile_rows")
+
+    def tile_rows(self, algo: str):
+        lanes = ctypes.c_int32(0)
+        rows = _check(lib().qap_get_tile_rows(self.ptr, 0 if algo == "tabu" else 1, ctypes.byref(lanes)),
+                      "qap_get_tile_rows")
+        return rows, lanes.value
+
+    # -- blocking host calls
+    def cost(self, perms) -> np.ndarray:
+        perms = _arr(perms, np.int32)
+        perms = perms.reshape(-1, self.n)
+        k = perms.shape[0]
+        out = np.zeros(k, dtype=np.int64)
+        _check(lib().qap_cost(self.ptr, _ptr(perms, _i32p), k, _ptr(out, _i64p)), "qap_cost")
+        return out
+
+    def delta_table(self, perms) -> np.ndarray:
+        perms = _arr(perms, np.int32).reshape(-1, self.n)
+        k = perms.shape[0]
+        out = np.zeros((k, self.m), dtype=np.int32)
+        _check(lib().qap_delta_table(self.ptr, _ptr(perms, _i32p), k, _ptr(out, _i32p)), "qap_delta_table")
+        return out
+
+    def two_opt(self, perms, max_iters: int = 0):
+        p = np.array(perms, dtype=np.int32, copy=True).reshape(-1, self.n)
+        k = p.shape[0]
+        costs = np.zeros(k, dtype=np.int64)
+        steps = np.zeros(k, dtype=np.int32)
+        _check(lib().qap_2opt(self.ptr, _ptr(p, _i32p), k, int(max_iters), _ptr(costs, _i64p),
+                              _ptr(steps, _i32p)), "qap_2opt")
+        return p, costs, steps
+
+    def tabu(self, perms, iters: int, lo: int, hi: int, seed: int):
+        p = np.array(perms, dtype=np.int32, copy=True).reshape(-1, self.n)
+        k = p.shape[0]
+        costs = np.zeros(k, dtype=np.int64)
+        done = np.zeros(k, dtype=np.int32)
+        _check(lib().qap_tabu(self.ptr, _ptr(p, _i32p), k, int(iters), int(lo), int(hi), int(seed),
+                              _ptr(costs, _i64p), _ptr(done, _i32p)), "qap_tabu")
+        return p, costs, done
+
+    # -- device / stream calls (torch tensors)
+    def cost_async(self, d_perms, d_costs, stream=None):
+        _check(lib().qap_cost_async(self.ptr, _dptr(d_perms, "int32"), d_perms.shape[0],
+                                    _dptr(d_costs, "int64"), _stream_ptr(stream)), "qap_cost_async")
+
+    def delta_table_async(self, d_perms, d_table, stream=None):
+        _check(lib().qap_delta_table_async(self.ptr, _dptr(d_perms, "int32"), d_perms.shape[0],
+                                           _dptr(d_table, "int32"), _stream_ptr(stream)),
+               "qap_delta_table_async")
+
+    def two_opt_async(self, d_perms, d_costs, d_steps=None, max_iters: int = 0, stream=None):
+        _check(lib().qap_2opt_async(self.ptr, _dptr(d_perms, "int32"), d_perms.shape[0], int(max_iters),
+                                    _dptr(d_costs, "int64"), _dptr(d_steps, "int32"), _stream_ptr(stream)),
+               "qap_2opt_async")
+
+    def tabu_async(self, d_perms, iters, lo, hi, seed, d_best, d_done=None, start_base: int = 0,
+                   stream=None, plain: bool = False):
+        f = lib().qap_tabu_plain_async if plain else lib().qap_tabu_async
+        _check(f(self.ptr, _dptr(d_perms, "int32"), d_perms.shape[0], int(iters), int(lo), int(hi), int(seed),
+                 int(start_base), _dptr(d_best, "int64"), _dptr(d_done, "int32"), _stream_ptr(stream)),
+               "qap_tabu_async")
+
+    def two_opt_with_table_async(self, d_perms, d_table, d_costs, d_steps=None, max_iters: int = 0, stream=None):
+        _check(lib().qap_2opt_with_table_async(self.ptr, _dptr(d_perms, "int32"), _dptr(d_table, "int32"),
+                                               d_perms.shape[0], int(max_iters), _dptr(d_costs, "int64"),
+                                               _dptr(d_steps, "int32"), _stream_ptr(stream)),
+               "qap_2opt_with_table_async")
+
+    def tabu_with_table_async(self, d_perms, d_table, iters, lo, hi, seed, d_best, d_done=None,
+                              start_base: int = 0, stream=None):
+        _check(lib().qap_tabu_with_table_async(self.ptr, _dptr(d_perms, "int32"), _dptr(d_table, "int32"),
+                                               d_perms.shape[0], int(iters), int(lo), int(hi), int(seed),
+                                               int(start_base), _dptr(d_best, "int64"), _dptr(d_done, "int32"),
+                                               _stream_ptr(stream)),
+               "qap_tabu_with_table_async")
