@@ -61,19 +61,16 @@ int rows_index(int rows) {
 bool shape_fits(const qap_ctx *h, int ri) {
     const TileSet &ts = h->tiles[ri];
     if (ts.lanes < 64 || ts.lanes > search_max_lanes(kRowsChoices[ri])) return false;
+    if (ts.ntiles > ts.lanes) return false;
     return search_smem_bytes(h->n, kRowsChoices[ri], ts.lanes, h->sym) <= h->max_smem;
 }
 
-// Default tile shape: the one whose lane count is closest to 256 (four waves per
-// search), larger tiles preferred on ties.
+// Default tile shape: the smallest tile that fits (the most lanes per search, hence the
+// shortest dependency chain per iteration).
 int default_rows(const qap_ctx *h) {
-    int best = -1, bestd = 1 << 30;
-    for (int i = 3; i >= 0; --i) {
-        if (!shape_fits(h, i)) continue;
-        const int d = std::abs(h->tiles[i].lanes - 256);
-        if (d < bestd) { best = i; bestd = d; }
-    }
-    return best;
+    for (int i = 0; i < 4; ++i)
+        if (shape_fits(h, i)) return i;
+    return -1;
 }
 
 // Map a HIP status to a QAP code; with QAP_VERBOSE set in the environment, a failure
@@ -232,7 +229,7 @@ int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out) {
         TileSet &ts = h->tiles[i];
         ts.ntiles = (int)tl.size();
         ts.ninterior = ninner;
-        ts.lanes = std::max(64, (ts.ntiles + 63) / 64 * 64);
+        ts.lanes = search_lanes(n, kRowsChoices[i], ts.ntiles, h->sym);
         e = hipMalloc((void **)&ts.d_tiles, tl.size() * sizeof(int32_t) + 16);
         if (e == hipSuccess)
             e = hipMemcpy(ts.d_tiles, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice);

@@ -35,10 +35,12 @@ __host__ __device__ inline long long pidx(int n, int r, int s) {
     return (long long)r * n - (long long)r * (r + 1) / 2 + (s - r - 1);
 }
 
-// Byte offsets of the per-search shared-memory arrays.  The matrices are the u8 copies
-// of F, F^T, D, D^T (only F and D when both are symmetric).
+// Byte offsets of the per-search shared-memory arrays of the search kernels.  The
+// matrices are u8 rows of RS bytes: D, D^T, and G = F[p][p] (the flows seen from the
+// locations under the current permutation p), G^T; only D and G when F and D are
+// both symmetric.
 struct Smem {
-    int mats, x, acbe, rr, p, rd, cd, perm, pinv, bestp, ten, red, total;
+    int d, dt, g, gt, acbe, rpr, rps, kc, perm, bestp, pinv, ten, red, total;
 };
 
 __host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym) {
@@ -46,21 +48,26 @@ __host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym) {
     Smem s;
     int o = 0;
     auto take = [&o](int bytes) { int at = o; o += (bytes + 15) & ~15; return at; };
-    s.mats = take((sym ? 2 : 4) * n * rs);
-    s.x = take(8 * rs);
+    s.d = take(n * rs);
+    s.dt = sym ? s.d : take(n * rs);
+    s.g = take(n * rs);
+    s.gt = sym ? s.g : take(n * rs);
     s.acbe = take(np * 8);
-    s.rr = take(np * 8);
-    s.p = take(4 * np * 8);
-    s.rd = take(np * 4);
-    s.cd = take(np * 4);
+    s.rpr = take(np * 4);
+    s.rps = take(np * 4);
+    s.kc = take(4 * 4);
     s.perm = take(np * 4);
-    s.pinv = take(np * 4);
     s.bestp = take(np * 4);
+    s.pinv = take(np * 4);
     s.ten = take(lanes * 4);
     s.red = take(16 * 8);
     s.total = o;
     return s;
 }
+
+// Lanes a search workgroup needs: one per register tile, and at least one per (index,
+// dot family) task when that fits, so the row recomputation runs in one pass.
+__host__ __device__ inline int families(int sym) { return sym ? 2 : 4; }
 
 // Arguments of the cost and neighbourhood-table kernels.
 struct TableArgs {
@@ -112,5 +119,7 @@ hipError_t launch_search(int rows, bool tabu, const SearchArgs &a, int grid, int
                          hipStream_t st);
 size_t search_smem_bytes(int n, int rows, int lanes, int sym);
 int search_max_lanes(int rows);
+// Lanes of a search workgroup for a tile shape, or 0 if the shape cannot serve n.
+int search_lanes(int n, int rows, int ntiles, int sym);
 
 }  // namespace qapk

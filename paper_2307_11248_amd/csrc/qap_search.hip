@@ -1,35 +1,38 @@
-// qap_search.hip -- persistent 2opt and tabu search kernels (Secs. 4.1-4.4), one
-// workgroup per search, the whole search in one launch.
+// qap_search.hip -- persistent 2opt and tabu search kernels (Secs. 4.1-4.4): one
+// workgroup per search, the whole search in one launch, two workgroup barriers per
+// iteration.
 //
 // Data layout
 //   * The neighbourhood (one delta per move) lives in registers for the whole search.
-//     Lane l of the workgroup owns one tile of the n x n move grid: rows
-//     u = ROWS*g .. ROWS*g+ROWS-1 and columns v = 4b .. 4b+3.  Only tiles that hold
-//     some u < v are kept.  A tile that straddles the diagonal also holds mirror slots
-//     (u > v), which carry the same delta and the same tabu state as (v, u), and
-//     diagonal slots (u == v), which hold BIG and are never chosen; slots with u or v
-//     beyond n (padding) are reset to BIG after every update.
-//   * F, F^T, D, D^T are staged in LDS as u8 rows padded to RS = roundup(n, 16) bytes
-//     (F and D only when both are symmetric).
+//     Lane l owns one tile of the n x n move grid: rows u = ROWS*g .. ROWS*g+ROWS-1 and
+//     columns v = 4b .. 4b+3.  Only tiles that hold some u < v exist.  A tile that
+//     straddles the diagonal also holds mirror slots (u > v), which carry the same delta
+//     and tabu state as (v, u) and so never change the choice, and diagonal slots
+//     (u == v), which hold BIG; slots past n (padding) are reset to BIG every iteration.
+//   * LDS holds u8 rows of RS = roundup(n, 16) bytes: D and D^T (static) and
+//     G = F[p][p], G^T, the flows seen from the locations under the current
+//     permutation p (only D and G when F and D are both symmetric).  After a move
+//     (r, s), G changes by exchanging rows r, s and columns r, s, done in place.
 //   * The tabu state of a move is the iteration at which it becomes free again
 //     (Tabuarr of Sec. 4.3), one int32 register beside each delta.
 //
-// One iteration (the move of iteration `it` is chosen from the deltas of the current
-// permutation pi; p' = pi with r and s exchanged):
-//   select  each lane folds admissibility and a (delta, key) minimum over its slots;
-//           wave minimum by shuffles, workgroup minimum through LDS      [barrier B1]
-//   A       apply: cost, best-so-far; the four per-index vectors of the incremental
-//           update (A, C | B, E packed as int16 pairs); the eight gathered vectors the
-//           row recomputation contracts against                          [barrier B2]
-//   P       the n-long dot products (u8 x u8, v_dot4) that give, for every u, the
-//           deltas of (u, r) and (u, s) under p'                         [barrier B3]
-//   R       combine them into Rr[u] = delta'(u, r), Rs[u] = delta'(u, s)   [barrier B4]
+// One iteration (p' = p with r and s exchanged, sigma the exchange of r and s):
+//   select  each lane folds admissibility and a (delta, key) minimum over its slots; a
+//           DPP wave minimum, then the workgroup minimum through LDS        [barrier B1]
+//   X       (a) every lane loads the update vectors of its tile's rows and columns
+//               A_x = d_xr - d_xs, C_x = d_rx - d_sx, B_x = g_xr - g_xs, E_x = g_rx - g_sx
+//               (g = G under p), packed as int16 pairs;
+//           (b) the deltas of the moves (u, r) and (u, s) under p', for every u, as four
+//               families of n-long u8 dot products (v_dot4) between rows of G, G^T and
+//               rows of D, D^T, read under sigma with an O(1) correction; the lanes of
+//               one u exchange their dot products by DPP quad permutes and combine them;
+//           (c) best-so-far bookkeeping                                       [barrier B2]
 //   C       every lane updates its tile: delta += (A_u - A_v)(B_u - B_v)
-//           + (C_u - C_v)(E_u - E_v) as one v_pk_sub_i16 pair and one v_dot2; the rows
-//           and columns of r and s are overwritten from Rr / Rs; the move gets its tabu
-//           tenure.
-// The deltas of moves disjoint from {r, s} follow from the k = r, s terms of Eq. (2)
-// (Taillard 1991, the elementary tabu search the paper follows); the others are
+//           + (C_u - C_v)(E_u - E_v) as two v_pk_sub_i16 and one v_dot2; the rows and
+//           columns of r and s are overwritten with the recomputed deltas; the move gets
+//           its tabu tenure; G, G^T and p are updated in place.
+// The deltas of moves disjoint from {r, s} change only through the k = r, s terms of
+// Eq. (2) (Taillard 1991, the elementary tabu search the paper follows); all others are
 // recomputed exactly, so every delta stays equal to Eq. (2) of the current permutation.
 #include "qap_internal.h"
 
@@ -39,12 +42,40 @@ namespace {
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
+template <int ROWS>
+constexpr int max_lanes() { return ROWS <= 2 ? 1024 : (ROWS <= 8 ? 512 : 256); }
+
+// (index, family) tasks one lane may carry: enough for 4 n <= 1024 tasks at the lane cap.
+template <int ROWS>
+constexpr int max_tasks() { return 1024 / max_lanes<ROWS>(); }
+
+template <int CTRL>
+__device__ inline int dpp(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+
+// Minimum of a signed 64-bit key over the wave, by DPP row shifts and row broadcasts;
+// every lane returns the minimum.
 __device__ inline long long wave_min64(long long v) {
-    for (int off = 32; off > 0; off >>= 1) {
-        const long long o = __shfl_xor(v, off, 64);
-        v = o < v ? o : v;
+    int lo = (int)v, hi = (int)(v >> 32);
+#define QAP_DPP_MIN_STEP(ctrl, rm)                                                        \
+    {                                                                                     \
+        const int olo = __builtin_amdgcn_update_dpp(lo, lo, ctrl, rm, 0xF, false);      \
+        const int ohi = __builtin_amdgcn_update_dpp(hi, hi, ctrl, rm, 0xF, false);      \
+        const long long o = ((long long)ohi << 32) | (unsigned)olo;                       \
+        const long long c = ((long long)hi << 32) | (unsigned)lo;                         \
+        if (o < c) { lo = olo; hi = ohi; }                                                \
     }
-    return v;
+    QAP_DPP_MIN_STEP(0x111, 0xF)   // row_shr:1
+    QAP_DPP_MIN_STEP(0x112, 0xF)   // row_shr:2
+    QAP_DPP_MIN_STEP(0x114, 0xF)   // row_shr:4
+    QAP_DPP_MIN_STEP(0x118, 0xF)   // row_shr:8
+    QAP_DPP_MIN_STEP(0x142, 0xA)   // row_bcast:15
+    QAP_DPP_MIN_STEP(0x143, 0xC)   // row_bcast:31
+#undef QAP_DPP_MIN_STEP
+    lo = __builtin_amdgcn_readlane(lo, 63);
+    hi = __builtin_amdgcn_readlane(hi, 63);
+    return ((long long)hi << 32) | (unsigned)lo;
 }
 
 __device__ inline long long wave_sum64(long long v) {
@@ -54,6 +85,16 @@ __device__ inline long long wave_sum64(long long v) {
 
 __device__ inline int pack16(int lo, int hi) {
     return (int)(((unsigned)hi << 16) | ((unsigned)lo & 0xffffu));
+}
+
+__device__ inline int byte_at(unsigned w, int e) { return (int)((w >> (8 * e)) & 0xffu); }
+
+// (x_e - y_e) | (z_e - w_e) << 16 for bytes e of four row words: one packed int16 pair
+// of update-vector entries.
+__device__ inline int diff_pair(unsigned x, unsigned y, unsigned z, unsigned w, int e) {
+    const short2_t a = __builtin_bit_cast(short2_t, pack16(byte_at(x, e), byte_at(z, e)));
+    const short2_t b = __builtin_bit_cast(short2_t, pack16(byte_at(y, e), byte_at(w, e)));
+    return __builtin_bit_cast(int, a - b);
 }
 
 // Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64x64->128 multiplications,
@@ -82,8 +123,53 @@ __device__ inline int draw_tenure(unsigned long long seed, long long it, long lo
     return lo + (int)(((x >> 32) * span) >> 32);
 }
 
+__device__ inline unsigned dot_rows(const uint8_t *a, const uint8_t *b, int rs) {
+    unsigned acc = 0;
+    for (int w = 0; w < rs; w += 16) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(a + w);
+        const uint4 y = *reinterpret_cast<const uint4 *>(b + w);
+        acc = __builtin_amdgcn_udot4(x.x, y.x, acc, false);
+        acc = __builtin_amdgcn_udot4(x.y, y.y, acc, false);
+        acc = __builtin_amdgcn_udot4(x.z, y.z, acc, false);
+        acc = __builtin_amdgcn_udot4(x.w, y.w, acc, false);
+    }
+    return acc;
+}
+
+// Two dot products sharing the row `a`.
+__device__ inline void dot_rows2(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
+                                 unsigned &o2) {
+    unsigned c1 = 0, c2 = 0;
+    for (int w = 0; w < rs; w += 16) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(a + w);
+        const uint4 y = *reinterpret_cast<const uint4 *>(b1 + w);
+        const uint4 z = *reinterpret_cast<const uint4 *>(b2 + w);
+        c1 = __builtin_amdgcn_udot4(x.x, y.x, c1, false);
+        c1 = __builtin_amdgcn_udot4(x.y, y.y, c1, false);
+        c1 = __builtin_amdgcn_udot4(x.z, y.z, c1, false);
+        c1 = __builtin_amdgcn_udot4(x.w, y.w, c1, false);
+        c2 = __builtin_amdgcn_udot4(x.x, z.x, c2, false);
+        c2 = __builtin_amdgcn_udot4(x.y, z.y, c2, false);
+        c2 = __builtin_amdgcn_udot4(x.z, z.z, c2, false);
+        c2 = __builtin_amdgcn_udot4(x.w, z.w, c2, false);
+    }
+    o1 = c1;
+    o2 = c2;
+}
+
+// ROWS consecutive bytes of an LDS row starting at u0 (u0 a multiple of ROWS): whole
+// words for ROWS >= 4, else one word and the byte offset of u0 inside it.
 template <int ROWS>
-constexpr int max_lanes() { return ROWS <= 4 ? 1024 : 512; }
+__device__ inline void row_bytes(const uint8_t *row, int u0, unsigned (&w)[(ROWS + 3) / 4], int &shift) {
+    if (ROWS >= 4) {
+#pragma unroll
+        for (int i = 0; i < (ROWS + 3) / 4; ++i) w[i] = *reinterpret_cast<const unsigned *>(row + u0 + 4 * i);
+        shift = 0;
+    } else {
+        w[0] = *reinterpret_cast<const unsigned *>(row + (u0 & ~3));
+        shift = u0 & 3;
+    }
+}
 
 template <int ROWS, bool TABU>
 __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a) {
@@ -93,36 +179,30 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
     const int lane = t & 63, wid = t >> 6, W = L >> 6;
     const int job = a.job0 + blockIdx.x;
     const int sym = a.sym;
+    const int nq = families(sym), lq = sym ? 1 : 2;
     const int np = padded_n(n, ROWS);
     const Smem S = smem_plan(n, np, L, sym);
+    constexpr int MAXT = max_tasks<ROWS>();
 
-    uint8_t *Fm = sm + S.mats;
-    uint8_t *FmT = sym ? Fm : Fm + n * rs;
-    uint8_t *Dm = sym ? Fm + n * rs : Fm + 2 * n * rs;
-    uint8_t *DmT = sym ? Dm : Fm + 3 * n * rs;
-    uint8_t *X = sm + S.x;
-    int2 *acbe = reinterpret_cast<int2 *>(sm + S.acbe);
-    int2 *R = reinterpret_cast<int2 *>(sm + S.rr);
-    int2 *P = reinterpret_cast<int2 *>(sm + S.p);
-    int *RD = reinterpret_cast<int *>(sm + S.rd);
-    int *CD = reinterpret_cast<int *>(sm + S.cd);
+    uint8_t *Dm = sm + S.d, *DmT = sm + S.dt, *Gm = sm + S.g, *GmT = sm + S.gt;
+    int *rpr = reinterpret_cast<int *>(sm + S.rpr);
+    int *rps = reinterpret_cast<int *>(sm + S.rps);
+    int *kc = reinterpret_cast<int *>(sm + S.kc);
+    int *acbe = reinterpret_cast<int *>(sm + S.acbe);
     int *perm = reinterpret_cast<int *>(sm + S.perm);
-    int *pinv = reinterpret_cast<int *>(sm + S.pinv);
     int *bestp = reinterpret_cast<int *>(sm + S.bestp);
+    int *pinv = reinterpret_cast<int *>(sm + S.pinv);
     int *ten = reinterpret_cast<int *>(sm + S.ten);
     long long *red = reinterpret_cast<long long *>(sm + S.red);
 
-    // ---- stage matrices, clear the gathered vectors, read and check the start
+    // ---- stage D, D^T; read and check the start
     {
         const int per = n * rs / 16;
         const uint4 *src = reinterpret_cast<const uint4 *>(a.mats);
-        uint4 *dst = reinterpret_cast<uint4 *>(Fm);
-        const int nm = sym ? 2 : 4;
-        for (int mi = 0; mi < nm; ++mi) {
-            const int from = sym ? 2 * mi : mi;
-            for (int i = t; i < per; i += L) dst[mi * per + i] = src[from * per + i];
+        for (int i = t; i < per; i += L) {
+            reinterpret_cast<uint4 *>(Dm)[i] = src[2 * per + i];
+            if (!sym) reinterpret_cast<uint4 *>(DmT)[i] = src[3 * per + i];
         }
-        for (int i = t; i < 2 * rs; i += L) reinterpret_cast<int *>(X)[i] = 0;
     }
     if (t == 0) s_bad = 0;
     for (int u = t; u < np; u += L) pinv[u] = -1;
@@ -131,6 +211,7 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
     for (int u = t; u < n; u += L) {
         const int v = pin[u];
         perm[u] = v;
+        bestp[u] = v;
         if (v < 0 || v >= n || atomicExch(&pinv[v], u) != -1) s_bad = 1;
     }
     __syncthreads();
@@ -144,22 +225,36 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
         return;
     }
 
-    // ---- cost (Eq. 1) and the row/column sums RD_u = sum_k D[u][k] F[p_u][p_k],
-    //      CD_u = sum_k D[k][u] F[p_k][p_u] that the row recomputation needs
+    // ---- G = F[p][p] and G^T, gathered from the global u8 copies of F and F^T
+    {
+        const int wpr = rs / 4;  // words per row
+        const uint8_t *Fg = a.mats, *FgT = a.mats + (size_t)n * rs;
+        for (int i = t; i < n * wpr; i += L) {
+            const int row = i / wpr, c0 = (i - row * wpr) * 4;
+            const int pr = perm[row];
+            unsigned wg = 0, wgt = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int c = c0 + e;
+                if (c < n) {
+                    const int pc = perm[c];
+                    wg |= (unsigned)Fg[(size_t)pr * rs + pc] << (8 * e);
+                    if (!sym) wgt |= (unsigned)FgT[(size_t)pr * rs + pc] << (8 * e);
+                }
+            }
+            reinterpret_cast<unsigned *>(Gm)[i] = wg;
+            if (!sym) reinterpret_cast<unsigned *>(GmT)[i] = wgt;
+        }
+    }
+    __syncthreads();
+
+    // ---- RD_u = sum_k D[u][k] G[u][k], CD_u = sum_k D[k][u] G[k][u]; cost (Eq. 1) = sum RD_u
     long long part = 0;
     for (int u = t; u < n; u += L) {
-        bestp[u] = perm[u];
-        const uint8_t *fr = Fm + perm[u] * rs, *dr = Dm + u * rs;
-        const uint8_t *ftr = FmT + perm[u] * rs, *dtr = DmT + u * rs;
-        int acc = 0, acc2 = 0;
-        for (int k = 0; k < n; ++k) {
-            const int pk = perm[k];
-            acc += (int)fr[pk] * (int)dr[k];
-            acc2 += (int)ftr[pk] * (int)dtr[k];
-        }
-        RD[u] = acc;
-        CD[u] = acc2;
-        part += acc;
+        const int rd = (int)dot_rows(Dm + u * rs, Gm + u * rs, rs);
+        rpr[u] = rd;
+        rps[u] = sym ? rd : (int)dot_rows(DmT + u * rs, GmT + u * rs, rs);
+        part += rd;
     }
     part = wave_sum64(part);
     if (lane == 0) red[wid] = part;
@@ -167,6 +262,20 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
     long long cur = 0;
     for (int w = 0; w < W; ++w) cur += red[w];
     long long best = cur;
+    // per task: RD_u, CD_u, d_uu and g_uu of its u, kept in registers
+    int rdv[MAXT], cdv[MAXT], duv[MAXT], guv[MAXT];
+#pragma unroll
+    for (int i = 0; i < MAXT; ++i) {
+        const int tk = t + i * L;
+        rdv[i] = cdv[i] = duv[i] = guv[i] = 0;
+        if (tk < nq * n) {
+            const int u = tk >> lq;
+            rdv[i] = rpr[u];
+            cdv[i] = rps[u];
+            duv[i] = Dm[u * rs + u];
+            guv[i] = Gm[u * rs + u];
+        }
+    }
 
     // ---- this lane's tile, its deltas and tabu state
     const bool active = t < a.ntiles;
@@ -194,7 +303,7 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
         }
     }
     const long long start_id = a.start_base + job;
-    int it = 1, steps = 0;
+    int it = 1, steps = 0, tpos = 0;   // tpos = (it - 1) mod L, the tenure ring slot
     __syncthreads();
 
     for (;;) {
@@ -221,157 +330,232 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
         }
         if (!active) bd = INT32_MAX;
         const int key = (bs < 0 || !active) ? KEY_NONE : (((u0 + (bs >> 2)) << 9) | (v0 + (bs & 3)));
-        long long kv = ((long long)bd << 32) | (unsigned)key;
-        kv = wave_min64(kv);
-        if (lane == 0) red[wid] = kv;
+        const long long kw = wave_min64(((long long)bd << 32) | (unsigned)key);
+        if (lane == 0) red[wid] = kw;
         __syncthreads();  // B1
         long long mk = red[0];
-        for (int w = 1; w < W; ++w) mk = red[w] < mk ? red[w] : mk;
+        for (int w = 1; w < W; ++w) {
+            const long long o = red[w];
+            mk = o < mk ? o : mk;
+        }
         const int dstar = (int)(mk >> 32);
         if (TABU ? (dstar == INT32_MAX) : (dstar >= 0)) break;
         const int kstar = (int)(mk & 0xffffffffLL);
         int r = kstar >> 9, s = kstar & 511;
         if (r > s) { const int tmp = r; r = s; s = tmp; }
-
-        // ---- A: apply the move to the cost, build the update vectors
-        const int pr = perm[r], ps = perm[s];
         const bool improved = TABU && (cur + dstar < best);
         cur += dstar;
         if (improved) best = cur;
-        if (TABU && ((it - 1) % L) == 0) ten[t] = draw_tenure(a.seed, (long long)it + t, start_id, a.lo, a.hi);
-        for (int u = t; u < n; u += L) {
-            const int pu = perm[u];
-            const int A = (int)DmT[r * rs + u] - (int)DmT[s * rs + u];   // d_ur - d_us
-            const int Cv = (int)Dm[r * rs + u] - (int)Dm[s * rs + u];    // d_ru - d_su
-            const int B = (int)FmT[pr * rs + pu] - (int)FmT[ps * rs + pu];  // f[pu][pr] - f[pu][ps]
-            const int E = (int)Fm[pr * rs + pu] - (int)Fm[ps * rs + pu];    // f[pr][pu] - f[ps][pu]
-            acbe[u] = make_int2(pack16(A, Cv), pack16(B, E));
-            if (u != r && u != s) {
-                RD[u] -= A * B;
-                CD[u] -= Cv * E;
-            }
-            const int pu2 = (u == r) ? ps : ((u == s) ? pr : pu);   // p'_u
-            // gathered vectors over locations k = u, contracted with rows of D and D^T
-            X[4 * rs + u] = Fm[ps * rs + pu2];    // f[p'_r][p'_k]
-            X[5 * rs + u] = Fm[pr * rs + pu2];    // f[p'_s][p'_k]
-            if (!sym) {
-                X[6 * rs + u] = FmT[ps * rs + pu2];  // f[p'_k][p'_r]
-                X[7 * rs + u] = FmT[pr * rs + pu2];  // f[p'_k][p'_s]
-            }
-            // gathered vectors over units m = u, contracted with rows of F and F^T
-            const int inv = pinv[u];
-            const int inv2 = (u == pr) ? s : ((u == ps) ? r : inv);   // p'^-1(m)
-            X[0 * rs + u] = Dm[r * rs + inv2];     // d[r][p'^-1 m]
-            X[1 * rs + u] = Dm[s * rs + inv2];     // d[s][p'^-1 m]
-            if (!sym) {
-                X[2 * rs + u] = DmT[r * rs + inv2];  // d[p'^-1 m][r]
-                X[3 * rs + u] = DmT[s * rs + inv2];  // d[p'^-1 m][s]
-            }
-            if (improved) bestp[u] = pu2;
+
+        // ---- X: one (u, family) task per lane: the update vectors of u, and the deltas
+        //      of (u, r) and (u, s) under p'
+        int colw_addr[MAXT], colw_val[MAXT];
+#pragma unroll
+        for (int i = 0; i < MAXT; ++i) {
+            colw_addr[i] = -1;   // every slot, also those past the last task of this lane
+            colw_val[i] = 0;
         }
+#pragma unroll
+        for (int i = 0; i < MAXT; ++i) {
+            const int tk = t + i * L;
+            if (tk >= nq * n) break;
+            const int u = tk >> lq, q = tk & (nq - 1);
+            const int f = sym ? 2 * q : q;   // 0 G.D, 1 G^T.D^T, 2 D.G, 3 D^T.G^T
+            const int su = u == r ? s : (u == s ? r : u);
+            // The lanes of u split the bytes they all need and share them by DPP:
+            //   q=0: d_ur d_us D_rr D_rs   q=1: d_ru d_su D_sr D_ss
+            //   q=2: g_ur g_us G_rr G_rs   q=3: g_ru g_su G_sr G_ss   (g = G under p)
+            // (symmetric: q=0 the D bytes, q=1 the G bytes, plus D_ss / G_ss).
+            const uint8_t *M = (sym ? q == 0 : q < 2) ? Dm : Gm;
+            const bool tr = !sym && (q & 1);
+            const unsigned rec = (unsigned)M[tr ? r * rs + u : u * rs + r] |
+                                 ((unsigned)M[tr ? s * rs + u : u * rs + s] << 8) |
+                                 ((unsigned)M[tr ? s * rs + r : r * rs + r] << 16) |
+                                 ((unsigned)M[tr ? s * rs + s : r * rs + s] << 24);
+            unsigned rd_, rdt_, rg_, rgt_, exd = 0, exg = 0;
+            if (sym) {
+                const int ex = M[s * rs + s];
+                rd_ = rdt_ = (unsigned)dpp<0xA0>((int)rec);
+                rg_ = rgt_ = (unsigned)dpp<0xF5>((int)rec);
+                exd = (unsigned)dpp<0xA0>(ex);
+                exg = (unsigned)dpp<0xF5>(ex);
+            } else {
+                rd_ = (unsigned)dpp<0x00>((int)rec);
+                rdt_ = (unsigned)dpp<0x55>((int)rec);
+                rg_ = (unsigned)dpp<0xAA>((int)rec);
+                rgt_ = (unsigned)dpp<0xFF>((int)rec);
+            }
+            const int d_ur = byte_at(rd_, 0), d_us = byte_at(rd_, 1), D_rr = byte_at(rd_, 2), D_rs = byte_at(rd_, 3);
+            const int g_ur = byte_at(rg_, 0), g_us = byte_at(rg_, 1), G_rr = byte_at(rg_, 2), G_rs = byte_at(rg_, 3);
+            const int d_ru = byte_at(rdt_, 0), d_su = byte_at(rdt_, 1);
+            const int g_ru = byte_at(rgt_, 0), g_su = byte_at(rgt_, 1);
+            const int D_sr = sym ? D_rs : byte_at(rdt_, 2), D_ss = sym ? (int)exd : byte_at(rdt_, 3);
+            const int G_sr = sym ? G_rs : byte_at(rgt_, 2), G_ss = sym ? (int)exg : byte_at(rgt_, 3);
+
+            // dot products with the O(1) correction sum_k a[sigma k] c[k] = a.c + (a_s - a_r)(c_r - c_s)
+            unsigned d1, d2;
+            int x, y;
+            if (f < 2) {
+                // sum_k G'[u][k] D[b][k] (f = 0), sum_k G'[k][u] D[k][b] (f = 1)
+                const uint8_t *ga = ((f & 1) ? GmT : Gm) + su * rs;
+                const uint8_t *c1 = ((f & 1) ? DmT : Dm) + r * rs, *c2 = ((f & 1) ? DmT : Dm) + s * rs;
+                dot_rows2(ga, c1, c2, rs, d1, d2);
+                int as_, ar_;
+                if (f == 0) {
+                    as_ = u == r ? G_ss : (u == s ? G_rs : g_us);
+                    ar_ = u == r ? G_sr : (u == s ? G_rr : g_ur);
+                    x = (int)d1 + (as_ - ar_) * (D_rr - D_rs);
+                    y = (int)d2 + (as_ - ar_) * (D_sr - D_ss);
+                } else {
+                    as_ = u == r ? G_ss : (u == s ? G_sr : g_su);
+                    ar_ = u == r ? G_rs : (u == s ? G_rr : g_ru);
+                    x = (int)d1 + (as_ - ar_) * (D_rr - D_sr);
+                    y = (int)d2 + (as_ - ar_) * (D_rs - D_ss);
+                }
+            } else {
+                // sum_k D[u][k] G'[b][k] (f = 2), sum_k D[k][u] G'[k][b] (f = 3)
+                const uint8_t *dc = ((f & 1) ? DmT : Dm) + u * rs;
+                const uint8_t *g1 = ((f & 1) ? GmT : Gm) + s * rs, *g2 = ((f & 1) ? GmT : Gm) + r * rs;
+                dot_rows2(dc, g1, g2, rs, d1, d2);
+                if (f == 2) {
+                    x = (int)d1 + (G_ss - G_sr) * (d_ur - d_us);
+                    y = (int)d2 + (G_rs - G_rr) * (d_ur - d_us);
+                } else {
+                    x = (int)d1 + (G_ss - G_rs) * (d_ru - d_su);
+                    y = (int)d2 + (G_sr - G_rr) * (d_ru - d_su);
+                }
+            }
+            // the four families of u (two when symmetric), shared inside the quad
+            int xf[4], yf[4];
+            if (sym) {
+                xf[0] = xf[1] = dpp<0xA0>(x);   // quad_perm [0,0,2,2]
+                yf[0] = yf[1] = dpp<0xA0>(y);
+                xf[2] = xf[3] = dpp<0xF5>(x);   // quad_perm [1,1,3,3]
+                yf[2] = yf[3] = dpp<0xF5>(y);
+            } else {
+                xf[0] = dpp<0x00>(x); yf[0] = dpp<0x00>(y);
+                xf[1] = dpp<0x55>(x); yf[1] = dpp<0x55>(y);
+                xf[2] = dpp<0xAA>(x); yf[2] = dpp<0xAA>(y);
+                xf[3] = dpp<0xFF>(x); yf[3] = dpp<0xFF>(y);
+            }
+            const int A = d_ur - d_us, B = g_ur - g_us, C = d_ru - d_su, E = g_ru - g_su;
+            // RD'_u, CD'_u under p'
+            int rdn, cdn;
+            if (u == r) {
+                rdn = xf[2];
+                cdn = xf[3];
+            } else if (u == s) {
+                rdn = yf[2];
+                cdn = yf[3];
+            } else {
+                rdn = rdv[i] - A * B;
+                cdn = cdv[i] - C * E;
+            }
+            rdv[i] = rdn;
+            cdv[i] = cdn;
+            if (q == 0) {
+                reinterpret_cast<int2 *>(acbe)[u] = make_int2(pack16(A, C), pack16(B, E));
+                if (u == r || u == s) kc[u == r ? 0 : 1] = rdn + cdn;
+            }
+            if (q < 2 && u != r && u != s) {
+                // delta'(u, b) + RD'_b + CD'_b for b = r (q == 0) or b = s (q == 1)
+                const int X = q == 0 ? xf[0] : yf[0], Y = q == 0 ? xf[1] : yf[1];
+                const int Z = q == 0 ? xf[2] : yf[2], Wv = q == 0 ? xf[3] : yf[3];
+                const int duu = duv[i], guu = guv[i];
+                const int dbb = q == 0 ? D_rr : D_ss, gbb = q == 0 ? G_ss : G_rr;
+                const int dub = q == 0 ? d_ur : d_us, dbu = q == 0 ? d_ru : d_su;
+                const int gub = q == 0 ? g_us : g_ur, gbu = q == 0 ? g_su : g_ru;
+                const int rowex = (dbu - duu) * (guu - gbu) + (dbb - dub) * (gub - gbb);
+                const int colex = (dub - duu) * (guu - gub) + (dbb - dbu) * (gbu - gbb);
+                const int diag = (dbb - duu) * (guu - gbb) + (dbu - dub) * (gub - gbu);
+                (q == 0 ? rpr : rps)[u] = X + Y + Z + Wv - rdn - cdn - rowex - colex + diag;
+            }
+            if (u == r) guv[i] = G_ss;
+            if (u == s) guv[i] = G_rr;
+            // this lane's share of exchanging columns r and s of G (and G^T) in row u
+            if (u != r && u != s) {
+                if (sym) {
+                    colw_addr[i] = S.g + u * rs + (q == 0 ? r : s);
+                    colw_val[i] = q == 0 ? g_us : g_ur;
+                } else {
+                    colw_addr[i] = ((q & 2) ? S.gt : S.g) + u * rs + ((q & 1) ? s : r);
+                    colw_val[i] = q == 0 ? g_us : (q == 1 ? g_ur : (q == 2 ? g_su : g_ru));
+                }
+            }
+        }
+
+        // ---- best-so-far and tenures
+        if (improved)
+            for (int u = t; u < n; u += L) bestp[u] = perm[u == r ? s : (u == s ? r : u)];
+        if (TABU && tpos == 0) ten[t] = draw_tenure(a.seed, (long long)it + t, start_id, a.lo, a.hi);
         __syncthreads();  // B2
 
-        // ---- P: dot products of n-long u8 rows for every u (q: F, F^T, D, D^T rows)
+        // ---- C: G, G^T and p follow the move
+        if (wid == 0 && lane < rs / 4) {
+            // rows r and s exchange, with their entries at columns r and s exchanged; one
+            // wave does both rows so every read precedes every write
+            const int wr = lane;
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                if (side == 1 && sym) break;
+                uint8_t *Gx = side ? GmT : Gm;
+                const unsigned grr = Gx[r * rs + r], grs = Gx[r * rs + s];
+                const unsigned gsr = Gx[s * rs + r], gss = Gx[s * rs + s];
+                const unsigned xr = reinterpret_cast<unsigned *>(Gx + r * rs)[wr];
+                const unsigned xs = reinterpret_cast<unsigned *>(Gx + s * rs)[wr];
+                unsigned nr = xs, ns = xr;
+                if ((r >> 2) == wr) {
+                    const int sh = 8 * (r & 3);
+                    nr = (nr & ~(0xffu << sh)) | (gss << sh);
+                    ns = (ns & ~(0xffu << sh)) | (grs << sh);
+                }
+                if ((s >> 2) == wr) {
+                    const int sh = 8 * (s & 3);
+                    nr = (nr & ~(0xffu << sh)) | (gsr << sh);
+                    ns = (ns & ~(0xffu << sh)) | (grr << sh);
+                }
+                __builtin_amdgcn_wave_barrier();
+                reinterpret_cast<unsigned *>(Gx + r * rs)[wr] = nr;
+                reinterpret_cast<unsigned *>(Gx + s * rs)[wr] = ns;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < MAXT; ++i)
+            if (colw_addr[i] >= 0) sm[colw_addr[i]] = (uint8_t)colw_val[i];
         if (t == 0) {
+            const int pr = perm[r], ps = perm[s];
             perm[r] = ps;
             perm[s] = pr;
-            pinv[pr] = s;
-            pinv[ps] = r;
         }
-        {
-            const int nq = sym ? 2 : 4;
-            for (int task = t; task < nq * n; task += L) {
-                const int qi = task / n, u = task - qi * n;
-                const int q = sym ? 2 * qi : qi;
-                const int pu2 = (u == r) ? ps : ((u == s) ? pr : perm[u]);
-                const uint8_t *row = q == 0 ? Fm + pu2 * rs
-                                   : q == 1 ? FmT + pu2 * rs
-                                   : q == 2 ? Dm + u * rs : DmT + u * rs;
-                const uint8_t *xr = X + (2 * q) * rs, *xs = xr + rs;
-                unsigned ar = 0, as = 0;
-                for (int w = 0; w < rs; w += 16) {
-                    const uint4 rv = *reinterpret_cast<const uint4 *>(row + w);
-                    const uint4 x1 = *reinterpret_cast<const uint4 *>(xr + w);
-                    const uint4 x2 = *reinterpret_cast<const uint4 *>(xs + w);
-                    ar = __builtin_amdgcn_udot4(rv.x, x1.x, ar, false);
-                    ar = __builtin_amdgcn_udot4(rv.y, x1.y, ar, false);
-                    ar = __builtin_amdgcn_udot4(rv.z, x1.z, ar, false);
-                    ar = __builtin_amdgcn_udot4(rv.w, x1.w, ar, false);
-                    as = __builtin_amdgcn_udot4(rv.x, x2.x, as, false);
-                    as = __builtin_amdgcn_udot4(rv.y, x2.y, as, false);
-                    as = __builtin_amdgcn_udot4(rv.z, x2.z, as, false);
-                    as = __builtin_amdgcn_udot4(rv.w, x2.w, as, false);
-                }
-                P[q * np + u] = make_int2((int)ar, (int)as);
-            }
-        }
-        __syncthreads();  // B3
-
-        // ---- R: delta'(u, r) and delta'(u, s) under p' for every u
-        {
-            const int qF = 0, qFT = sym ? 0 : 1, qD = 2, qDT = sym ? 2 : 3;
-            for (int u = t; u < n; u += L) {
-                int rr, rsv;
-                if (u == r) {
-                    rr = BIG;
-                    rsv = -dstar;
-                } else if (u == s) {
-                    rr = -dstar;
-                    rsv = BIG;
-                } else {
-                    const int pa = perm[u];
-                    const int daa = Dm[u * rs + u];
-                    const int gaa = Fm[pa * rs + pa];
-                    const int rdu = RD[u], cdu = CD[u];
-                    const int2 p1 = P[qF * np + u], p3 = P[qFT * np + u];
-                    const int2 p2 = P[qD * np + u], p4 = P[qDT * np + u];
-                    int res[2];
-#pragma unroll
-                    for (int side = 0; side < 2; ++side) {
-                        const int bb = side ? s : r;
-                        const int pb = perm[bb];
-                        const int P1 = side ? p1.y : p1.x, P3 = side ? p3.y : p3.x;
-                        const int P2 = side ? p2.y : p2.x, P4 = side ? p4.y : p4.x;
-                        const int2 rdb2 = P[qD * np + bb], cdb2 = P[qDT * np + bb];
-                        const int rdb = side ? rdb2.y : rdb2.x, cdb = side ? cdb2.y : cdb2.x;
-                        const int dbb = Dm[bb * rs + bb], dab = Dm[u * rs + bb], dba = Dm[bb * rs + u];
-                        const int gbb = Fm[pb * rs + pb], gab = Fm[pa * rs + pb], gba = Fm[pb * rs + pa];
-                        const int srow = P1 - rdb - rdu + P2;
-                        const int scol = P3 - cdb - cdu + P4;
-                        const int rowex = (dba - daa) * (gaa - gba) + (dbb - dab) * (gab - gbb);
-                        const int colex = (dab - daa) * (gaa - gab) + (dbb - dba) * (gba - gbb);
-                        res[side] = srow + scol - rowex - colex + (dbb - daa) * (gaa - gbb)
-                                  + (dba - dab) * (gab - gba);
-                    }
-                    rr = res[0];
-                    rsv = res[1];
-                }
-                R[u] = make_int2(rr, rsv);
-            }
-            if (t == 0) {
-                RD[r] = P[qD * np + r].x;
-                RD[s] = P[qD * np + s].y;
-                CD[r] = P[qDT * np + r].x;
-                CD[s] = P[qDT * np + s].y;
-            }
-        }
-        __syncthreads();  // B4
-
-        // ---- C: update this lane's tile
+        // ---- C: the tile follows the move
         if (active) {
+            const int2 kk = *reinterpret_cast<const int2 *>(kc);
+            const int kr = kk.x, ks = kk.y;
             int acu[ROWS], beu[ROWS], acv[4], bev[4];
+            {
+                const int4 c01 = reinterpret_cast<const int4 *>(acbe + 2 * v0)[0];
+                const int4 c23 = reinterpret_cast<const int4 *>(acbe + 2 * v0)[1];
+                acv[0] = c01.x; bev[0] = c01.y; acv[1] = c01.z; bev[1] = c01.w;
+                acv[2] = c23.x; bev[2] = c23.y; acv[3] = c23.z; bev[3] = c23.w;
 #pragma unroll
-            for (int j = 0; j < ROWS; ++j) {
-                const int2 w = acbe[u0 + j];
-                acu[j] = w.x;
-                beu[j] = w.y;
+                for (int j = 0; j < ROWS; j += 2) {
+                    const int4 w = reinterpret_cast<const int4 *>(acbe + 2 * (u0 + j))[0];
+                    acu[j] = w.x; beu[j] = w.y; acu[j + 1] = w.z; beu[j + 1] = w.w;
+                }
             }
+            // recomputed deltas of rows/columns r and s at this tile's indices
+            const int4 rv = *reinterpret_cast<const int4 *>(rpr + v0);
+            const int4 sv = *reinterpret_cast<const int4 *>(rps + v0);
+            const int rprv[4] = {rv.x, rv.y, rv.z, rv.w}, rpsv[4] = {sv.x, sv.y, sv.z, sv.w};
+            int rpru[ROWS], rpsu[ROWS];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int2 w = acbe[v0 + e];
-                acv[e] = w.x;
-                bev[e] = w.y;
+            for (int j = 0; j < ROWS; j += 2) {
+                const int2 x2 = *reinterpret_cast<const int2 *>(rpr + u0 + j);
+                const int2 y2 = *reinterpret_cast<const int2 *>(rps + u0 + j);
+                rpru[j] = x2.x; rpru[j + 1] = x2.y;
+                rpsu[j] = y2.x; rpsu[j + 1] = y2.y;
             }
+            const int until = TABU ? it + ten[tpos] : 0;
 #pragma unroll
             for (int j = 0; j < ROWS; ++j) {
 #pragma unroll
@@ -381,30 +565,32 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
                     dl[j][e] = __builtin_amdgcn_sdot2(da, db, dl[j][e], false);
                 }
             }
-            const int rg = r / ROWS, sg = s / ROWS;
-            if (g == rg) {
+            // delta'(x, r) for x = r (a diagonal slot), x = s (the move undone), or another x
+            auto val_r = [&](int x, int raw) { return x == r ? BIG : (x == s ? -dstar : raw - kr); };
+            auto val_s = [&](int x, int raw) { return x == s ? BIG : (x == r ? -dstar : raw - ks); };
+            if (g == r / ROWS) {
                 const int jr = r - u0;
 #pragma unroll
                 for (int j = 0; j < ROWS; ++j)
                     if (j == jr) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) dl[j][e] = R[v0 + e].x;
+                        for (int e = 0; e < 4; ++e) dl[j][e] = val_r(v0 + e, rprv[e]);
                     }
             }
-            if (g == sg) {
+            if (g == s / ROWS) {
                 const int js = s - u0;
 #pragma unroll
                 for (int j = 0; j < ROWS; ++j)
                     if (j == js) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) dl[j][e] = R[v0 + e].y;
+                        for (int e = 0; e < 4; ++e) dl[j][e] = val_s(v0 + e, rpsv[e]);
                     }
             }
             if (b == (r >> 2)) {
                 const int er = r & 3;
 #pragma unroll
                 for (int j = 0; j < ROWS; ++j) {
-                    const int x = R[u0 + j].x;
+                    const int x = val_r(u0 + j, rpru[j]);
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         if (e == er) dl[j][e] = x;
@@ -414,27 +600,28 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
                 const int es = s & 3;
 #pragma unroll
                 for (int j = 0; j < ROWS; ++j) {
-                    const int x = R[u0 + j].y;
+                    const int x = val_s(u0 + j, rpsu[j]);
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         if (e == es) dl[j][e] = x;
                 }
             }
             if (TABU) {
-                const int until = it + ten[(it - 1) % L];
-                if (g == rg && b == (s >> 2)) {
+                // the move and its mirror become tabu until iteration it + t
+                const int ja = r - u0, ea = s - v0, jb = s - u0, eb = r - v0;
+                if ((unsigned)ja < (unsigned)ROWS && (unsigned)ea < 4u) {
 #pragma unroll
                     for (int j = 0; j < ROWS; ++j)
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
-                            if (j == r - u0 && e == (s & 3)) ut[j][e] = until;
+                            if (j == ja && e == ea) ut[j][e] = until;
                 }
-                if (g == sg && b == (r >> 2)) {
+                if ((unsigned)jb < (unsigned)ROWS && (unsigned)eb < 4u) {
 #pragma unroll
                     for (int j = 0; j < ROWS; ++j)
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
-                            if (j == s - u0 && e == (r & 3)) ut[j][e] = until;
+                            if (j == jb && e == eb) ut[j][e] = until;
                 }
             }
             if (boundary) {
@@ -445,6 +632,7 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
                         if (u0 + j >= n || v0 + e >= n) dl[j][e] = BIG;
             }
         }
+        if (TABU && ++tpos == L) tpos = 0;
         if (TABU) ++it; else ++steps;
     }
 
@@ -466,7 +654,24 @@ hipError_t launch_one(const SearchArgs &a, int grid, int lanes, size_t smem, hip
 
 }  // namespace
 
-int search_max_lanes(int rows) { return rows <= 4 ? max_lanes<2>() : max_lanes<8>(); }
+int search_max_lanes(int rows) { return rows <= 2 ? max_lanes<2>() : (rows <= 8 ? max_lanes<8>() : max_lanes<16>()); }
+
+// Block size for a tile shape: at least one lane per tile; one lane per (index, family)
+// task when the workgroup limit allows, else up to MAXT tasks per lane.  Returns 0 when
+// the shape cannot serve n.
+int search_lanes(int n, int rows, int ntiles, int sym) {
+    const int maxl = search_max_lanes(rows);
+    const int tasks = families(sym) * n;
+    int lanes = (ntiles + 63) / 64 * 64;
+    if (lanes < 64) lanes = 64;
+    if (lanes > maxl) return 0;
+    const int want = (tasks + 63) / 64 * 64;
+    if (want > lanes) lanes = want < maxl ? want : maxl;
+    const int maxt = 1024 / maxl;
+    const int need = ((tasks + maxt - 1) / maxt + 63) / 64 * 64;
+    if (need > lanes) lanes = need;
+    return lanes <= maxl ? lanes : 0;
+}
 
 size_t search_smem_bytes(int n, int rows, int lanes, int sym) {
     return (size_t)smem_plan(n, padded_n(n, rows), lanes, sym).total;
