@@ -20,8 +20,10 @@ constexpr int TILE_COLS = 4;   // columns of the register tile held by one lane
 // decreases, so this only bounds a run on inconsistent data).
 constexpr int TWO_OPT_MAX_MOVES = 1 << 20;
 
-// Rows are padded to RS bytes (a multiple of 16) so every row starts 16-byte aligned.
-__host__ __device__ inline int row_stride(int n) { return (n + 15) & ~15; }
+// Rows are padded to RS bytes, an odd multiple of 16: every row starts 16-byte aligned,
+// and 16 consecutive rows start in 16 different groups of four LDS banks, so the
+// 16-byte row reads of a wave (one row per index) do not collide.
+__host__ __device__ inline int row_stride(int n) { return (((n + 15) >> 4) | 1) << 4; }
 
 // Number of indices (locations or units) addressable by a tile of `rows` x 4.
 __host__ __device__ inline int padded_n(int n, int rows) {
@@ -48,10 +50,11 @@ __host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym) {
     Smem s;
     int o = 0;
     auto take = [&o](int bytes) { int at = o; o += (bytes + 15) & ~15; return at; };
-    s.d = take(n * rs);
-    s.dt = sym ? s.d : take(n * rs);
-    s.g = take(n * rs);
-    s.gt = sym ? s.g : take(n * rs);
+    auto take_mat = [&o]() { o = (o + 255) & ~255; return o; };   // matrices start on 256-byte boundaries
+    s.d = take_mat(); o += n * rs;
+    s.dt = sym ? s.d : take_mat(); if (!sym) o += n * rs;
+    s.g = take_mat(); o += n * rs;
+    s.gt = sym ? s.g : take_mat(); if (!sym) o += n * rs;
     s.acbe = take(np * 8);
     s.rpr = take(np * 4);
     s.rps = take(np * 4);

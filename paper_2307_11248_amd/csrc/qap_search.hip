@@ -136,14 +136,21 @@ __device__ inline unsigned dot_rows(const uint8_t *a, const uint8_t *b, int rs) 
     return acc;
 }
 
-// Two dot products sharing the row `a`.
+// Two dot products sharing the row `a`, over rows of rs bytes (a multiple of 16); the
+// loads of the next 16-byte column block are issued before the current one is used.
 __device__ inline void dot_rows2(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
                                  unsigned &o2) {
     unsigned c1 = 0, c2 = 0;
-    for (int w = 0; w < rs; w += 16) {
-        const uint4 x = *reinterpret_cast<const uint4 *>(a + w);
-        const uint4 y = *reinterpret_cast<const uint4 *>(b1 + w);
-        const uint4 z = *reinterpret_cast<const uint4 *>(b2 + w);
+    uint4 x = *reinterpret_cast<const uint4 *>(a);
+    uint4 y = *reinterpret_cast<const uint4 *>(b1);
+    uint4 z = *reinterpret_cast<const uint4 *>(b2);
+    for (int w = 16; w <= rs; w += 16) {
+        uint4 xn = x, yn = y, zn = z;
+        if (w < rs) {
+            xn = *reinterpret_cast<const uint4 *>(a + w);
+            yn = *reinterpret_cast<const uint4 *>(b1 + w);
+            zn = *reinterpret_cast<const uint4 *>(b2 + w);
+        }
         c1 = __builtin_amdgcn_udot4(x.x, y.x, c1, false);
         c1 = __builtin_amdgcn_udot4(x.y, y.y, c1, false);
         c1 = __builtin_amdgcn_udot4(x.z, y.z, c1, false);
@@ -152,6 +159,9 @@ __device__ inline void dot_rows2(const uint8_t *a, const uint8_t *b1, const uint
         c2 = __builtin_amdgcn_udot4(x.y, z.y, c2, false);
         c2 = __builtin_amdgcn_udot4(x.z, z.z, c2, false);
         c2 = __builtin_amdgcn_udot4(x.w, z.w, c2, false);
+        x = xn;
+        y = yn;
+        z = zn;
     }
     o1 = c1;
     o2 = c2;
@@ -302,6 +312,7 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
             }
         }
     }
+    if (t >= W && t < 16) red[t] = LLONG_MAX;   // unused wave-minimum slots
     const long long start_id = a.start_base + job;
     int it = 1, steps = 0, tpos = 0;   // tpos = (it - 1) mod L, the tenure ring slot
     __syncthreads();
@@ -333,20 +344,37 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
         const long long kw = wave_min64(((long long)bd << 32) | (unsigned)key);
         if (lane == 0) red[wid] = kw;
         __syncthreads();  // B1
-        long long mk = red[0];
-        for (int w = 1; w < W; ++w) {
-            const long long o = red[w];
-            mk = o < mk ? o : mk;
+        // workgroup minimum: the W wave minima, two per 16-byte load (slots past W hold
+        // the largest key)
+        long long mk = LLONG_MAX;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            if (2 * p < W) {
+                const longlong2 o = reinterpret_cast<const longlong2 *>(red)[p];
+                mk = o.x < mk ? o.x : mk;
+                mk = o.y < mk ? o.y : mk;
+            }
         }
-        const int dstar = (int)(mk >> 32);
+        // the winner is the same in every lane: keep it in scalar registers
+        const int dstar = __builtin_amdgcn_readfirstlane((int)(mk >> 32));
         if (TABU ? (dstar == INT32_MAX) : (dstar >= 0)) break;
-        const int kstar = (int)(mk & 0xffffffffLL);
-        int r = kstar >> 9, s = kstar & 511;
-        if (r > s) { const int tmp = r; r = s; s = tmp; }
+        const int kstar = __builtin_amdgcn_readfirstlane((int)(mk & 0xffffffffLL));
+        const int r = min(kstar >> 9, kstar & 511), s = max(kstar >> 9, kstar & 511);
         const bool improved = TABU && (cur + dstar < best);
         cur += dstar;
         if (improved) best = cur;
 
+        // words of rows r and s of G and G^T for the exchange in C (read now, G is not
+        // written before B2); lanes 0 .. RS/4-1 of wave 0, which all hold task 0
+        const bool swap_lane = wid == 0 && lane < rs / 4;
+        unsigned sw_r = 0, sw_s = 0, swt_r = 0, swt_s = 0;
+        int sw_grr = 0, sw_grs = 0, sw_gsr = 0, sw_gss = 0;
+        if (swap_lane) {
+            sw_r = reinterpret_cast<const unsigned *>(Gm + r * rs)[lane];
+            sw_s = reinterpret_cast<const unsigned *>(Gm + s * rs)[lane];
+            swt_r = reinterpret_cast<const unsigned *>(GmT + r * rs)[lane];
+            swt_s = reinterpret_cast<const unsigned *>(GmT + s * rs)[lane];
+        }
         // ---- X: one (u, family) task per lane: the update vectors of u, and the deltas
         //      of (u, r) and (u, s) under p'
         int colw_addr[MAXT], colw_val[MAXT];
@@ -391,40 +419,35 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
             const int g_ru = byte_at(rgt_, 0), g_su = byte_at(rgt_, 1);
             const int D_sr = sym ? D_rs : byte_at(rdt_, 2), D_ss = sym ? (int)exd : byte_at(rdt_, 3);
             const int G_sr = sym ? G_rs : byte_at(rgt_, 2), G_ss = sym ? (int)exg : byte_at(rgt_, 3);
-
-            // dot products with the O(1) correction sum_k a[sigma k] c[k] = a.c + (a_s - a_r)(c_r - c_s)
-            unsigned d1, d2;
-            int x, y;
-            if (f < 2) {
-                // sum_k G'[u][k] D[b][k] (f = 0), sum_k G'[k][u] D[k][b] (f = 1)
-                const uint8_t *ga = ((f & 1) ? GmT : Gm) + su * rs;
-                const uint8_t *c1 = ((f & 1) ? DmT : Dm) + r * rs, *c2 = ((f & 1) ? DmT : Dm) + s * rs;
-                dot_rows2(ga, c1, c2, rs, d1, d2);
-                int as_, ar_;
-                if (f == 0) {
-                    as_ = u == r ? G_ss : (u == s ? G_rs : g_us);
-                    ar_ = u == r ? G_sr : (u == s ? G_rr : g_ur);
-                    x = (int)d1 + (as_ - ar_) * (D_rr - D_rs);
-                    y = (int)d2 + (as_ - ar_) * (D_sr - D_ss);
-                } else {
-                    as_ = u == r ? G_ss : (u == s ? G_sr : g_su);
-                    ar_ = u == r ? G_rs : (u == s ? G_rr : g_ru);
-                    x = (int)d1 + (as_ - ar_) * (D_rr - D_sr);
-                    y = (int)d2 + (as_ - ar_) * (D_rs - D_ss);
-                }
-            } else {
-                // sum_k D[u][k] G'[b][k] (f = 2), sum_k D[k][u] G'[k][b] (f = 3)
-                const uint8_t *dc = ((f & 1) ? DmT : Dm) + u * rs;
-                const uint8_t *g1 = ((f & 1) ? GmT : Gm) + s * rs, *g2 = ((f & 1) ? GmT : Gm) + r * rs;
-                dot_rows2(dc, g1, g2, rs, d1, d2);
-                if (f == 2) {
-                    x = (int)d1 + (G_ss - G_sr) * (d_ur - d_us);
-                    y = (int)d2 + (G_rs - G_rr) * (d_ur - d_us);
-                } else {
-                    x = (int)d1 + (G_ss - G_rs) * (d_ru - d_su);
-                    y = (int)d2 + (G_sr - G_rr) * (d_ru - d_su);
-                }
+            if (i == 0) {
+                sw_grr = G_rr;
+                sw_grs = G_rs;
+                sw_gsr = G_sr;
+                sw_gss = G_ss;
             }
+
+            // dot products with the O(1) correction sum_k a[sigma k] c[k] = a.c + (a_s - a_r)(c_r - c_s),
+            // a a row of G or G^T, c a row of D or D^T:
+            //   f = 0: sum_k G'[u][k] D[b][k]    a = G[sigma u],   c = D[b]
+            //   f = 1: sum_k G'[k][u] D[k][b]    a = G^T[sigma u], c = D^T[b]
+            //   f = 2: sum_k D[u][k] G'[b][k]    a = G[sigma b],   c = D[u]
+            //   f = 3: sum_k D[k][u] G'[k][b]    a = G^T[sigma b], c = D^T[u]
+            // One loop for every family: the row shared by both sides first, then the side rows.
+            const uint8_t *Gf = (f & 1) ? GmT : Gm, *Df = (f & 1) ? DmT : Dm;
+            const uint8_t *shared = f < 2 ? Gf + su * rs : Df + u * rs;
+            const uint8_t *side1 = f < 2 ? Df + r * rs : Gf + s * rs;
+            const uint8_t *side2 = f < 2 ? Df + s * rs : Gf + r * rs;
+            unsigned d1, d2;
+            dot_rows2(shared, side1, side2, rs, d1, d2);
+            // (a_s - a_r) and (c_r - c_s) for the sides r and s, chosen without branches
+            const int a0 = (u == r ? G_ss : (u == s ? G_rs : g_us)) - (u == r ? G_sr : (u == s ? G_rr : g_ur));
+            const int a1 = (u == r ? G_ss : (u == s ? G_sr : g_su)) - (u == r ? G_rs : (u == s ? G_rr : g_ru));
+            const int ar1 = f == 0 ? a0 : (f == 1 ? a1 : (f == 2 ? G_ss - G_sr : G_ss - G_rs));
+            const int ar2 = f == 0 ? a0 : (f == 1 ? a1 : (f == 2 ? G_rs - G_rr : G_sr - G_rr));
+            const int cr1 = f == 0 ? D_rr - D_rs : (f == 1 ? D_rr - D_sr : (f == 2 ? d_ur - d_us : d_ru - d_su));
+            const int cr2 = f == 0 ? D_sr - D_ss : (f == 1 ? D_rs - D_ss : (f == 2 ? d_ur - d_us : d_ru - d_su));
+            const int x = (int)d1 + ar1 * cr1;
+            const int y = (int)d2 + ar2 * cr2;
             // the four families of u (two when symmetric), shared inside the quad
             int xf[4], yf[4];
             if (sym) {
@@ -453,9 +476,19 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
             }
             rdv[i] = rdn;
             cdv[i] = cdn;
-            if (q == 0) {
-                reinterpret_cast<int2 *>(acbe)[u] = make_int2(pack16(A, C), pack16(B, E));
-                if (u == r || u == s) kc[u == r ? 0 : 1] = rdn + cdn;
+            if (q == 0) reinterpret_cast<int2 *>(acbe)[u] = make_int2(pack16(A, C), pack16(B, E));
+            if (u == r || u == s) {
+                // K_b = RD'_b + CD'_b; every recomputed entry is stored as delta' + K_b, so
+                // the tiles subtract K_b alone: here delta'(b, b) = BIG (a diagonal slot)
+                // and delta'(r, s) = -dstar (the move undone)
+                const int kb = rdn + cdn;
+                int *rb = u == r ? rpr : rps;
+                if (q == 0) {
+                    kc[u == r ? 0 : 1] = kb;
+                    rb[u] = BIG + kb;
+                } else if (q == 1) {
+                    rb[u == r ? s : r] = kb - dstar;
+                }
             }
             if (q < 2 && u != r && u != s) {
                 // delta'(u, b) + RD'_b + CD'_b for b = r (q == 0) or b = s (q == 1)
@@ -491,32 +524,31 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
         __syncthreads();  // B2
 
         // ---- C: G, G^T and p follow the move
-        if (wid == 0 && lane < rs / 4) {
-            // rows r and s exchange, with their entries at columns r and s exchanged; one
-            // wave does both rows so every read precedes every write
+        if (swap_lane) {
+            // rows r and s exchange, with their entries at columns r and s exchanged
             const int wr = lane;
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                if (side == 1 && sym) break;
-                uint8_t *Gx = side ? GmT : Gm;
-                const unsigned grr = Gx[r * rs + r], grs = Gx[r * rs + s];
-                const unsigned gsr = Gx[s * rs + r], gss = Gx[s * rs + s];
-                const unsigned xr = reinterpret_cast<unsigned *>(Gx + r * rs)[wr];
-                const unsigned xs = reinterpret_cast<unsigned *>(Gx + s * rs)[wr];
-                unsigned nr = xs, ns = xr;
-                if ((r >> 2) == wr) {
-                    const int sh = 8 * (r & 3);
-                    nr = (nr & ~(0xffu << sh)) | (gss << sh);
-                    ns = (ns & ~(0xffu << sh)) | (grs << sh);
-                }
-                if ((s >> 2) == wr) {
-                    const int sh = 8 * (s & 3);
-                    nr = (nr & ~(0xffu << sh)) | (gsr << sh);
-                    ns = (ns & ~(0xffu << sh)) | (grr << sh);
-                }
-                __builtin_amdgcn_wave_barrier();
-                reinterpret_cast<unsigned *>(Gx + r * rs)[wr] = nr;
-                reinterpret_cast<unsigned *>(Gx + s * rs)[wr] = ns;
+            unsigned nr = sw_s, ns = sw_r, nrt = swt_s, nst = swt_r;
+            if ((r >> 2) == wr) {
+                const int sh = 8 * (r & 3);
+                const unsigned m = ~(0xffu << sh);
+                nr = (nr & m) | ((unsigned)sw_gss << sh);
+                ns = (ns & m) | ((unsigned)sw_grs << sh);
+                nrt = (nrt & m) | ((unsigned)sw_gss << sh);
+                nst = (nst & m) | ((unsigned)sw_gsr << sh);
+            }
+            if ((s >> 2) == wr) {
+                const int sh = 8 * (s & 3);
+                const unsigned m = ~(0xffu << sh);
+                nr = (nr & m) | ((unsigned)sw_gsr << sh);
+                ns = (ns & m) | ((unsigned)sw_grr << sh);
+                nrt = (nrt & m) | ((unsigned)sw_grs << sh);
+                nst = (nst & m) | ((unsigned)sw_grr << sh);
+            }
+            reinterpret_cast<unsigned *>(Gm + r * rs)[wr] = nr;
+            reinterpret_cast<unsigned *>(Gm + s * rs)[wr] = ns;
+            if (!sym) {
+                reinterpret_cast<unsigned *>(GmT + r * rs)[wr] = nrt;
+                reinterpret_cast<unsigned *>(GmT + s * rs)[wr] = nst;
             }
         }
 #pragma unroll
@@ -530,7 +562,7 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
         // ---- C: the tile follows the move
         if (active) {
             const int2 kk = *reinterpret_cast<const int2 *>(kc);
-            const int kr = kk.x, ks = kk.y;
+            const int kr = __builtin_amdgcn_readfirstlane(kk.x), ks = __builtin_amdgcn_readfirstlane(kk.y);
             int acu[ROWS], beu[ROWS], acv[4], bev[4];
             {
                 const int4 c01 = reinterpret_cast<const int4 *>(acbe + 2 * v0)[0];
@@ -543,10 +575,9 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
                     acu[j] = w.x; beu[j] = w.y; acu[j + 1] = w.z; beu[j + 1] = w.w;
                 }
             }
-            // recomputed deltas of rows/columns r and s at this tile's indices
+            // recomputed deltas of rows/columns r and s at this tile's indices (stored + K)
             const int4 rv = *reinterpret_cast<const int4 *>(rpr + v0);
             const int4 sv = *reinterpret_cast<const int4 *>(rps + v0);
-            const int rprv[4] = {rv.x, rv.y, rv.z, rv.w}, rpsv[4] = {sv.x, sv.y, sv.z, sv.w};
             int rpru[ROWS], rpsu[ROWS];
 #pragma unroll
             for (int j = 0; j < ROWS; j += 2) {
@@ -565,63 +596,58 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
                     dl[j][e] = __builtin_amdgcn_sdot2(da, db, dl[j][e], false);
                 }
             }
-            // delta'(x, r) for x = r (a diagonal slot), x = s (the move undone), or another x
-            auto val_r = [&](int x, int raw) { return x == r ? BIG : (x == s ? -dstar : raw - kr); };
-            auto val_s = [&](int x, int raw) { return x == s ? BIG : (x == r ? -dstar : raw - ks); };
+            // the rows and columns of r and s; the row/column inside the tile is the same for
+            // every lane that holds it, so the slot choice is a scalar branch
+            const int jr = r % ROWS, js = s % ROWS, er = r & 3, es = s & 3;
             if (g == r / ROWS) {
-                const int jr = r - u0;
+                const int vr[4] = {rv.x - kr, rv.y - kr, rv.z - kr, rv.w - kr};
 #pragma unroll
                 for (int j = 0; j < ROWS; ++j)
                     if (j == jr) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) dl[j][e] = val_r(v0 + e, rprv[e]);
+                        for (int e = 0; e < 4; ++e) dl[j][e] = vr[e];
                     }
             }
             if (g == s / ROWS) {
-                const int js = s - u0;
+                const int vs[4] = {sv.x - ks, sv.y - ks, sv.z - ks, sv.w - ks};
 #pragma unroll
                 for (int j = 0; j < ROWS; ++j)
                     if (j == js) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) dl[j][e] = val_s(v0 + e, rpsv[e]);
+                        for (int e = 0; e < 4; ++e) dl[j][e] = vs[e];
                     }
             }
             if (b == (r >> 2)) {
-                const int er = r & 3;
 #pragma unroll
-                for (int j = 0; j < ROWS; ++j) {
-                    const int x = val_r(u0 + j, rpru[j]);
+                for (int e = 0; e < 4; ++e)
+                    if (e == er) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (e == er) dl[j][e] = x;
-                }
+                        for (int j = 0; j < ROWS; ++j) dl[j][e] = rpru[j] - kr;
+                    }
             }
             if (b == (s >> 2)) {
-                const int es = s & 3;
 #pragma unroll
-                for (int j = 0; j < ROWS; ++j) {
-                    const int x = val_s(u0 + j, rpsu[j]);
+                for (int e = 0; e < 4; ++e)
+                    if (e == es) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (e == es) dl[j][e] = x;
-                }
+                        for (int j = 0; j < ROWS; ++j) dl[j][e] = rpsu[j] - ks;
+                    }
             }
             if (TABU) {
                 // the move and its mirror become tabu until iteration it + t
-                const int ja = r - u0, ea = s - v0, jb = s - u0, eb = r - v0;
-                if ((unsigned)ja < (unsigned)ROWS && (unsigned)ea < 4u) {
+                if (g == r / ROWS && b == (s >> 2)) {
 #pragma unroll
                     for (int j = 0; j < ROWS; ++j)
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
-                            if (j == ja && e == ea) ut[j][e] = until;
+                            if (j == jr && e == es) ut[j][e] = until;
                 }
-                if ((unsigned)jb < (unsigned)ROWS && (unsigned)eb < 4u) {
+                if (g == s / ROWS && b == (r >> 2)) {
 #pragma unroll
                     for (int j = 0; j < ROWS; ++j)
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
-                            if (j == jb && e == eb) ut[j][e] = until;
+                            if (j == js && e == er) ut[j][e] = until;
                 }
             }
             if (boundary) {
