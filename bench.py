@@ -4,6 +4,9 @@
 A step is one pass of the whole hot path over one batch of starts that are already
 resident in HBM: reset the working permutations from the starts, build every start's
 neighbourhood table, then run every search to completion in one persistent launch.
+The uneven batch (--workload c4: 512 instances, n from 20 to 150) runs every start of
+every instance in one launch of the batched kernel; its step is a captured HIP graph
+(reset, tables, searches) replayed once per step.
 
 Prints one JSON line (see the keys below).  --gpus N with N > 1 is refused: this build
 runs on one GPU.
@@ -37,7 +40,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3-2opt", "c3-tabu"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3-2opt", "c3-tabu", "c4"])
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-start comparison")
@@ -55,6 +58,8 @@ def load_workload(name):
         return W.c2_dense64()
     if name == "c3-2opt":
         return W.c3_euclid128_2opt()
+    if name == "c4":
+        return W.c4_batch()
     return W.c3_euclid128_tabu()
 
 
@@ -90,6 +95,135 @@ def cpu_baseline(w, gpu_best, gpu_perm, nstarts):
                       % (len(idx), len(I.perms), dt)}, exact
 
 
+def cpu_baseline_batch(w, gpu_best, gpu_perm, sample):
+    """The oracle on a bounded sample of (instance, start) pairs of the uneven batch."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    insts = w.instances
+    k = len(insts[0].perms)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    off = np.concatenate([[0], np.cumsum([k * I.n for I in insts])])
+
+    def run(a):
+        t, j = a
+        I = insts[t]
+        lo, hi = w.tenure(I.n)
+        return oracle.tabu(I.F, I.D, I.perms[j], w.iters, lo, hi, I.seed, j)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        res = list(ex.map(run, sample))
+    dt = time.perf_counter() - t0
+    evals = sum(insts[t].n * (insts[t].n - 1) // 2 * (r[2] + 1) for (t, _), r in zip(sample, res))
+    exact = all((gpu_perm[off[t] + j * insts[t].n: off[t] + (j + 1) * insts[t].n] == r[0]).all()
+                and gpu_best[t * k + j] == r[1] for (t, j), r in zip(sample, res))
+    return {"value": evals / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": "%d (instance, start) pairs of the uneven batch, one start per instance spread over "
+                      "the batch, run to completion (%.1f s wall)" % (len(sample), dt)}, exact
+
+
+def run_batch(args, w):
+    import torch
+    from paper_2307_11248_amd import qap
+    insts = w.instances
+    m, k = len(insts), len(insts[0].perms)
+    hs = [qap.Handle(I.F, I.D) for I in insts]
+    lo = [w.tenure(I.n)[0] for I in insts]
+    hi = [w.tenure(I.n)[1] for I in insts]
+    seeds = [I.seed for I in insts]
+    b = qap.Batch(hs, [k] * m, w.iters, lo, hi, seeds)
+    stream = torch.cuda.Stream()
+    starts = torch.from_numpy(np.concatenate([I.perms.reshape(-1) for I in insts])).cuda()
+    work = torch.empty_like(starts)
+    best = torch.empty(m * k, dtype=torch.int64, device="cuda")
+    done = torch.empty(m * k, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+
+    # kernel durations: the same three launches, eagerly, bracketed by events on their stream
+    ev = []
+    for rep in range(args.warmup + args.steps):
+        with torch.cuda.stream(stream):
+            work.copy_(starts)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            b.tables_async(work, stream=stream)
+            e[1].record(stream)
+            b.search_async(work, best, done, stream=stream)
+            e[2].record(stream)
+        if rep >= args.warmup:
+            ev.append(e)
+    torch.cuda.synchronize()
+    table_ms = float(np.mean([a.elapsed_time(c) for a, c, _ in ev]))
+    search_ms = float(np.mean([c.elapsed_time(d) for _, c, d in ev]))
+    eager_p, eager_c = work.cpu().numpy(), best.cpu().numpy()
+
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        work.copy_(starts)
+        b.run_async(work, best, done, stream=stream)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    gpu_perm, gpu_best = work.cpu().numpy(), best.cpu().numpy()
+    moves = done.cpu().numpy().astype(np.int64)
+    assert (gpu_perm == eager_p).all() and (gpu_best == eager_c).all(), "graph replay differs from eager run"
+    ms = np.repeat([I.n * (I.n - 1) // 2 for I in insts], k).astype(np.int64)
+    off = np.concatenate([[0], np.cumsum([k * I.n for I in insts])])
+    for t, I in enumerate(insts):
+        assert (hs[t].cost(gpu_perm[off[t]:off[t + 1]].reshape(k, I.n)) == gpu_best[t * k:(t + 1) * k]).all()
+    evals_step = int((ms * (moves + 1)).sum())
+    search_evals = int((ms * moves).sum())
+    value = evals_step / (ms_step / 1e3)
+    valu = VALU_PER_EVAL["tabu"] * search_evals / (search_ms / 1e3) / 1e12
+    roof = {"bound": "alu", "achieved": round(valu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s",
+            "frac": round(valu / PEAK_VALU_TOPS, 4), "traffic": None, "kernel": "batch_kernel",
+            "kernel_ms": round(search_ms, 4), "ops_per_eval": VALU_PER_EVAL["tabu"],
+            "hbm_equivalent": {"achieved": round(BYTES_PER_EVAL * search_evals / (search_ms / 1e3) / 1e9, 1),
+                               "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                               "frac": round(BYTES_PER_EVAL * search_evals / (search_ms / 1e3) / 1e9
+                                             / PEAK_HBM_GBS, 4)}}
+    ns = [I.n for I in insts]
+    out = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": w.name, "instances": m, "n_range": [min(ns), max(ns)], "starts_per_instance": k,
+                      "iters": w.iters, "tenure": "[0.9n, 1.1n]", "graph": True},
+           "solves_per_s": m * k / (ms_step / 1e3), "table_kernel_ms": table_ms, "roofline": roof}
+
+    if not args.no_plain:
+        # the same searches launched per instance (one launch of k blocks each)
+        pw = starts.clone()
+        pb = torch.empty(m * k, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for t, I in enumerate(insts):
+                hs[t].tabu_async(pw[off[t]:off[t + 1]].view(k, I.n), w.iters, lo[t], hi[t], I.seed,
+                                 pb[t * k:(t + 1) * k], None, stream=stream)
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t0
+        out["per_instance_launches"] = {
+            "solves_per_s": m * k / pdt, "speedup_batched": (m * k / (ms_step / 1e3)) / (m * k / pdt),
+            "identical_costs": bool((pb.cpu().numpy() == gpu_best).all() and (pw.cpu().numpy() == gpu_perm).all())}
+
+    if not args.no_cpu:
+        step = max(1, m // args.cpu_starts)
+        sample = [(t, t % k) for t in range(0, m, step)][:args.cpu_starts]
+        cb, exact = cpu_baseline_batch(w, gpu_best, gpu_perm, sample)
+        out["cpu_baseline"] = cb
+        out["bit_exact_sample"] = exact
+    b.close()
+    for h in hs:
+        h.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -109,6 +243,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": nbytes, "copy_calibration_bytes_written": nbytes}))
         return
     w = load_workload(args.workload)
+    if len(w.instances) > 1:
+        return run_batch(args, w)
     I = w.instances[0]
     n, k = I.n, len(I.perms)
     m = n * (n - 1) // 2

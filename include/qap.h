@@ -164,6 +164,42 @@ int qap_tabu_with_table_async(qap_handle h, int32_t *d_perms, const int32_t *d_t
                               int64_t start_base, int64_t *d_best, int32_t *d_done, void *stream);
 
 /*
+ * Batched tabu search over many instances of uneven n in one launch (the many starts
+ * of Secs. 4.4 and 5.2, delivered for many instances at once).  Instance i (handle
+ * hs[i], size n_i) runs k_per[i] starts with tenure range [lo_per[i], hi_per[i]] and
+ * seed seed_per[i], all for `iters` iterations; its start j uses start_id = j, so every
+ * result equals that of qap_tabu on the instance alone.  Starts and results are
+ * concatenated in instance order: starts (and best permutations) int32[sum k_i n_i],
+ * best costs int64[sum k_i], moves made int32[sum k_i].
+ * qap_batch_create plans the batch (tile shape per instance: rows_per[i], or NULL / 0
+ * for the library's choice; instances whose n no tile shape of the batched kernel
+ * serves give QAP_E_UNSUPPORTED) and owns its device descriptors and neighbourhood
+ * scratch until qap_batch_destroy.  qap_batch_run_async only enqueues kernels on
+ * `stream` (it allocates nothing, so it may be captured in a HIP graph); the plan may
+ * be run any number of times, one run at a time.  It is qap_batch_tables_async (every
+ * start's neighbourhood table, Eq. (2), into the plan's scratch) followed by
+ * qap_batch_search_async (every search, from those tables); the two halves may be
+ * enqueued separately, in that order, on one stream.  qap_batch_size reports the number
+ * of starts and of permutation entries.  qap_tabu_batch is the blocking host form (rows
+ * of perms are checked; QAP_E_NOT_PERM otherwise).  A device-side row that is not a
+ * permutation is left as it is, with best cost INT64_MIN and moves QAP_E_NOT_PERM.
+ */
+typedef struct qap_batch *qap_batch_handle;
+int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *k_per, int32_t iters,
+                     const int32_t *lo_per, const int32_t *hi_per, const uint64_t *seed_per,
+                     const int32_t *rows_per, qap_batch_handle *out);
+int qap_batch_size(qap_batch_handle b, int64_t *starts_out, int64_t *perm_ints_out);
+int qap_batch_run_async(qap_batch_handle b, int32_t *d_perms, int64_t *d_best, int32_t *d_done,
+                        void *stream);
+int qap_batch_tables_async(qap_batch_handle b, const int32_t *d_perms, void *stream);
+int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int64_t *d_best, int32_t *d_done,
+                           void *stream);
+int qap_batch_destroy(qap_batch_handle b);
+int qap_tabu_batch(const qap_handle *hs, int32_t m, int32_t *perms, const int32_t *k_per,
+                   int32_t iters, const int32_t *lo_per, const int32_t *hi_per,
+                   const uint64_t *seed_per, int64_t *best_out, int32_t *done_out);
+
+/*
  * Tile shape of the search kernels (the thread-configuration search of Sec. 5.2,
  * re-done for gfx950): each lane of a search's workgroup holds a block of `rows` x 4
  * neighbourhood entries in registers, rows in {2, 4, 8, 16}; 0 restores the library's

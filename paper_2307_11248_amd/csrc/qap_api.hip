@@ -170,7 +170,27 @@ int run_search(qap_ctx *h, int algo, int32_t *d_perms, int k, int iters, int lo,
     return dev_err(e);
 }
 
+// Tile shape of an instance in the batched kernel: the smallest of 2, 4, 8 rows that
+// fits its lanes and LDS.
+int batch_rows(const qap_ctx *h) {
+    for (int i = 0; i < 3; ++i) {
+        const TileSet &ts = h->tiles[i];
+        if (ts.d_tiles && batch_shape_ok(h->n, kRowsChoices[i], ts.ntiles, h->sym) &&
+            search_smem_bytes(h->n, kRowsChoices[i], BATCH_LANES, h->sym) <= h->max_smem)
+            return kRowsChoices[i];
+    }
+    return -1;
+}
+
 }  // namespace
+
+struct qap_batch {
+    int count = 0;                  // searches (items)
+    long long perm_ints = 0, table_ints = 0;
+    Item *d_items = nullptr;
+    int32_t *d_table = nullptr;
+    size_t smem = 0, table_smem = 0;
+};
 
 extern "C" {
 
@@ -419,3 +439,144 @@ int qap_tabu(qap_handle h, int32_t *perms, int32_t k, int32_t iters, int32_t lo,
 }
 
 }  // extern "C"
+
+// ---- batched tabu over many instances of uneven n
+
+extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *k_per, int32_t iters,
+                                const int32_t *lo_per, const int32_t *hi_per, const uint64_t *seed_per,
+                                const int32_t *rows_per, qap_batch_handle *out) {
+    if (!hs || !k_per || !lo_per || !hi_per || !seed_per || !out || m < 0 || iters < 0) return QAP_E_INVALID;
+    *out = nullptr;
+    std::vector<Item> items;
+    long long perm_off = 0, out_off = 0, table_off = 0;
+    size_t smem = 0, tsmem = 0;
+    for (int i = 0; i < m; ++i) {
+        qap_ctx *h = hs[i];
+        if (!h || k_per[i] < 0 || lo_per[i] < 0 || lo_per[i] > hi_per[i]) return QAP_E_INVALID;
+        int rows = rows_per && rows_per[i] > 0 ? rows_per[i] : batch_rows(h);
+        const int ri = rows_index(rows);
+        if (rows < 0 || ri < 0 || ri > 2 || !batch_shape_ok(h->n, rows, h->tiles[ri].ntiles, h->sym)) return QAP_E_UNSUPPORTED;
+        const size_t sm = search_smem_bytes(h->n, rows, BATCH_LANES, h->sym);
+        if (sm > h->max_smem) return QAP_E_UNSUPPORTED;
+        smem = std::max(smem, sm);
+        tsmem = std::max(tsmem, table_smem_bytes(h->n));
+        for (int j = 0; j < k_per[i]; ++j) {
+            Item it{};
+            it.mats = h->d_mats;
+            it.tiles = h->tiles[ri].d_tiles;
+            it.n = h->n;
+            it.m = h->m;
+            it.sym = h->sym;
+            it.ntiles = h->tiles[ri].ntiles;
+            it.ninterior = h->tiles[ri].ninterior;
+            it.rows = rows;
+            it.iters = iters;
+            it.lo = lo_per[i];
+            it.hi = hi_per[i];
+            it.seed = seed_per[i];
+            it.start_id = j;
+            it.perm_off = perm_off;
+            it.out_off = out_off;
+            it.table_off = table_off;
+            items.push_back(it);
+            perm_off += h->n;
+            out_off += 1;
+            table_off += h->m;
+        }
+    }
+    // longest first: the hardware starts blocks in index order
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
+        return (long long)a.n * a.n > (long long)b.n * b.n;
+    });
+    qap_batch *b = new (std::nothrow) qap_batch;
+    if (!b) return QAP_E_NOMEM;
+    b->count = (int)items.size();
+    b->perm_ints = perm_off;
+    b->table_ints = table_off;
+    b->smem = smem;
+    b->table_smem = tsmem;
+    hipError_t e = hipSuccess;
+    if (b->count > 0) {
+        e = hipMalloc((void **)&b->d_items, items.size() * sizeof(Item));
+        if (e == hipSuccess) e = hipMalloc((void **)&b->d_table, (size_t)table_off * sizeof(int32_t) + 16);
+        if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        qap_batch_destroy(b);
+        return dev_err(e);
+    }
+    *out = b;
+    return QAP_OK;
+}
+
+extern "C" int qap_batch_size(qap_batch_handle b, int64_t *starts_out, int64_t *perm_ints_out) {
+    if (!b) return QAP_E_INVALID;
+    if (starts_out) *starts_out = b->count;
+    if (perm_ints_out) *perm_ints_out = b->perm_ints;
+    return QAP_OK;
+}
+
+extern "C" int qap_batch_tables_async(qap_batch_handle b, const int32_t *d_perms, void *stream) {
+    if (!b || (b->count > 0 && !d_perms)) return QAP_E_INVALID;
+    if (b->count == 0) return QAP_OK;
+    BatchArgs a{b->d_items, b->count, const_cast<int32_t *>(d_perms), nullptr, nullptr, b->d_table};
+    return dev_err(launch_table_batch(a, b->table_smem, (hipStream_t)stream));
+}
+
+extern "C" int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int64_t *d_best, int32_t *d_done,
+                                      void *stream) {
+    if (!b || (b->count > 0 && (!d_perms || !d_best))) return QAP_E_INVALID;
+    if (b->count == 0) return QAP_OK;
+    BatchArgs a{b->d_items, b->count, d_perms, d_best, d_done, b->d_table};
+    return dev_err(launch_batch(a, b->smem, (hipStream_t)stream));
+}
+
+extern "C" int qap_batch_run_async(qap_batch_handle b, int32_t *d_perms, int64_t *d_best, int32_t *d_done,
+                                   void *stream) {
+    int rc = qap_batch_tables_async(b, d_perms, stream);
+    return rc == QAP_OK ? qap_batch_search_async(b, d_perms, d_best, d_done, stream) : rc;
+}
+
+extern "C" int qap_batch_destroy(qap_batch_handle b) {
+    if (!b) return QAP_OK;
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_table) (void)hipFree(b->d_table);
+    delete b;
+    return QAP_OK;
+}
+
+extern "C" int qap_tabu_batch(const qap_handle *hs, int32_t m, int32_t *perms, const int32_t *k_per, int32_t iters,
+                              const int32_t *lo_per, const int32_t *hi_per, const uint64_t *seed_per,
+                              int64_t *best_out, int32_t *done_out) {
+    if (!hs || !k_per || (m > 0 && (!perms || !best_out))) return QAP_E_INVALID;
+    long long off = 0;
+    for (int i = 0; i < m; ++i) {
+        if (!hs[i] || k_per[i] < 0) return QAP_E_INVALID;
+        if (!check_perms(perms + off, k_per[i], hs[i]->n)) return QAP_E_NOT_PERM;
+        off += (long long)k_per[i] * hs[i]->n;
+    }
+    qap_batch_handle b = nullptr;
+    int rc = qap_batch_create(hs, m, k_per, iters, lo_per, hi_per, seed_per, nullptr, &b);
+    if (rc != QAP_OK) return rc;
+    HostCall c;
+    DevBuf dp, db, dd;
+    hipError_t e = c.init();
+    if (e == hipSuccess) e = dp.alloc((size_t)b->perm_ints * 4);
+    if (e == hipSuccess) e = db.alloc((size_t)b->count * 8);
+    if (e == hipSuccess) e = dd.alloc((size_t)b->count * 4);
+    if (e == hipSuccess && b->count > 0)
+        e = hipMemcpyAsync(dp.p, perms, (size_t)b->perm_ints * 4, hipMemcpyHostToDevice, c.st);
+    if (e == hipSuccess) {
+        rc = qap_batch_run_async(b, (int32_t *)dp.p, (int64_t *)db.p, (int32_t *)dd.p, c.st);
+        if (rc == QAP_OK && b->count > 0) {
+            e = hipMemcpyAsync(perms, dp.p, (size_t)b->perm_ints * 4, hipMemcpyDeviceToHost, c.st);
+            if (e == hipSuccess) e = hipMemcpyAsync(best_out, db.p, (size_t)b->count * 8, hipMemcpyDeviceToHost, c.st);
+            if (e == hipSuccess && done_out)
+                e = hipMemcpyAsync(done_out, dd.p, (size_t)b->count * 4, hipMemcpyDeviceToHost, c.st);
+            if (e == hipSuccess) e = hipStreamSynchronize(c.st);
+        }
+    }
+    qap_batch_destroy(b);
+    if (rc != QAP_OK) return rc;
+    return dev_err(e);
+}

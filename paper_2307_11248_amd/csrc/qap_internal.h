@@ -115,12 +115,63 @@ inline size_t max_dyn_smem() {
     return (size_t)v;
 }
 
+// Saved state of a search run in chunks of iterations (serving).  The arrays it
+// refers to live beside it in device memory: the current and the best permutation (n
+// each) and, in packed move order, the deltas of the current permutation and the
+// iteration at which each move becomes free again (m each).
+struct SearchState {
+    long long cur, best;
+    int it;      // next iteration to run, 1-based; 1 = not started
+    int done;    // 1 once the last iteration ran or no move was allowed
+    int moves;   // moves made so far
+    int pad;
+};
+
+// One search as the search kernels see it.
+struct Item {
+    const uint8_t *mats;      // global [F | F^T | D | D^T] of the instance
+    const int32_t *tiles;     // lane -> tile for the item's tile shape
+    const int32_t *table;     // neighbourhood of the start (read when the search starts)
+    const int32_t *perm_in;   // start permutation
+    int32_t *perm_out;        // best (tabu) or final (2opt) permutation, written when finished
+    int64_t *cost_out;        // its cost
+    int32_t *steps_out;       // moves made, or null
+    SearchState *st;          // null: run from the start to `iters` in one go
+    int32_t *st_perm, *st_bestp, *st_table, *st_until;
+    int n, m, sym, ntiles, ninterior, rows;
+    int iters;                // tabu: last iteration of this run; 2opt: move cap (<= 0: none)
+    int lo, hi;
+    unsigned long long seed;
+    long long start_id;
+    // batched launches: offsets of this item's start / result / neighbourhood in the
+    // launch's buffers (the pointers above are filled from them on the device)
+    long long perm_off, out_off, table_off;
+};
+
+// The batched launch: one block per item of `items`; per-start buffers are shared by
+// all items and addressed through the items' offsets.
+struct BatchArgs {
+    const Item *items;
+    int count;
+    int32_t *perms;    // starts in, best permutations out
+    int64_t *best;
+    int32_t *done;     // or null
+    int32_t *table;    // neighbourhood of every start
+};
+
 hipError_t launch_cost(const TableArgs &a, hipStream_t st);
 hipError_t launch_table(const TableArgs &a, hipStream_t st);
+// Neighbourhood tables of all items of a batch, one block per item.
+hipError_t launch_table_batch(const BatchArgs &b, size_t smem, hipStream_t st);
+size_t table_smem_bytes(int n);
 // rows in {2, 4, 8, 16}; grid = number of searches in this launch; lanes = block size.
 hipError_t launch_search(int rows, bool tabu, const SearchArgs &a, int grid, int lanes,
                          hipStream_t st);
 size_t search_smem_bytes(int n, int rows, int lanes, int sym);
+// Lanes of the persistent batched kernel, and whether a tile shape can serve n there.
+constexpr int BATCH_LANES = 512;
+int batch_shape_ok(int n, int rows, int ntiles, int sym);
+hipError_t launch_batch(const BatchArgs &b, size_t smem, hipStream_t st);
 int search_max_lanes(int rows);
 // Lanes of a search workgroup for a tile shape, or 0 if the shape cannot serve n.
 int search_lanes(int n, int rows, int ntiles, int sym);

@@ -181,18 +181,20 @@ __device__ inline void row_bytes(const uint8_t *row, int u0, unsigned (&w)[(ROWS
     }
 }
 
-template <int ROWS, bool TABU>
-__global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a) {
-    extern __shared__ __align__(16) unsigned char sm[];
+// One whole search (or one chunk of it) by the calling workgroup; every lane of the
+// block takes part.  MAXT: (index, family) tasks one lane may carry (blockDim.x * MAXT
+// >= families * n).
+template <int ROWS, bool TABU, int MAXT, bool RESUME>
+__device__ void search_body(const Item &a, unsigned char *sm) {
     __shared__ int s_bad;
     const int n = a.n, rs = row_stride(n), L = blockDim.x, t = threadIdx.x;
     const int lane = t & 63, wid = t >> 6, W = L >> 6;
-    const int job = a.job0 + blockIdx.x;
     const int sym = a.sym;
     const int nq = families(sym), lq = sym ? 1 : 2;
     const int np = padded_n(n, ROWS);
     const Smem S = smem_plan(n, np, L, sym);
-    constexpr int MAXT = max_tasks<ROWS>();
+    SearchState *const st = RESUME ? a.st : nullptr;   // saved state, chunked runs only
+    const bool resume = RESUME && st != nullptr && st->it > 1;
 
     uint8_t *Dm = sm + S.d, *DmT = sm + S.dt, *Gm = sm + S.g, *GmT = sm + S.gt;
     int *rpr = reinterpret_cast<int *>(sm + S.rpr);
@@ -217,21 +219,23 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
     if (t == 0) s_bad = 0;
     for (int u = t; u < np; u += L) pinv[u] = -1;
     __syncthreads();
-    const int32_t *pin = a.perms_in + (size_t)job * n;
+    const int32_t *pin = resume ? a.st_perm : a.perm_in;
     for (int u = t; u < n; u += L) {
         const int v = pin[u];
         perm[u] = v;
-        bestp[u] = v;
+        bestp[u] = resume ? a.st_bestp[u] : v;
         if (v < 0 || v >= n || atomicExch(&pinv[v], u) != -1) s_bad = 1;
     }
     __syncthreads();
     if (s_bad) {
-        if (a.perm_out != a.perms_in)
-            for (int u = t; u < n; u += L) a.perm_out[(size_t)job * n + u] = pin[u];
+        if (a.perm_out != a.perm_in)
+            for (int u = t; u < n; u += L) a.perm_out[u] = pin[u];
         if (t == 0) {
-            a.cost_out[job] = INT64_MIN;
-            if (a.steps_out) a.steps_out[job] = -2;  // QAP_E_NOT_PERM
+            *a.cost_out = INT64_MIN;
+            if (a.steps_out) *a.steps_out = -2;  // QAP_E_NOT_PERM
+            if (st) st->done = 1;
         }
+        __syncthreads();
         return;
     }
 
@@ -272,6 +276,7 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
     long long cur = 0;
     for (int w = 0; w < W; ++w) cur += red[w];
     long long best = cur;
+    if (resume) best = st->best;   // cur is recomputed from the saved permutation
     // per task: RD_u, CD_u, d_uu and g_uu of its u, kept in registers
     int rdv[MAXT], cdv[MAXT], duv[MAXT], guv[MAXT];
 #pragma unroll
@@ -300,21 +305,25 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
     int dl[ROWS][4];
     int ut[TABU ? ROWS : 1][4];
     {
-        const int32_t *tab = a.table + (size_t)job * a.m;
+        const int32_t *tab = resume ? a.st_table : a.table;
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int u = u0 + j, v = v0 + e;
                 const bool real = active && u < n && v < n && u != v;
-                dl[j][e] = real ? tab[pidx(n, u < v ? u : v, u < v ? v : u)] : BIG;
-                if (TABU) ut[j][e] = real ? 0 : INT32_MAX;
+                const long long ix = real ? pidx(n, u < v ? u : v, u < v ? v : u) : 0;
+                dl[j][e] = real ? tab[ix] : BIG;
+                if (TABU) ut[j][e] = real ? (resume ? a.st_until[ix] : 0) : INT32_MAX;
             }
         }
     }
     if (t >= W && t < 16) red[t] = LLONG_MAX;   // unused wave-minimum slots
-    const long long start_id = a.start_base + job;
-    int it = 1, steps = 0, tpos = 0;   // tpos = (it - 1) mod L, the tenure ring slot
+    const long long start_id = a.start_id;
+    int it = resume ? st->it : 1, steps = 0;
+    int tpos = (it - 1) % L;   // (it - 1) mod L, the tenure ring slot
+    if (TABU && tpos != 0) ten[t] = draw_tenure(a.seed, (long long)(it - tpos) + t, start_id, a.lo, a.hi);
+    bool stopped = false;
     __syncthreads();
 
     for (;;) {
@@ -357,7 +366,10 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
         }
         // the winner is the same in every lane: keep it in scalar registers
         const int dstar = __builtin_amdgcn_readfirstlane((int)(mk >> 32));
-        if (TABU ? (dstar == INT32_MAX) : (dstar >= 0)) break;
+        if (TABU ? (dstar == INT32_MAX) : (dstar >= 0)) {
+            stopped = true;
+            break;
+        }
         const int kstar = __builtin_amdgcn_readfirstlane((int)(mk & 0xffffffffLL));
         const int r = min(kstar >> 9, kstar & 511), s = max(kstar >> 9, kstar & 511);
         const bool improved = TABU && (cur + dstar < best);
@@ -664,11 +676,87 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
 
     // ---- results
     __syncthreads();
-    const int *res = TABU ? bestp : perm;
-    for (int u = t; u < n; u += L) a.perm_out[(size_t)job * n + u] = res[u];
-    if (t == 0) {
-        a.cost_out[job] = TABU ? best : cur;
-        if (a.steps_out) a.steps_out[job] = TABU ? it - 1 : steps;
+    const int moves = TABU ? it - 1 : steps;
+    const bool finished = st == nullptr || !TABU || stopped || it > a.iters;
+    if (st != nullptr) {
+        // save the search so a later run resumes it exactly where it stopped
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int u = u0 + j, v = v0 + e;
+                if (active && u < v && v < n) {
+                    const long long ix = pidx(n, u, v);
+                    a.st_table[ix] = dl[j][e];
+                    if (TABU) a.st_until[ix] = ut[j][e];
+                }
+            }
+        for (int u = t; u < n; u += L) {
+            a.st_perm[u] = perm[u];
+            a.st_bestp[u] = bestp[u];
+        }
+        if (t == 0) {
+            st->cur = cur;
+            st->best = best;
+            st->it = it;
+            st->moves = moves;
+            st->done = finished ? 1 : 0;
+        }
+    }
+    if (finished) {
+        const int *res = TABU ? bestp : perm;
+        for (int u = t; u < n; u += L) a.perm_out[u] = res[u];
+        if (t == 0) {
+            *a.cost_out = TABU ? best : cur;
+            if (a.steps_out) *a.steps_out = moves;
+        }
+    }
+    __syncthreads();
+}
+
+// One search per workgroup: block b runs search job0 + b of the launch.
+template <int ROWS, bool TABU>
+__global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    const int job = a.job0 + blockIdx.x;
+    Item it{};
+    it.mats = a.mats;
+    it.tiles = a.tiles;
+    it.table = a.table + (size_t)job * a.m;
+    it.perm_in = a.perms_in + (size_t)job * a.n;
+    it.perm_out = a.perm_out + (size_t)job * a.n;
+    it.cost_out = a.cost_out + job;
+    it.steps_out = a.steps_out ? a.steps_out + job : nullptr;
+    it.st = nullptr;
+    it.n = a.n;
+    it.m = a.m;
+    it.sym = a.sym;
+    it.ntiles = a.ntiles;
+    it.ninterior = a.ninterior;
+    it.rows = ROWS;
+    it.iters = a.iters;
+    it.lo = a.lo;
+    it.hi = a.hi;
+    it.seed = a.seed;
+    it.start_id = a.start_base + job;
+    search_body<ROWS, TABU, max_tasks<ROWS>(), false>(it, sm);
+}
+
+// The batched launch: block i runs item i as one tabu search with the item's tile
+// shape.  Items come sorted by decreasing work, and the hardware hands blocks to compute
+// units in index order as they free up, so the longest searches start first.
+__global__ void __launch_bounds__(BATCH_LANES) batch_kernel(BatchArgs b) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    Item it = b.items[blockIdx.x];
+    it.perm_in = b.perms + it.perm_off;
+    it.perm_out = b.perms + it.perm_off;
+    it.cost_out = b.best + it.out_off;
+    it.steps_out = b.done ? b.done + it.out_off : nullptr;
+    it.table = b.table + it.table_off;
+    switch (it.rows) {
+        case 2: search_body<2, true, 1024 / BATCH_LANES, false>(it, sm); break;
+        case 4: search_body<4, true, 1024 / BATCH_LANES, false>(it, sm); break;
+        default: search_body<8, true, 1024 / BATCH_LANES, false>(it, sm); break;
     }
 }
 
@@ -697,6 +785,16 @@ int search_lanes(int n, int rows, int ntiles, int sym) {
     const int need = ((tasks + maxt - 1) / maxt + 63) / 64 * 64;
     if (need > lanes) lanes = need;
     return lanes <= maxl ? lanes : 0;
+}
+
+int batch_shape_ok(int n, int rows, int ntiles, int sym) {
+    return rows <= 8 && ntiles <= BATCH_LANES && families(sym) * n <= BATCH_LANES * (1024 / BATCH_LANES) ? 1 : 0;
+}
+
+hipError_t launch_batch(const BatchArgs &b, size_t smem, hipStream_t st) {
+    if (b.count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_kernel, dim3(b.count), dim3(BATCH_LANES), smem, st, b);
+    return report(hipGetLastError(), "batch kernel launch");
 }
 
 size_t search_smem_bytes(int n, int rows, int lanes, int sym) {

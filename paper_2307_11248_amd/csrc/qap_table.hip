@@ -68,7 +68,11 @@ __global__ void __launch_bounds__(256) cost_kernel(TableArgs a) {
     }
 }
 
-// table[j][idx(u,v)] = Eq. (2) with the diagonal term, one entry per lane at a time.
+// out[idx(u,v)] = Eq. (2) with the diagonal term for one start, one entry per lane at a
+// time (F, D and the permutation already staged).
+__device__ void table_body(int n, const uint8_t *Fm, const uint8_t *Dm, const int *perm, int32_t *out);
+
+// table[j][idx(u,v)] for every start j of the launch.
 __global__ void __launch_bounds__(256) table_kernel(TableArgs a) {
     extern __shared__ __align__(16) unsigned char sm[];
     __shared__ int bad;
@@ -82,6 +86,29 @@ __global__ void __launch_bounds__(256) table_kernel(TableArgs a) {
         for (int i = t; i < a.m; i += blockDim.x) out[i] = 0;
         return;
     }
+    table_body(n, Fm, Dm, perm, out);
+}
+
+// The neighbourhood of every item of a batch: block i stages item i's F, D and start.
+__global__ void __launch_bounds__(256) table_batch_kernel(BatchArgs b) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    __shared__ int bad;
+    const Item &it = b.items[blockIdx.x];
+    TableArgs a{it.mats, b.perms + it.perm_off, nullptr, b.table + it.table_off, it.n, it.m, 1};
+    const int n = it.n, rs = row_stride(n), t = threadIdx.x;
+    uint8_t *Fm = sm, *Dm = sm + n * rs;
+    int *perm = reinterpret_cast<int *>(sm + 2 * n * rs);
+    int *pinv = perm + n;
+    const bool ok = stage_f_d_perm(a, 0, Fm, Dm, perm, pinv, &bad);
+    if (!ok) {
+        for (int i = t; i < it.m; i += blockDim.x) a.table[i] = 0;
+        return;
+    }
+    table_body(n, Fm, Dm, perm, a.table);
+}
+
+__device__ void table_body(int n, const uint8_t *Fm, const uint8_t *Dm, const int *perm, int32_t *out) {
+    const int rs = row_stride(n), t = threadIdx.x;
     for (int u = 0; u < n - 1; ++u) {
         const int pu = perm[u];
         const long long base = pidx(n, u, u + 1);
@@ -106,6 +133,14 @@ __global__ void __launch_bounds__(256) table_kernel(TableArgs a) {
 size_t table_smem(int n) { return (size_t)2 * n * row_stride(n) + (size_t)2 * n * 4; }
 
 }  // namespace
+
+size_t table_smem_bytes(int n) { return table_smem(n); }
+
+hipError_t launch_table_batch(const BatchArgs &b, size_t smem, hipStream_t st) {
+    if (b.count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(table_batch_kernel, dim3(b.count), dim3(256), smem, st, b);
+    return report(hipGetLastError(), "batch table kernel launch");
+}
 
 hipError_t launch_cost(const TableArgs &a, hipStream_t st) {
     if (a.k == 0) return hipSuccess;

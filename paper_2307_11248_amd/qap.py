@@ -30,13 +30,15 @@ EXPORTS = [
     "qap_strerror", "qap_create", "qap_destroy", "qap_size", "qap_cost", "qap_cost_async",
     "qap_delta_table", "qap_delta_table_async", "qap_2opt", "qap_2opt_async", "qap_tabu",
     "qap_tabu_async", "qap_tabu_plain_async", "qap_2opt_with_table_async", "qap_tabu_with_table_async",
-    "qap_set_tile_rows", "qap_get_tile_rows",
+    "qap_set_tile_rows", "qap_get_tile_rows", "qap_batch_create", "qap_batch_size", "qap_batch_run_async",
+    "qap_batch_tables_async", "qap_batch_search_async", "qap_batch_destroy", "qap_tabu_batch",
 ]
 
 _lib = None
 _lock = threading.Lock()
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
 _vp = ctypes.c_void_p
 
 
@@ -76,6 +78,15 @@ def lib():
                                                              _vp, _vp]),
                 "qap_set_tile_rows": (ctypes.c_int, [_vp, i32, i32]),
                 "qap_get_tile_rows": (ctypes.c_int, [_vp, i32, _i32p]),
+                "qap_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), i32, _i32p, i32, _i32p, _i32p, _u64p,
+                                                    _i32p, ctypes.POINTER(_vp)]),
+                "qap_batch_size": (ctypes.c_int, [_vp, _i64p, _i64p]),
+                "qap_batch_run_async": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+                "qap_batch_tables_async": (ctypes.c_int, [_vp, _vp, _vp]),
+                "qap_batch_search_async": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+                "qap_batch_destroy": (ctypes.c_int, [_vp]),
+                "qap_tabu_batch": (ctypes.c_int, [ctypes.POINTER(_vp), i32, _i32p, _i32p, i32, _i32p, _i32p,
+                                                  _u64p, _i64p, _i32p]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -233,3 +244,76 @@ class Handle:
                                                int(start_base), _dptr(d_best, "int64"), _dptr(d_done, "int32"),
                                                _stream_ptr(stream)),
                "qap_tabu_with_table_async")
+
+
+def _batch_args(handles, ks, lo, hi, seeds):
+    m = len(handles)
+    hs = (_vp * max(m, 1))(*[h.ptr for h in handles])
+    ks = _arr(ks, np.int32, (m,))
+    lo = _arr(lo, np.int32, (m,))
+    hi = _arr(hi, np.int32, (m,))
+    seeds = _arr(seeds, np.uint64, (m,))
+    return m, hs, ks, lo, hi, seeds
+
+
+class Batch:
+    """A planned batch of tabu searches over many instances (``qap_batch_create``).
+
+    Instance i (``handles[i]``) runs ``ks[i]`` starts with tenure range [lo[i], hi[i]]
+    and seed seeds[i]; starts and results are concatenated in instance order.
+    """
+
+    def __init__(self, handles, ks, iters, lo, hi, seeds, rows=None):
+        m, hs, ks, lo, hi, seeds = _batch_args(handles, ks, lo, hi, seeds)
+        rows_p = None if rows is None else _ptr(_arr(rows, np.int32, (m,)), _i32p)
+        b = _vp()
+        _check(lib().qap_batch_create(hs, m, _ptr(ks, _i32p), int(iters), _ptr(lo, _i32p), _ptr(hi, _i32p),
+                                      _ptr(seeds, _u64p), rows_p, ctypes.byref(b)), "qap_batch_create")
+        self._b = b
+        self._handles = list(handles)   # the plan refers to their device matrices
+        s, p = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().qap_batch_size(b, ctypes.byref(s), ctypes.byref(p)), "qap_batch_size")
+        self.starts, self.perm_ints = s.value, p.value
+
+    def run_async(self, d_perms, d_best, d_done=None, stream=None):
+        _check(lib().qap_batch_run_async(self._b, _dptr(d_perms, "int32"), _dptr(d_best, "int64"),
+                                         _dptr(d_done, "int32"), _stream_ptr(stream)), "qap_batch_run_async")
+
+    def tables_async(self, d_perms, stream=None):
+        _check(lib().qap_batch_tables_async(self._b, _dptr(d_perms, "int32"), _stream_ptr(stream)),
+               "qap_batch_tables_async")
+
+    def search_async(self, d_perms, d_best, d_done=None, stream=None):
+        _check(lib().qap_batch_search_async(self._b, _dptr(d_perms, "int32"), _dptr(d_best, "int64"),
+                                            _dptr(d_done, "int32"), _stream_ptr(stream)), "qap_batch_search_async")
+
+    def close(self):
+        if getattr(self, "_b", None) is not None:
+            lib().qap_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def tabu_batch(handles, perms, ks, iters, lo, hi, seeds):
+    """Blocking batched tabu (``qap_tabu_batch``): perms is the concatenation of every
+    instance's starts, flattened; returns (best permutations, best costs, moves made)."""
+    m, hs, ks, lo, hi, seeds = _batch_args(handles, ks, lo, hi, seeds)
+    p = np.array(perms, dtype=np.int32, copy=True).reshape(-1)
+    total = int(sum(int(k) for k in ks))
+    best = np.zeros(total, dtype=np.int64)
+    done = np.zeros(total, dtype=np.int32)
+    _check(lib().qap_tabu_batch(hs, m, _ptr(p, _i32p), _ptr(ks, _i32p), int(iters), _ptr(lo, _i32p),
+                                _ptr(hi, _i32p), _ptr(seeds, _u64p), _ptr(best, _i64p), _ptr(done, _i32p)),
+           "qap_tabu_batch")
+    return p, best, done

@@ -1,0 +1,177 @@
+"""GPU parity of the batched tabu search over many instances of uneven n.
+
+The batched launch must give every start exactly what the oracle gives it alone (best
+permutation, best cost, moves made), and exactly what a search of that instance alone on
+the GPU gives (batch invariance).  The full-size uneven batch (512 instances, n from 20
+to 150, 8 starts of 5000 iterations) is run as the benchmark runs it, inside a captured
+HIP graph replayed several times, and a sample of its starts is recomputed by the oracle.
+"""
+import os
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_11248_amd import qap
+from paper_2307_11248_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+WORKERS = max(1, min(16, os.cpu_count() or 1))
+
+
+def note(msg):
+    sys.__stderr__.write("[gpu-case] %s\n" % msg)
+    sys.__stderr__.flush()
+
+
+def pmap(f, items):
+    with ThreadPoolExecutor(WORKERS) as ex:
+        return list(ex.map(f, items))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.init()
+    yield
+
+
+def oracle_rows(insts, ks, iters, lohi, seeds):
+    """Every (instance, start) of a batch through the oracle, in batch order."""
+    jobs = [(i, j) for i in range(len(insts)) for j in range(ks[i])]
+
+    def one(a):
+        i, j = a
+        F, D, P = insts[i]
+        return oracle.tabu(F, D, P[j], iters, lohi[i][0], lohi[i][1], seeds[i], j)
+
+    return jobs, pmap(one, jobs)
+
+
+def mixed_batch(seed, sizes, k):
+    rng = np.random.default_rng(seed)
+    insts, lohi, seeds = [], [], []
+    for t, n in enumerate(sizes):
+        F, D = W.random_instance(rng, n, 0, 99, symmetric=(t % 3 == 1), diag=(t % 4 == 2))
+        insts.append((F, D, W.starts(rng, n, k[t])))
+        lo, hi = W.tabu_tenure_range(n)
+        lohi.append((lo, hi))
+        seeds.append(int(rng.integers(0, 2**62)))
+    return insts, lohi, seeds
+
+
+@pytest.mark.parametrize("sizes,k,iters", [
+    ([2, 3, 5, 12, 40, 64, 33, 150, 97, 128], [3, 2, 4, 1, 3, 2, 0, 2, 3, 2], 400),
+    ([150, 149, 20, 21, 65, 66, 130], [2, 1, 3, 2, 2, 1, 2], 1500),
+])
+def test_batch_equals_oracle_mixed_n(sizes, k, iters):
+    insts, lohi, seeds = mixed_batch(sum(sizes), sizes, k)
+    note("batch mixed sizes=%s k=%s iters=%d" % (sizes, k, iters))
+    hs = [qap.Handle(F, D) for F, D, _ in insts]
+    perms = np.concatenate([P.reshape(-1) for _, _, P in insts]).astype(np.int32)
+    p, c, d = qap.tabu_batch(hs, perms, k, iters, [a for a, _ in lohi], [b for _, b in lohi], seeds)
+    jobs, res = oracle_rows(insts, k, iters, lohi, seeds)
+    off = 0
+    for (i, j), r in zip(jobs, res):
+        n = insts[i][0].shape[0]
+        row = sum(k[:i]) + j
+        got = p[off:off + n]
+        assert (got == r[0]).all() and c[row] == r[1] and d[row] == r[2], (i, j, n)
+        off += n
+    for h in hs:
+        h.close()
+
+
+def test_batch_invariance_against_single_instance_searches():
+    w = W.c4_batch(m=24, k=4, iters=1200)
+    note("batch invariance: 24 instances of the uneven workload, 4 starts x 1200 iterations")
+    hs = [qap.Handle(I.F, I.D) for I in w.instances]
+    lo = [w.tenure(I.n)[0] for I in w.instances]
+    hi = [w.tenure(I.n)[1] for I in w.instances]
+    seeds = [I.seed for I in w.instances]
+    perms = np.concatenate([I.perms.reshape(-1) for I in w.instances])
+    p, c, d = qap.tabu_batch(hs, perms, [4] * 24, w.iters, lo, hi, seeds)
+    off, row = 0, 0
+    for t, I in enumerate(w.instances):
+        sp, sc, sd = hs[t].tabu(I.perms, w.iters, lo[t], hi[t], I.seed)
+        n = I.n
+        assert (p[off:off + 4 * n].reshape(4, n) == sp).all(), t
+        assert (c[row:row + 4] == sc).all() and (d[row:row + 4] == sd).all(), t
+        off += 4 * n
+        row += 4
+    for h in hs:
+        h.close()
+
+
+def test_batch_rejects_unsupported_and_bad_input():
+    rng = np.random.default_rng(5)
+    F, D = W.random_instance(rng, 256, 0, 99)
+    with qap.Handle(F, D) as big, qap.Handle(*W.random_instance(rng, 10, 0, 9)) as small:
+        with pytest.raises(qap.QapError) as ei:
+            qap.Batch([small, big], [1, 1], 100, [1, 1], [3, 30], [1, 2])
+        assert ei.value.code == qap.QAP_E_UNSUPPORTED
+        bad = np.arange(10, dtype=np.int32)
+        bad[3] = 4
+        with pytest.raises(qap.QapError) as ei:
+            qap.tabu_batch([small], bad, [1], 100, [1], [3], [1])
+        assert ei.value.code == qap.QAP_E_NOT_PERM
+        with qap.Batch([small], [0], 100, [1], [3], [1]) as b:   # empty batch runs as a no-op
+            assert b.starts == 0 and b.perm_ints == 0
+
+
+def test_batch_full_size_graph_replay_sampled():
+    import torch
+    w = W.c4_batch()
+    insts = w.instances
+    m, k = len(insts), len(insts[0].perms)
+    note("batch full size: %d instances x %d starts x %d iterations, graph replay" % (m, k, w.iters))
+    hs = [qap.Handle(I.F, I.D) for I in insts]
+    lo = [w.tenure(I.n)[0] for I in insts]
+    hi = [w.tenure(I.n)[1] for I in insts]
+    seeds = [I.seed for I in insts]
+    starts = torch.from_numpy(np.concatenate([I.perms.reshape(-1) for I in insts])).cuda()
+    work = torch.empty_like(starts)
+    best = torch.empty(m * k, dtype=torch.int64, device="cuda")
+    done = torch.empty(m * k, dtype=torch.int32, device="cuda")
+    with qap.Batch(hs, [k] * m, w.iters, lo, hi, seeds) as b:
+        assert b.starts == m * k and b.perm_ints == starts.numel()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            work.copy_(starts)
+            b.run_async(work, best, done, stream=s)
+        torch.cuda.synchronize()
+        ep, ec, ed = work.cpu().numpy(), best.cpu().numpy(), done.cpu().numpy()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            work.copy_(starts)
+            b.run_async(work, best, done, stream=s)
+        for rep in range(3):
+            best.fill_(-1)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert (work.cpu().numpy() == ep).all() and (best.cpu().numpy() == ec).all(), rep
+            assert (done.cpu().numpy() == ed).all(), rep
+    assert (ed <= w.iters).all() and (ed >= 0).all()
+    off = np.concatenate([[0], np.cumsum([k * I.n for I in insts])])
+    for t, I in enumerate(insts):
+        rows = ep[off[t]:off[t + 1]].reshape(k, I.n)
+        assert (hs[t].cost(rows) == ec[t * k:(t + 1) * k]).all(), t
+    sample = [(0, 0), (1, 7), (2, 3), (257, 5), (510, 1), (511, 6)]
+    sample += [(int(np.argmax([I.n for I in insts])), 2)]
+
+    def one(a):
+        t, j = a
+        I = insts[t]
+        return oracle.tabu(I.F, I.D, I.perms[j], w.iters, lo[t], hi[t], I.seed, j)
+
+    for (t, j), r in zip(sample, pmap(one, sample)):
+        n = insts[t].n
+        got = ep[off[t] + j * n: off[t] + (j + 1) * n]
+        assert (got == r[0]).all() and ec[t * k + j] == r[1] and ed[t * k + j] == r[2], (t, j)
+    for h in hs:
+        h.close()
