@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-start comparison")
     ap.add_argument("--cpu-starts", type=int, default=32)
+    ap.add_argument("--no-tune", action="store_true", help="uneven batch: the default tile shape for every n")
+    ap.add_argument("--tune-cache", default=None, help="uneven batch: JSON cache of tuned tile shapes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (to scale HBM byte counters)")
     return ap.parse_args()
@@ -131,6 +133,15 @@ def run_batch(args, w):
     lo = [w.tenure(I.n)[0] for I in insts]
     hi = [w.tenure(I.n)[1] for I in insts]
     seeds = [I.seed for I in insts]
+    tune_s, rows_hist = None, None
+    if not args.no_tune:
+        from paper_2307_11248_amd.autotune import TileCache
+        t0 = time.perf_counter()
+        cache = TileCache(args.tune_cache)
+        rows = cache.apply_all(hs, "batch")
+        cache.save()
+        tune_s = time.perf_counter() - t0
+        rows_hist = {str(r): rows.count(r) for r in sorted(set(rows))}
     b = qap.Batch(hs, [k] * m, w.iters, lo, hi, seeds)
     stream = torch.cuda.Stream()
     starts = torch.from_numpy(np.concatenate([I.perms.reshape(-1) for I in insts])).cuda()
@@ -193,7 +204,8 @@ def run_batch(args, w):
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int32", "data": "synthetic",
            "config": {"workload": w.name, "instances": m, "n_range": [min(ns), max(ns)], "starts_per_instance": k,
-                      "iters": w.iters, "tenure": "[0.9n, 1.1n]", "graph": True},
+                      "iters": w.iters, "tenure": "[0.9n, 1.1n]", "graph": True,
+                      "tile_rows_per_instance": rows_hist, "tuning_s": tune_s},
            "solves_per_s": m * k / (ms_step / 1e3), "table_kernel_ms": table_ms, "roofline": roof}
 
     if not args.no_plain:

@@ -61,9 +61,11 @@ const char *qap_strerror(int code);
  * Create a handle for one instance (F, D) of size n (Sec. 2.1) on the current HIP
  * device.  F and D are host pointers, read once and copied; the handle owns its device
  * copies until qap_destroy.  Returns QAP_E_RANGE if an entry lies outside [0, 255].
- * Cost and neighbourhood tables serve every n <= QAP_NMAX; the 2opt and tabu entry
- * points return QAP_E_UNSUPPORTED when no tile shape of the search kernels fits n in
- * one workgroup (the neighbourhood is held in registers, F, F^T, D, D^T in LDS).
+ * Every entry point serves every n <= QAP_NMAX: the searches hold the neighbourhood in
+ * registers and F, F^T, D, D^T in LDS while that fits one workgroup (n <= 176 in the
+ * batched kernels), and above that run the streamed kernel (neighbourhood in global
+ * memory, only G = F[p][p] in LDS).  QAP_E_UNSUPPORTED is left for a device whose LDS
+ * is smaller than the streamed kernel needs.
  */
 int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out);
 
@@ -200,17 +202,72 @@ int qap_tabu_batch(const qap_handle *hs, int32_t m, int32_t *perms, const int32_
                    const uint64_t *seed_per, int64_t *best_out, int32_t *done_out);
 
 /*
+ * Serving: tabu solves of uneven n submitted one at a time, run with continuous
+ * batching over device-resident state (the many-search delivery of Secs. 4.4 and 5.2,
+ * applied to a stream of requests).
+ *
+ * qap_server_create reserves a device memory pool of pool_bytes and slots for up to
+ * max_active concurrent searches.  qap_server_submit copies a request (its own F, D, n,
+ * one start permutation, iteration count and tenure range [lo, hi], Philox seed; start id
+ * 0) and queues it; it returns QAP_E_NOMEM at once if the request's footprint
+ * (qap_server_footprint(s, n, sym) bytes, sym = 1 when F and D are both symmetric)
+ * exceeds the whole pool, QAP_E_UNSUPPORTED if no tile
+ * shape of the batched kernel serves n, QAP_E_RANGE / QAP_E_NOT_PERM as qap_create and
+ * qap_tabu do.  qap_server_step admits queued requests in arrival order while a slot is
+ * free and their footprint fits the pool, then runs one chunk of every admitted search
+ * in one launch: each search runs until about chunk_ms of device time has passed (0: to
+ * its end), stopping at an iteration boundary, with its permutation, neighbourhood,
+ * tabu list and best solution kept in the pool in between.  It blocks until the chunk
+ * ends, then copies back the results of searches that finished and frees their memory;
+ * it returns how many finished, and the numbers still running and still queued.  Every
+ * result equals that of qap_tabu on the same instance, start, iterations, tenure range
+ * and seed (start id 0), whatever else was admitted alongside and however it was
+ * chunked.  qap_server_result returns 1 and the result (best permutation int32[n], best
+ * cost, moves made, and in latency_ms_out[2] (may be NULL) the time from submission to
+ * the step that finished it and the time spent queued, in ms) once the request has
+ * finished, after which its ticket is forgotten; 0 while it is queued or running.
+ * qap_server_stats fills int64[6]: running, queued, pool bytes in use, pool bytes,
+ * steps, chunks run.  One thread at a time may call a server's functions.
+ */
+typedef struct qap_server *qap_server_handle;
+int qap_server_create(int64_t pool_bytes, int32_t max_active, double chunk_ms, qap_server_handle *out);
+int64_t qap_server_footprint(qap_server_handle s, int32_t n, int32_t sym);
+int qap_server_submit(qap_server_handle s, const int32_t *F, const int32_t *D, int32_t n, const int32_t *start,
+                      int32_t iters, int32_t lo, int32_t hi, uint64_t seed, int64_t *ticket_out);
+int qap_server_step(qap_server_handle s, int32_t *active_out, int32_t *pending_out);
+int qap_server_result(qap_server_handle s, int64_t ticket, int32_t *perm_out, int64_t *best_out,
+                      int32_t *moves_out, double *latency_ms_out);
+int qap_server_stats(qap_server_handle s, int64_t *out);
+int qap_server_destroy(qap_server_handle s);
+
+/*
  * Tile shape of the search kernels (the thread-configuration search of Sec. 5.2,
  * re-done for gfx950): each lane of a search's workgroup holds a block of `rows` x 4
- * neighbourhood entries in registers, rows in {2, 4, 8, 16}; 0 restores the library's
- * own choice for this n.  algo: 0 = tabu, 1 = 2opt.  Returns QAP_E_UNSUPPORTED if the
- * shape needs more than 1024 lanes for this n.
+ * neighbourhood entries in registers, rows in {2, 4, 8, 16}; rows = -8 selects the
+ * streamed kernel (tiles of 8 rows kept in global memory and updated in passes, D read
+ * from global memory; 512 lanes; serves every n up to QAP_NMAX); 0 restores the
+ * library's own choice for this n (the smallest register tile that fits, else the
+ * streamed kernel).  algo: 0 = tabu, 1 = 2opt, 2 = this instance inside a batch
+ * (qap_batch_create with rows_per NULL or 0; rows 2, 4, 8 or -8, fixed workgroup of 512
+ * lanes).  Returns QAP_E_UNSUPPORTED if the shape does not fit this n (lanes or LDS).
  */
 int qap_set_tile_rows(qap_handle h, int32_t algo, int32_t rows);
 
-/* Tile rows currently used for algo (0 = tabu, 1 = 2opt), and the lanes per search in
- * *lanes_out (may be NULL). */
+/* Tile rows currently used for algo, and the lanes per search in *lanes_out (may be
+ * NULL). */
 int qap_get_tile_rows(qap_handle h, int32_t algo, int32_t *lanes_out);
+
+/*
+ * Autotuner of the tile shape (replaces the paper's search over thread counts and block
+ * sizes, Sec. 5.2 and Eq. (3), with measurement): for algo (as above) runs k searches of
+ * `iters` iterations (2opt: at most `iters` moves) from fixed pseudo-random starts with
+ * every shape that fits n, times the search kernel with HIP events (one warm-up run
+ * first), stores the fastest as the handle's shape for algo and returns its rows.
+ * ms_out (float[5] or NULL) receives the time per rows value 2, 4, 8, 16, -8, or -1
+ * where a shape does not fit.  Blocking; allocates its own device buffers; results do not
+ * depend on the shape, only the time does.
+ */
+int qap_tune_tile_rows(qap_handle h, int32_t algo, int32_t k, int32_t iters, float *ms_out);
 
 #ifdef __cplusplus
 }

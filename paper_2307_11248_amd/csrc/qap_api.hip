@@ -9,11 +9,12 @@
 #include <vector>
 
 #include "../../include/qap.h"
+#include "qap_host.h"
 #include "qap_internal.h"
 
 using namespace qapk;
 
-namespace {
+namespace qaph {
 
 const int kRowsChoices[4] = {2, 4, 8, 16};
 
@@ -39,49 +40,34 @@ std::vector<int32_t> enumerate_tiles(int n, int rows, int *ninterior) {
     return inner;
 }
 
-}  // namespace
-
-struct qap_ctx {
-    int n = 0, m = 0, sym = 0, device = 0;
-    size_t max_smem = 0;
-    uint8_t *d_mats = nullptr;       // [F | F^T | D | D^T] u8, n rows of row_stride(n) bytes
-    TileSet tiles[4];                // one per entry of kRowsChoices
-    int rows_choice[2] = {0, 0};     // 0 tabu, 1 2opt: index into kRowsChoices
-    int rows_default[2] = {0, 0};
-};
-
-namespace {
-
-int rows_index(int rows) {
-    for (int i = 0; i < 4; ++i)
-        if (kRowsChoices[i] == rows) return i;
-    return -1;
+int pack_instance(const int32_t *F, const int32_t *D, int n, std::vector<uint8_t> &pack, int *sym) {
+    bool symF = true, symD = true;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const int32_t f = F[(size_t)i * n + j], d = D[(size_t)i * n + j];
+            if (f < 0 || f > 255 || d < 0 || d > 255) return QAP_E_RANGE;
+            if (f != F[(size_t)j * n + i]) symF = false;
+            if (d != D[(size_t)j * n + i]) symD = false;
+        }
+    *sym = (symF && symD) ? 1 : 0;
+    const int rs = row_stride(n);
+    pack.assign((size_t)4 * n * rs, 0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            pack[(size_t)0 * n * rs + (size_t)i * rs + j] = (uint8_t)F[(size_t)i * n + j];
+            pack[(size_t)1 * n * rs + (size_t)i * rs + j] = (uint8_t)F[(size_t)j * n + i];
+            pack[(size_t)2 * n * rs + (size_t)i * rs + j] = (uint8_t)D[(size_t)i * n + j];
+            pack[(size_t)3 * n * rs + (size_t)i * rs + j] = (uint8_t)D[(size_t)j * n + i];
+        }
+    return QAP_OK;
 }
 
-bool shape_fits(const qap_ctx *h, int ri) {
-    const TileSet &ts = h->tiles[ri];
-    if (ts.lanes < 64 || ts.lanes > search_max_lanes(kRowsChoices[ri])) return false;
-    if (ts.ntiles > ts.lanes) return false;
-    return search_smem_bytes(h->n, kRowsChoices[ri], ts.lanes, h->sym) <= h->max_smem;
-}
-
-// Default tile shape: the smallest tile that fits (the most lanes per search, hence the
-// shortest dependency chain per iteration).
-int default_rows(const qap_ctx *h) {
-    for (int i = 0; i < 4; ++i)
-        if (shape_fits(h, i)) return i;
-    return -1;
-}
-
-// Map a HIP status to a QAP code; with QAP_VERBOSE set in the environment, a failure
-// is also reported on stderr with HIP's own text and the call site.
 int dev_err_at(hipError_t e, const char *where) {
     if (e == hipSuccess) return QAP_OK;
     static const bool verbose = std::getenv("QAP_VERBOSE") != nullptr;
     if (verbose) std::fprintf(stderr, "libqap: %s: %s (%d)\n", where, hipGetErrorString(e), (int)e);
     return e == hipErrorOutOfMemory ? QAP_E_NOMEM : QAP_E_DEVICE;
 }
-#define dev_err(e) dev_err_at((e), __func__)
 
 bool check_perms(const int32_t *perms, int k, int n) {
     std::vector<int> seen(n);
@@ -96,6 +82,58 @@ bool check_perms(const int32_t *perms, int k, int n) {
     return true;
 }
 
+}  // namespace qaph
+
+using namespace qaph;
+
+struct qap_ctx {
+    int n = 0, m = 0, sym = 0, device = 0;
+    size_t max_smem = 0;
+    uint8_t *d_mats = nullptr;       // [F | F^T | D | D^T] u8, n rows of row_stride(n) bytes
+    TileSet tiles[4];                // one per entry of kRowsChoices
+    // per algorithm (0 tabu, 1 2opt, 2 batched tabu): index into kRowsChoices, kStream for
+    // the streamed kernel, -1 when no kernel serves this n
+    int rows_choice[3] = {0, 0, 0};
+    int rows_default[3] = {0, 0, 0};
+    int stream_ok = 0;               // the streamed kernel serves this n
+};
+
+namespace {
+
+// Shape index of the streamed kernel (tiles of STREAM_ROWS rows in global memory); the
+// ABI names it rows = -STREAM_ROWS.
+constexpr int kStream = 4;
+
+int rows_index(int rows) {
+    if (rows == -STREAM_ROWS) return kStream;
+    for (int i = 0; i < 4; ++i)
+        if (kRowsChoices[i] == rows) return i;
+    return -1;
+}
+
+int shape_rows(int ri) { return ri == kStream ? -STREAM_ROWS : kRowsChoices[ri]; }
+
+// The tile list a shape uses (the streamed kernel uses the STREAM_ROWS list).
+const TileSet &shape_tiles(const qap_ctx *h, int ri) { return h->tiles[ri == kStream ? 2 : ri]; }
+
+bool shape_fits(const qap_ctx *h, int ri) {
+    if (ri == kStream) return h->stream_ok != 0;
+    if (ri < 0 || ri > 3) return false;
+    const TileSet &ts = h->tiles[ri];
+    if (ts.lanes < 64 || ts.lanes > search_max_lanes(kRowsChoices[ri])) return false;
+    if (ts.ntiles > ts.lanes) return false;
+    return search_smem_bytes(h->n, kRowsChoices[ri], ts.lanes, h->sym) <= h->max_smem;
+}
+
+// Default tile shape: the smallest tile that fits (the most lanes per search, hence the
+// shortest dependency chain per iteration).
+int default_rows(const qap_ctx *h) {
+    for (int i = 0; i < 4; ++i)
+        if (shape_fits(h, i)) return i;
+    return h->stream_ok ? kStream : -1;
+}
+
+
 // RAII device buffer for the blocking entry points.
 struct DevBuf {
     void *p = nullptr;
@@ -103,8 +141,15 @@ struct DevBuf {
     ~DevBuf() { if (p) (void)hipFree(p); }
 };
 
+// Private stream of a blocking entry point.
+struct HostCall {
+    hipStream_t st = nullptr;
+    ~HostCall() { if (st) (void)hipStreamDestroy(st); }
+    hipError_t init() { return hipStreamCreateWithFlags(&st, hipStreamNonBlocking); }
+};
+
 SearchArgs base_args(qap_ctx *h, int algo) {
-    const TileSet &ts = h->tiles[h->rows_choice[algo]];
+    const TileSet &ts = shape_tiles(h, h->rows_choice[algo]);
     SearchArgs a{};
     a.mats = h->d_mats;
     a.n = h->n;
@@ -141,9 +186,29 @@ hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t
     a.hi = hi;
     a.seed = seed;
     a.start_base = start_base;
-    const int rows = kRowsChoices[h->rows_choice[algo]];
-    const int lanes = h->tiles[h->rows_choice[algo]].lanes;
+    const int ri = h->rows_choice[algo];
     hipError_t e = hipSuccess;
+    if (ri == kStream) {
+        // tile state in stream-ordered scratch, one slice per search of a launch
+        a.tile_stride = stream_tile_int4(a.ntiles);
+        const int per_launch = plain ? 1 : k;
+        e = report(hipMallocAsync((void **)&a.tile_work, (size_t)per_launch * a.tile_stride * sizeof(int4), st),
+                   "hipMallocAsync");
+        if (e != hipSuccess) return e;
+        if (plain) {
+            for (int j = 0; j < k && e == hipSuccess; ++j) {
+                a.job0 = j;
+                e = launch_stream(algo == 0, a, 1, st);
+            }
+        } else {
+            a.job0 = 0;
+            e = launch_stream(algo == 0, a, k, st);
+        }
+        const hipError_t e2 = hipFreeAsync(a.tile_work, st);
+        return e != hipSuccess ? e : e2;
+    }
+    const int rows = kRowsChoices[ri];
+    const int lanes = h->tiles[ri].lanes;
     if (plain) {
         for (int j = 0; j < k && e == hipSuccess; ++j) {
             a.job0 = j;
@@ -170,25 +235,57 @@ int run_search(qap_ctx *h, int algo, int32_t *d_perms, int k, int iters, int lo,
     return dev_err(e);
 }
 
-// Tile shape of an instance in the batched kernel: the smallest of 2, 4, 8 rows that
-// fits its lanes and LDS.
-int batch_rows(const qap_ctx *h) {
-    for (int i = 0; i < 3; ++i) {
-        const TileSet &ts = h->tiles[i];
-        if (ts.d_tiles && batch_shape_ok(h->n, kRowsChoices[i], ts.ntiles, h->sym) &&
-            search_smem_bytes(h->n, kRowsChoices[i], BATCH_LANES, h->sym) <= h->max_smem)
-            return kRowsChoices[i];
+// Whether tile shape ri serves this instance in the batched kernel (fixed workgroup of
+// BATCH_LANES lanes, rows 2, 4 or 8).
+bool batch_fits(const qap_ctx *h, int ri) {
+    if (ri == kStream) return h->stream_ok != 0;
+    if (ri < 0 || ri > 2) return false;
+    const TileSet &ts = h->tiles[ri];
+    return ts.d_tiles && batch_shape_ok(h->n, kRowsChoices[ri], ts.ntiles, h->sym) &&
+           search_smem_bytes(h->n, kRowsChoices[ri], BATCH_LANES, h->sym) <= h->max_smem;
+}
+
+// Default batched shape: the smallest tile that fits.
+int batch_default(const qap_ctx *h) {
+    for (int i = 0; i < 3; ++i)
+        if (batch_fits(h, i)) return i;
+    return h->stream_ok ? kStream : -1;
+}
+
+bool algo_fits(const qap_ctx *h, int algo, int ri) { return algo == 2 ? batch_fits(h, ri) : shape_fits(h, ri); }
+
+// Tile shape of an instance in the batched kernel: the handle's choice for algo 2.
+int batch_shape(const qap_ctx *h) {
+    const int ri = h->rows_choice[2];
+    return ri >= 0 && batch_fits(h, ri) ? ri : -1;
+}
+
+// Starts for timing runs: fixed pseudo-random permutations (splitmix64 driving a
+// Fisher-Yates shuffle), so that every shape is timed on the same work.
+void timing_starts(int n, int k, std::vector<int32_t> &p) {
+    p.resize((size_t)k * n);
+    uint64_t x = 0x243F6A8885A308D3ull;
+    for (int j = 0; j < k; ++j) {
+        int32_t *q = p.data() + (size_t)j * n;
+        for (int i = 0; i < n; ++i) q[i] = i;
+        for (int i = n - 1; i > 0; --i) {
+            uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            std::swap(q[i], q[z % (uint64_t)(i + 1)]);
+        }
     }
-    return -1;
 }
 
 }  // namespace
 
 struct qap_batch {
     int count = 0;                  // searches (items)
-    long long perm_ints = 0, table_ints = 0;
+    long long perm_ints = 0, table_ints = 0, tile_int4 = 0;
     Item *d_items = nullptr;
     int32_t *d_table = nullptr;
+    int4 *d_tile_work = nullptr;    // tile state of the streamed searches
     size_t smem = 0, table_smem = 0;
 };
 
@@ -210,20 +307,15 @@ const char *qap_strerror(int code) {
 int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out) {
     if (!F || !D || !out || n < 2 || n > QAP_NMAX) return QAP_E_INVALID;
     *out = nullptr;
-    const size_t nn = (size_t)n * n;
-    bool symF = true, symD = true;
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
-            const int32_t f = F[(size_t)i * n + j], d = D[(size_t)i * n + j];
-            if (f < 0 || f > 255 || d < 0 || d > 255) return QAP_E_RANGE;
-            if (f != F[(size_t)j * n + i]) symF = false;
-            if (d != D[(size_t)j * n + i]) symD = false;
-        }
+    std::vector<uint8_t> pack;
+    int sym = 0;
+    const int prc = pack_instance(F, D, n, pack, &sym);
+    if (prc != QAP_OK) return prc;
     qap_ctx *h = new (std::nothrow) qap_ctx;
     if (!h) return QAP_E_NOMEM;
     h->n = n;
     h->m = n * (n - 1) / 2;
-    h->sym = (symF && symD) ? 1 : 0;
+    h->sym = sym;
     if (hipGetDevice(&h->device) != hipSuccess) { delete h; return QAP_E_DEVICE; }
     int smem = 0;
     if (hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) != hipSuccess) {
@@ -231,16 +323,6 @@ int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out) {
         return QAP_E_DEVICE;
     }
     h->max_smem = (size_t)smem;
-    const int rs = row_stride(n);
-    std::vector<uint8_t> pack((size_t)4 * n * rs, 0);
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
-            pack[(size_t)0 * n * rs + (size_t)i * rs + j] = (uint8_t)F[(size_t)i * n + j];
-            pack[(size_t)1 * n * rs + (size_t)i * rs + j] = (uint8_t)F[(size_t)j * n + i];
-            pack[(size_t)2 * n * rs + (size_t)i * rs + j] = (uint8_t)D[(size_t)i * n + j];
-            pack[(size_t)3 * n * rs + (size_t)i * rs + j] = (uint8_t)D[(size_t)j * n + i];
-        }
-    (void)nn;
     hipError_t e = hipMalloc((void **)&h->d_mats, pack.size());
     if (e == hipSuccess) e = hipMemcpy(h->d_mats, pack.data(), pack.size(), hipMemcpyHostToDevice);
     for (int i = 0; i < 4 && e == hipSuccess; ++i) {
@@ -258,9 +340,11 @@ int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out) {
         qap_destroy(h);
         return dev_err(e);
     }
+    h->stream_ok = stream_shape_ok(n, h->sym, h->max_smem);
     const int d = default_rows(h);   // -1: no search kernel shape fits this n
     h->rows_default[0] = h->rows_default[1] = d;
     h->rows_choice[0] = h->rows_choice[1] = d;
+    h->rows_default[2] = h->rows_choice[2] = batch_default(h);
     *out = h;
     return QAP_OK;
 }
@@ -277,24 +361,96 @@ int qap_destroy(qap_handle h) {
 int qap_size(qap_handle h) { return h ? h->n : QAP_E_INVALID; }
 
 int qap_set_tile_rows(qap_handle h, int32_t algo, int32_t rows) {
-    if (!h || algo < 0 || algo > 1) return QAP_E_INVALID;
+    if (!h || algo < 0 || algo > 2) return QAP_E_INVALID;
     if (rows == 0) {
         h->rows_choice[algo] = h->rows_default[algo];
         return QAP_OK;
     }
     const int ri = rows_index(rows);
     if (ri < 0) return QAP_E_INVALID;
-    if (!shape_fits(h, ri)) return QAP_E_UNSUPPORTED;
+    if (!algo_fits(h, algo, ri)) return QAP_E_UNSUPPORTED;
     h->rows_choice[algo] = ri;
     return QAP_OK;
 }
 
 int qap_get_tile_rows(qap_handle h, int32_t algo, int32_t *lanes_out) {
-    if (!h || algo < 0 || algo > 1) return QAP_E_INVALID;
+    if (!h || algo < 0 || algo > 2) return QAP_E_INVALID;
     const int ri = h->rows_choice[algo];
     if (ri < 0) return QAP_E_UNSUPPORTED;
-    if (lanes_out) *lanes_out = h->tiles[ri].lanes;
-    return kRowsChoices[ri];
+    if (lanes_out) *lanes_out = (algo == 2 || ri == kStream) ? BATCH_LANES : h->tiles[ri].lanes;
+    return shape_rows(ri);
+}
+
+int qap_tune_tile_rows(qap_handle h, int32_t algo, int32_t k, int32_t iters, float *ms_out) {
+    if (!h || algo < 0 || algo > 2 || k <= 0 || iters <= 0) return QAP_E_INVALID;
+    for (int i = 0; i < 5; ++i)
+        if (ms_out) ms_out[i] = -1.0f;
+    const int n = h->n;
+    std::vector<int32_t> hp;
+    timing_starts(n, k, hp);
+    const int lo = std::max(0, n * 9 / 10), hi = n + n / 10;
+    HostCall c;
+    DevBuf ds, dw, db, dd, dt;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = c.init();
+    if (e == hipSuccess) e = ds.alloc(hp.size() * 4);
+    if (e == hipSuccess) e = dw.alloc(hp.size() * 4);
+    if (e == hipSuccess) e = db.alloc((size_t)k * 8);
+    if (e == hipSuccess) e = dd.alloc((size_t)k * 4);
+    if (e == hipSuccess && algo < 2) e = dt.alloc((size_t)k * h->m * 4);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemcpyAsync(ds.p, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, c.st);
+    const int saved = h->rows_choice[algo];
+    int best = -1, rc = QAP_OK;
+    float best_ms = 0.0f;
+    for (int ri = 0; ri <= kStream && e == hipSuccess && rc == QAP_OK; ++ri) {
+        if (!algo_fits(h, algo, ri)) continue;
+        qap_batch_handle b = nullptr;
+        if (algo == 2) {
+            const int32_t rows = shape_rows(ri);
+            const uint64_t seed = 1;
+            const qap_handle hh = h;
+            rc = qap_batch_create(&hh, 1, &k, iters, &lo, &hi, &seed, &rows, &b);
+            if (rc != QAP_OK) break;
+        }
+        h->rows_choice[algo] = ri;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {   // the first run warms up
+            e = hipMemcpyAsync(dw.p, ds.p, hp.size() * 4, hipMemcpyDeviceToDevice, c.st);
+            int32_t *w = (int32_t *)dw.p;
+            if (e == hipSuccess && algo < 2) {
+                TableArgs ta{h->d_mats, w, nullptr, (int32_t *)dt.p, n, h->m, k};
+                e = launch_table(ta, c.st);
+            } else if (e == hipSuccess) {
+                rc = qap_batch_tables_async(b, w, c.st);
+            }
+            if (e == hipSuccess && rc == QAP_OK) e = hipEventRecord(e0, c.st);
+            if (e == hipSuccess && rc == QAP_OK) {
+                if (algo < 2)
+                    e = launch_searches(h, algo, w, (const int32_t *)dt.p, k, iters, lo, hi, 1, 0, (int64_t *)db.p,
+                                        (int32_t *)dd.p, c.st, false);
+                else
+                    rc = qap_batch_search_async(b, w, (int64_t *)db.p, (int32_t *)dd.p, c.st);
+            }
+            if (e == hipSuccess && rc == QAP_OK) e = hipEventRecord(e1, c.st);
+            if (e == hipSuccess && rc == QAP_OK) e = hipEventSynchronize(e1);
+            if (e == hipSuccess && rc == QAP_OK) e = hipEventElapsedTime(&ms, e0, e1);
+        }
+        qap_batch_destroy(b);
+        if (e != hipSuccess || rc != QAP_OK) break;
+        if (ms_out) ms_out[ri] = ms;
+        if (best < 0 || ms < best_ms) {
+            best = ri;
+            best_ms = ms;
+        }
+    }
+    h->rows_choice[algo] = best >= 0 ? best : saved;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return dev_err(e);
+    if (rc != QAP_OK) return rc;
+    return best >= 0 ? shape_rows(best) : QAP_E_UNSUPPORTED;
 }
 
 int qap_cost_async(qap_handle h, const int32_t *d_perms, int32_t k, int64_t *d_costs, void *stream) {
@@ -355,15 +511,6 @@ int qap_tabu_with_table_async(qap_handle h, int32_t *d_perms, const int32_t *d_t
 
 // ---- blocking host entry points: validate, copy in, run on a private stream, copy out
 
-namespace {
-
-struct HostCall {
-    hipStream_t st = nullptr;
-    ~HostCall() { if (st) (void)hipStreamDestroy(st); }
-    hipError_t init() { return hipStreamCreateWithFlags(&st, hipStreamNonBlocking); }
-};
-
-}  // namespace
 
 int qap_cost(qap_handle h, const int32_t *perms, int32_t k, int64_t *costs) {
     if (!h || k < 0 || (k > 0 && (!perms || !costs))) return QAP_E_INVALID;
@@ -448,28 +595,34 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
     if (!hs || !k_per || !lo_per || !hi_per || !seed_per || !out || m < 0 || iters < 0) return QAP_E_INVALID;
     *out = nullptr;
     std::vector<Item> items;
-    long long perm_off = 0, out_off = 0, table_off = 0;
+    long long perm_off = 0, out_off = 0, table_off = 0, tile_off = 0;
     size_t smem = 0, tsmem = 0;
     for (int i = 0; i < m; ++i) {
         qap_ctx *h = hs[i];
         if (!h || k_per[i] < 0 || lo_per[i] < 0 || lo_per[i] > hi_per[i]) return QAP_E_INVALID;
-        int rows = rows_per && rows_per[i] > 0 ? rows_per[i] : batch_rows(h);
-        const int ri = rows_index(rows);
-        if (rows < 0 || ri < 0 || ri > 2 || !batch_shape_ok(h->n, rows, h->tiles[ri].ntiles, h->sym)) return QAP_E_UNSUPPORTED;
-        const size_t sm = search_smem_bytes(h->n, rows, BATCH_LANES, h->sym);
-        if (sm > h->max_smem) return QAP_E_UNSUPPORTED;
+        const int ri = rows_per && rows_per[i] != 0 ? rows_index(rows_per[i]) : batch_shape(h);
+        if (ri < 0 || !batch_fits(h, ri)) return QAP_E_UNSUPPORTED;
+        const bool streamed = ri == kStream;
+        const TileSet &ts = shape_tiles(h, ri);
+        const size_t sm = streamed ? stream_smem_bytes(h->n, h->sym)
+                                   : search_smem_bytes(h->n, kRowsChoices[ri], BATCH_LANES, h->sym);
         smem = std::max(smem, sm);
         tsmem = std::max(tsmem, table_smem_bytes(h->n));
         for (int j = 0; j < k_per[i]; ++j) {
             Item it{};
             it.mats = h->d_mats;
-            it.tiles = h->tiles[ri].d_tiles;
+            it.tiles = ts.d_tiles;
             it.n = h->n;
             it.m = h->m;
             it.sym = h->sym;
-            it.ntiles = h->tiles[ri].ntiles;
-            it.ninterior = h->tiles[ri].ninterior;
-            it.rows = rows;
+            it.ntiles = ts.ntiles;
+            it.ninterior = ts.ninterior;
+            it.rows = streamed ? STREAM_ROWS : kRowsChoices[ri];
+            it.stream = streamed ? 1 : 0;
+            if (streamed) {
+                it.tile_off = tile_off;
+                tile_off += stream_tile_int4(ts.ntiles);
+            }
             it.iters = iters;
             it.lo = lo_per[i];
             it.hi = hi_per[i];
@@ -493,12 +646,14 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
     b->count = (int)items.size();
     b->perm_ints = perm_off;
     b->table_ints = table_off;
+    b->tile_int4 = tile_off;
     b->smem = smem;
     b->table_smem = tsmem;
     hipError_t e = hipSuccess;
     if (b->count > 0) {
         e = hipMalloc((void **)&b->d_items, items.size() * sizeof(Item));
         if (e == hipSuccess) e = hipMalloc((void **)&b->d_table, (size_t)table_off * sizeof(int32_t) + 16);
+        if (e == hipSuccess && tile_off > 0) e = hipMalloc((void **)&b->d_tile_work, (size_t)tile_off * sizeof(int4));
         if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
@@ -519,7 +674,7 @@ extern "C" int qap_batch_size(qap_batch_handle b, int64_t *starts_out, int64_t *
 extern "C" int qap_batch_tables_async(qap_batch_handle b, const int32_t *d_perms, void *stream) {
     if (!b || (b->count > 0 && !d_perms)) return QAP_E_INVALID;
     if (b->count == 0) return QAP_OK;
-    BatchArgs a{b->d_items, b->count, const_cast<int32_t *>(d_perms), nullptr, nullptr, b->d_table};
+    BatchArgs a{b->d_items, b->count, const_cast<int32_t *>(d_perms), nullptr, nullptr, b->d_table, b->d_tile_work};
     return dev_err(launch_table_batch(a, b->table_smem, (hipStream_t)stream));
 }
 
@@ -527,7 +682,7 @@ extern "C" int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int6
                                       void *stream) {
     if (!b || (b->count > 0 && (!d_perms || !d_best))) return QAP_E_INVALID;
     if (b->count == 0) return QAP_OK;
-    BatchArgs a{b->d_items, b->count, d_perms, d_best, d_done, b->d_table};
+    BatchArgs a{b->d_items, b->count, d_perms, d_best, d_done, b->d_table, b->d_tile_work};
     return dev_err(launch_batch(a, b->smem, (hipStream_t)stream));
 }
 
@@ -541,6 +696,7 @@ extern "C" int qap_batch_destroy(qap_batch_handle b) {
     if (!b) return QAP_OK;
     if (b->d_items) (void)hipFree(b->d_items);
     if (b->d_table) (void)hipFree(b->d_table);
+    if (b->d_tile_work) (void)hipFree(b->d_tile_work);
     delete b;
     return QAP_OK;
 }

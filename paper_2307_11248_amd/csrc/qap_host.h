@@ -1,0 +1,29 @@
+// qap_host.h -- host helpers shared by the C ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace qaph {
+
+// Tile heights of the search kernels.
+extern const int kRowsChoices[4];
+
+// Tiles of `rows` x 4 that hold at least one move (u < v), interior tiles first; each
+// entry is g | b << 16 (row group g, column block b).
+std::vector<int32_t> enumerate_tiles(int n, int rows, int *ninterior);
+
+// Range-check F and D (entries in [0, 255]) and pack [F | F^T | D | D^T] as u8 rows of
+// row_stride(n) bytes; *sym = 1 when F and D are both symmetric.  QAP_OK or QAP_E_RANGE.
+int pack_instance(const int32_t *F, const int32_t *D, int n, std::vector<uint8_t> &pack, int *sym);
+
+// Map a HIP status to a QAP code (QAP_VERBOSE in the environment also reports it).
+int dev_err_at(hipError_t e, const char *where);
+#define dev_err(e) ::qaph::dev_err_at((e), __func__)
+
+// Whether each of the k rows of perms is a permutation of 0..n-1.
+bool check_perms(const int32_t *perms, int k, int n);
+
+}  // namespace qaph

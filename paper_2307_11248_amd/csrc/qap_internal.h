@@ -45,14 +45,19 @@ struct Smem {
     int d, dt, g, gt, acbe, rpr, rps, kc, perm, bestp, pinv, ten, red, total;
 };
 
-__host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym) {
+// dglobal: D and D^T are read from global memory (the streamed kernels), not staged.
+__host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym, bool dglobal = false) {
     const int rs = row_stride(n);
     Smem s;
     int o = 0;
     auto take = [&o](int bytes) { int at = o; o += (bytes + 15) & ~15; return at; };
     auto take_mat = [&o]() { o = (o + 255) & ~255; return o; };   // matrices start on 256-byte boundaries
-    s.d = take_mat(); o += n * rs;
-    s.dt = sym ? s.d : take_mat(); if (!sym) o += n * rs;
+    if (dglobal) {
+        s.d = s.dt = -1;
+    } else {
+        s.d = take_mat(); o += n * rs;
+        s.dt = sym ? s.d : take_mat(); if (!sym) o += n * rs;
+    }
     s.g = take_mat(); o += n * rs;
     s.gt = sym ? s.g : take_mat(); if (!sym) o += n * rs;
     s.acbe = take(np * 8);
@@ -97,6 +102,8 @@ struct SearchArgs {
     long long start_base;
     int sym;
     int job0;                // search index of block 0
+    int4 *tile_work;         // streamed kernels: per search, tile_stride int4 of tile state
+    long long tile_stride;
 };
 
 // With QAP_VERBOSE set in the environment, report a failed HIP call on stderr.
@@ -137,7 +144,8 @@ struct Item {
     int64_t *cost_out;        // its cost
     int32_t *steps_out;       // moves made, or null
     SearchState *st;          // null: run from the start to `iters` in one go
-    int32_t *st_perm, *st_bestp, *st_table, *st_until;
+    int32_t *st_perm, *st_bestp;
+    int2 *st_du;              // chunked runs: (delta, tabu until) per packed pair index
     int n, m, sym, ntiles, ninterior, rows;
     int iters;                // tabu: last iteration of this run; 2opt: move cap (<= 0: none)
     int lo, hi;
@@ -146,6 +154,14 @@ struct Item {
     // batched launches: offsets of this item's start / result / neighbourhood in the
     // launch's buffers (the pointers above are filled from them on the device)
     long long perm_off, out_off, table_off;
+    // chunked runs (st != null): stop after about this many ticks of the device's
+    // constant-rate clock, at an iteration boundary; 0 = run to `iters`
+    long long budget;
+    // streamed kernels: the search's tiles in global memory, pass-major, one int4 per
+    // (pass, tile row, lane): deltas and tabu-until values (kept between chunks)
+    int4 *tile_d, *tile_u;
+    int stream;               // 1: the streamed kernel (tiles of STREAM_ROWS rows)
+    long long tile_off;       // batched launches: offset of tile_d in the launch's tile work
 };
 
 // The batched launch: one block per item of `items`; per-start buffers are shared by
@@ -157,6 +173,7 @@ struct BatchArgs {
     int64_t *best;
     int32_t *done;     // or null
     int32_t *table;    // neighbourhood of every start
+    int4 *tile_work;   // tile state of the searches that run streamed
 };
 
 hipError_t launch_cost(const TableArgs &a, hipStream_t st);
@@ -173,6 +190,21 @@ constexpr int BATCH_LANES = 512;
 int batch_shape_ok(int n, int rows, int ntiles, int sym);
 hipError_t launch_batch(const BatchArgs &b, size_t smem, hipStream_t st);
 int search_max_lanes(int rows);
+// Streamed kernels (any n up to 256): tiles of STREAM_ROWS x 4 slots kept in global memory
+// between passes, D read from global memory, BATCH_LANES lanes per search.
+constexpr int STREAM_ROWS = 8;
+int stream_shape_ok(int n, int sym, size_t max_smem);
+// int4 of tile state one streamed search needs (deltas, then tabu-until values)
+__host__ __device__ inline long long stream_tile_int4(int ntiles) {
+    const long long passes = (ntiles + BATCH_LANES - 1) / BATCH_LANES;
+    return 2 * passes * STREAM_ROWS * BATCH_LANES;
+}
+size_t stream_smem_bytes(int n, int sym);
+hipError_t launch_stream(bool tabu, const SearchArgs &a, int grid, hipStream_t st);
+// Chunked runs of resumable searches: one block per item, pointers absolute.  Tables of
+// items that start now (into their `table`), then one chunk of every item.
+hipError_t launch_table_items(const Item *d_items, int count, size_t smem, hipStream_t st);
+hipError_t launch_resume(const Item *d_items, int count, size_t smem, hipStream_t st);
 // Lanes of a search workgroup for a tile shape, or 0 if the shape cannot serve n.
 int search_lanes(int n, int rows, int ntiles, int sym);
 

@@ -184,19 +184,23 @@ __device__ inline void row_bytes(const uint8_t *row, int u0, unsigned (&w)[(ROWS
 // One whole search (or one chunk of it) by the calling workgroup; every lane of the
 // block takes part.  MAXT: (index, family) tasks one lane may carry (blockDim.x * MAXT
 // >= families * n).
-template <int ROWS, bool TABU, int MAXT, bool RESUME>
-__device__ void search_body(const Item &a, unsigned char *sm) {
+template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM>
+__device__ __attribute__((always_inline)) void search_body(const Item &a, unsigned char *sm) {
     __shared__ int s_bad;
+    __shared__ int s_chunk_end;   // chunked runs: set by thread 0 once the clock budget is spent
     const int n = a.n, rs = row_stride(n), L = blockDim.x, t = threadIdx.x;
     const int lane = t & 63, wid = t >> 6, W = L >> 6;
     const int sym = a.sym;
     const int nq = families(sym), lq = sym ? 1 : 2;
     const int np = padded_n(n, ROWS);
-    const Smem S = smem_plan(n, np, L, sym);
+    const Smem S = smem_plan(n, np, L, sym, STREAM);
     SearchState *const st = RESUME ? a.st : nullptr;   // saved state, chunked runs only
     const bool resume = RESUME && st != nullptr && st->it > 1;
 
-    uint8_t *Dm = sm + S.d, *DmT = sm + S.dt, *Gm = sm + S.g, *GmT = sm + S.gt;
+    // D and D^T: staged in LDS, or (streamed kernels) read in place from global memory
+    const uint8_t *Dm = STREAM ? a.mats + 2 * n * rs : sm + S.d;
+    const uint8_t *DmT = STREAM ? a.mats + 3 * n * rs : sm + S.dt;
+    uint8_t *Gm = sm + S.g, *GmT = sm + S.gt;
     int *rpr = reinterpret_cast<int *>(sm + S.rpr);
     int *rps = reinterpret_cast<int *>(sm + S.rps);
     int *kc = reinterpret_cast<int *>(sm + S.kc);
@@ -208,12 +212,12 @@ __device__ void search_body(const Item &a, unsigned char *sm) {
     long long *red = reinterpret_cast<long long *>(sm + S.red);
 
     // ---- stage D, D^T; read and check the start
-    {
+    if (!STREAM) {
         const int per = n * rs / 16;
         const uint4 *src = reinterpret_cast<const uint4 *>(a.mats);
         for (int i = t; i < per; i += L) {
-            reinterpret_cast<uint4 *>(Dm)[i] = src[2 * per + i];
-            if (!sym) reinterpret_cast<uint4 *>(DmT)[i] = src[3 * per + i];
+            reinterpret_cast<uint4 *>(sm + S.d)[i] = src[2 * per + i];
+            if (!sym) reinterpret_cast<uint4 *>(sm + S.dt)[i] = src[3 * per + i];
         }
     }
     if (t == 0) s_bad = 0;
@@ -292,37 +296,119 @@ __device__ void search_body(const Item &a, unsigned char *sm) {
         }
     }
 
-    // ---- this lane's tile, its deltas and tabu state
-    const bool active = t < a.ntiles;
-    int g = 0, b = 0;
-    if (active) {
-        const int tv = a.tiles[t];
-        g = tv & 0xffff;
-        b = tv >> 16;
+    // ---- iteration counter and tenure ring (before the tile loads, so that the Philox
+    //      draws do not overlap the loads in flight)
+    const long long start_id = a.start_id;
+    int it = resume ? st->it : 1, steps = 0;
+    const int it_first = it;
+    long long clock_end = 0;
+    if (RESUME && t == 0) {
+        s_chunk_end = 0;
+        clock_end = a.budget > 0 ? (long long)wall_clock64() + a.budget : 0;
     }
-    const int u0 = g * ROWS, v0 = b * TILE_COLS;
-    const bool boundary = active && t >= a.ninterior;
-    int dl[ROWS][4];
-    int ut[TABU ? ROWS : 1][4];
-    {
-        const int32_t *tab = resume ? a.st_table : a.table;
+    int tpos = (it - 1) % L;   // (it - 1) mod L, the tenure ring slot
+    if (TABU && tpos != 0) ten[t] = draw_tenure(a.seed, (long long)(it - tpos) + t, start_id, a.lo, a.hi);
+
+    // ---- tiles.  A tile is `ROWS` x 4 neighbourhood slots (u, v) = (u0 + j, v0 + e) held
+    //      in registers: dl the deltas, ut the iteration until which the move is tabu.
+    //      Register kernels: lane t holds tile t for the whole search.  Streamed kernels:
+    //      lane t handles tiles t, t + L, t + 2L, ... one pass at a time, kept in global
+    //      memory between passes (tile_d, tile_u, one int4 per (pass, row, lane)).
+    constexpr int UTR = TABU ? ROWS : 1;
+    constexpr long long NO_MOVE = ((long long)INT32_MAX << 32) | (unsigned)KEY_NONE;
+    // slot values of tile (g, b) at the start of the search
+    auto load_tile = [&](int (&d)[ROWS][4], int (&u_)[UTR][4], int tu0, int tv0, bool act) {
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int u = u0 + j, v = v0 + e;
-                const bool real = active && u < n && v < n && u != v;
-                const long long ix = real ? pidx(n, u < v ? u : v, u < v ? v : u) : 0;
-                dl[j][e] = real ? tab[ix] : BIG;
-                if (TABU) ut[j][e] = real ? (resume ? a.st_until[ix] : 0) : INT32_MAX;
+                const int u = tu0 + j, v = tv0 + e;
+                const bool real = act && u < n && v < n && u != v;
+                const int ix = real ? (int)pidx(n, u < v ? u : v, u < v ? v : u) : 0;
+                if (!STREAM && RESUME && resume) {
+                    // (delta, tabu until) of the slot, saved by the previous chunk
+                    const int2 du = real ? a.st_du[ix] : make_int2(BIG, INT32_MAX);
+                    d[j][e] = du.x;
+                    if (TABU) u_[j][e] = du.y;
+                } else {
+                    d[j][e] = real ? a.table[ix] : BIG;
+                    if (TABU) u_[j][e] = real ? 0 : INT32_MAX;
+                }
             }
+        }
+    };
+    // lowest admissible slot of a tile at iteration itx (aspiration threshold thr), as
+    // (delta << 32 | key), key = u << 9 | v; slots are scanned in key order
+    auto tile_min = [&](const int (&d)[ROWS][4], const int (&u_)[UTR][4], int tu0, int tv0, int itx,
+                        int thr) -> long long {
+        int bd = INT32_MAX, bs = -1;
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = d[j][e];
+                const bool adm = TABU ? (u_[j][e] <= itx || x < thr) : true;
+                if (adm && x < bd) { bd = x; bs = j * 4 + e; }
+            }
+        }
+        const int key = bs < 0 ? KEY_NONE : (((tu0 + (bs >> 2)) << 9) | (tv0 + (bs & 3)));
+        return ((long long)bd << 32) | (unsigned)key;
+    };
+    auto aspiration = [&]() -> int {
+        if (!TABU) return 0;
+        const long long d = best - cur;  // aspiration: cur + delta < best
+        return d < (long long)INT32_MIN ? INT32_MIN : (int)d;
+    };
+    const int npass = STREAM ? (a.ntiles + L - 1) / L : 1;
+    auto tile_of = [&](int tix, int &g, int &b) {
+        const int tv = a.tiles[tix];
+        g = tv & 0xffff;
+        b = tv >> 16;
+    };
+    auto tile_addr = [&](int q, int j) { return (q * ROWS + j) * L + t; };
+
+    // register kernels: this lane's tile
+    const bool active = !STREAM && t < a.ntiles;
+    int g = 0, b = 0;
+    if (active) tile_of(t, g, b);
+    const int u0 = g * ROWS, v0 = b * TILE_COLS;
+    const bool boundary = active && t >= a.ninterior;
+    int dl[ROWS][4];
+    int ut[UTR][4];
+    long long sel = NO_MOVE;   // streamed kernels: this lane's candidate for the next select
+    if (!STREAM) {
+        load_tile(dl, ut, u0, v0, active);
+    } else {
+        const int thr = aspiration();
+        for (int q = 0; q < npass; ++q) {
+            const int tix = t + q * L;
+            if (tix >= a.ntiles) break;
+            int tg, tb;
+            tile_of(tix, tg, tb);
+            int d[ROWS][4], u_[UTR][4];
+            if (RESUME && resume) {
+#pragma unroll
+                for (int j = 0; j < ROWS; ++j) {
+                    const int4 x = a.tile_d[tile_addr(q, j)];
+                    d[j][0] = x.x; d[j][1] = x.y; d[j][2] = x.z; d[j][3] = x.w;
+                    if (TABU) {
+                        const int4 y = a.tile_u[tile_addr(q, j)];
+                        u_[j][0] = y.x; u_[j][1] = y.y; u_[j][2] = y.z; u_[j][3] = y.w;
+                    }
+                }
+            } else {
+                load_tile(d, u_, tg * ROWS, tb * TILE_COLS, true);
+#pragma unroll
+                for (int j = 0; j < ROWS; ++j) {
+                    a.tile_d[tile_addr(q, j)] = make_int4(d[j][0], d[j][1], d[j][2], d[j][3]);
+                    if (TABU) a.tile_u[tile_addr(q, j)] = make_int4(u_[j][0], u_[j][1], u_[j][2], u_[j][3]);
+                }
+            }
+            const long long c = tile_min(d, u_, tg * ROWS, tb * TILE_COLS, it, thr);
+            sel = c < sel ? c : sel;
         }
     }
     if (t >= W && t < 16) red[t] = LLONG_MAX;   // unused wave-minimum slots
-    const long long start_id = a.start_id;
-    int it = resume ? st->it : 1, steps = 0;
-    int tpos = (it - 1) % L;   // (it - 1) mod L, the tenure ring slot
-    if (TABU && tpos != 0) ten[t] = draw_tenure(a.seed, (long long)(it - tpos) + t, start_id, a.lo, a.hi);
     bool stopped = false;
     __syncthreads();
 
@@ -332,27 +418,16 @@ __device__ void search_body(const Item &a, unsigned char *sm) {
         } else {
             if (steps >= (a.iters > 0 ? a.iters : TWO_OPT_MAX_MOVES)) break;
         }
-        // ---- select: lowest (delta, key) over the admissible slots
-        int thr = 0;
-        if (TABU) {
-            const long long d = best - cur;  // aspiration: cur + delta < best
-            thr = d < (long long)INT32_MIN ? INT32_MIN : (int)d;
-        }
-        int bd = INT32_MAX, bs = -1;
-#pragma unroll
-        for (int j = 0; j < ROWS; ++j) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int x = dl[j][e];
-                const bool adm = TABU ? (ut[j][e] <= it || x < thr) : true;
-                if (adm && x < bd) { bd = x; bs = j * 4 + e; }
-            }
-        }
-        if (!active) bd = INT32_MAX;
-        const int key = (bs < 0 || !active) ? KEY_NONE : (((u0 + (bs >> 2)) << 9) | (v0 + (bs & 3)));
-        const long long kw = wave_min64(((long long)bd << 32) | (unsigned)key);
+        // chunk end: decided by thread 0 every 16 iterations, read by all after B1
+        if (RESUME && t == 0 && clock_end != 0 && it != it_first && (it & 15) == 0)
+            s_chunk_end = (long long)wall_clock64() >= clock_end;
+        // ---- select: lowest (delta, key) over the admissible slots (streamed kernels
+        //      found their lane's candidate while updating the tiles)
+        if (!STREAM) sel = active ? tile_min(dl, ut, u0, v0, it, aspiration()) : NO_MOVE;
+        const long long kw = wave_min64(sel);
         if (lane == 0) red[wid] = kw;
         __syncthreads();  // B1
+        if (RESUME && s_chunk_end) break;   // uniform: every lane reads the same word
         // workgroup minimum: the W wave minima, two per 16-byte load (slots past W hold
         // the largest key)
         long long mk = LLONG_MAX;
@@ -571,10 +646,13 @@ __device__ void search_body(const Item &a, unsigned char *sm) {
             perm[r] = ps;
             perm[s] = pr;
         }
-        // ---- C: the tile follows the move
-        if (active) {
-            const int2 kk = *reinterpret_cast<const int2 *>(kc);
-            const int kr = __builtin_amdgcn_readfirstlane(kk.x), ks = __builtin_amdgcn_readfirstlane(kk.y);
+        // ---- C: the tiles follow the move
+        const int2 kk = *reinterpret_cast<const int2 *>(kc);
+        const int kr = __builtin_amdgcn_readfirstlane(kk.x), ks = __builtin_amdgcn_readfirstlane(kk.y);
+        const int until = TABU ? it + ten[tpos] : 0;
+        // returns whether the move or its mirror lies in this tile (its tabu state changed)
+        auto move_tile = [&](int (&dl)[ROWS][4], int (&ut)[UTR][4], int g, int b, bool boundary) -> bool {
+            const int u0 = g * ROWS, v0 = b * TILE_COLS;
             int acu[ROWS], beu[ROWS], acv[4], bev[4];
             {
                 const int4 c01 = reinterpret_cast<const int4 *>(acbe + 2 * v0)[0];
@@ -598,7 +676,6 @@ __device__ void search_body(const Item &a, unsigned char *sm) {
                 rpru[j] = x2.x; rpru[j + 1] = x2.y;
                 rpsu[j] = y2.x; rpsu[j + 1] = y2.y;
             }
-            const int until = TABU ? it + ten[tpos] : 0;
 #pragma unroll
             for (int j = 0; j < ROWS; ++j) {
 #pragma unroll
@@ -645,8 +722,10 @@ __device__ void search_body(const Item &a, unsigned char *sm) {
                         for (int j = 0; j < ROWS; ++j) dl[j][e] = rpsu[j] - ks;
                     }
             }
+            bool tabu_set = false;
             if (TABU) {
                 // the move and its mirror become tabu until iteration it + t
+                tabu_set = (g == r / ROWS && b == (s >> 2)) || (g == s / ROWS && b == (r >> 2));
                 if (g == r / ROWS && b == (s >> 2)) {
 #pragma unroll
                     for (int j = 0; j < ROWS; ++j)
@@ -669,6 +748,39 @@ __device__ void search_body(const Item &a, unsigned char *sm) {
                     for (int e = 0; e < 4; ++e)
                         if (u0 + j >= n || v0 + e >= n) dl[j][e] = BIG;
             }
+            return tabu_set;
+        };
+        if (!STREAM) {
+            if (active) move_tile(dl, ut, g, b, boundary);
+        } else {
+            // each pass: load, update, find the lane's candidate for the next iteration
+            // (it + 1, with cur and best after this move), store
+            const int thr = aspiration();
+            sel = NO_MOVE;
+            for (int q = 0; q < npass; ++q) {
+                const int tix = t + q * L;
+                if (tix >= a.ntiles) break;
+                int tg, tb;
+                tile_of(tix, tg, tb);
+                int d[ROWS][4], u_[UTR][4];
+#pragma unroll
+                for (int j = 0; j < ROWS; ++j) {
+                    const int4 x = a.tile_d[tile_addr(q, j)];
+                    d[j][0] = x.x; d[j][1] = x.y; d[j][2] = x.z; d[j][3] = x.w;
+                    if (TABU) {
+                        const int4 y = a.tile_u[tile_addr(q, j)];
+                        u_[j][0] = y.x; u_[j][1] = y.y; u_[j][2] = y.z; u_[j][3] = y.w;
+                    }
+                }
+                const bool changed = move_tile(d, u_, tg, tb, tix >= a.ninterior);
+#pragma unroll
+                for (int j = 0; j < ROWS; ++j) {
+                    a.tile_d[tile_addr(q, j)] = make_int4(d[j][0], d[j][1], d[j][2], d[j][3]);
+                    if (TABU && changed) a.tile_u[tile_addr(q, j)] = make_int4(u_[j][0], u_[j][1], u_[j][2], u_[j][3]);
+                }
+                const long long c = tile_min(d, u_, tg * ROWS, tb * TILE_COLS, it + 1, thr);
+                sel = c < sel ? c : sel;
+            }
         }
         if (TABU && ++tpos == L) tpos = 0;
         if (TABU) ++it; else ++steps;
@@ -679,16 +791,20 @@ __device__ void search_body(const Item &a, unsigned char *sm) {
     const int moves = TABU ? it - 1 : steps;
     const bool finished = st == nullptr || !TABU || stopped || it > a.iters;
     if (st != nullptr) {
-        // save the search so a later run resumes it exactly where it stopped
+        // save the search so a later run resumes it exactly where it stopped (opaque
+        // copies of the tile origin: the slot indices are recomputed here rather than
+        // kept live through the search from the load above)
+        int su0 = u0, sv0 = v0;
+        asm volatile("" : "+v"(su0), "+v"(sv0));
+        if (!STREAM && !finished)
 #pragma unroll
         for (int j = 0; j < ROWS; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int u = u0 + j, v = v0 + e;
+                const int u = su0 + j, v = sv0 + e;
                 if (active && u < v && v < n) {
                     const long long ix = pidx(n, u, v);
-                    a.st_table[ix] = dl[j][e];
-                    if (TABU) a.st_until[ix] = ut[j][e];
+                    a.st_du[ix] = make_int2(dl[j][e], TABU ? ut[j][e] : 0);
                 }
             }
         for (int u = t; u < n; u += L) {
@@ -739,7 +855,7 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
     it.hi = a.hi;
     it.seed = a.seed;
     it.start_id = a.start_base + job;
-    search_body<ROWS, TABU, max_tasks<ROWS>(), false>(it, sm);
+    search_body<ROWS, TABU, max_tasks<ROWS>(), false, false>(it, sm);
 }
 
 // The batched launch: block i runs item i as one tabu search with the item's tile
@@ -753,11 +869,62 @@ __global__ void __launch_bounds__(BATCH_LANES) batch_kernel(BatchArgs b) {
     it.cost_out = b.best + it.out_off;
     it.steps_out = b.done ? b.done + it.out_off : nullptr;
     it.table = b.table + it.table_off;
-    switch (it.rows) {
-        case 2: search_body<2, true, 1024 / BATCH_LANES, false>(it, sm); break;
-        case 4: search_body<4, true, 1024 / BATCH_LANES, false>(it, sm); break;
-        default: search_body<8, true, 1024 / BATCH_LANES, false>(it, sm); break;
+    if (it.stream) {
+        it.tile_d = b.tile_work + it.tile_off;
+        it.tile_u = it.tile_d + stream_tile_int4(it.ntiles) / 2;
+        search_body<STREAM_ROWS, true, 1024 / BATCH_LANES, false, true>(it, sm);
+        return;
     }
+    switch (it.rows) {
+        case 2: search_body<2, true, 1024 / BATCH_LANES, false, false>(it, sm); break;
+        case 4: search_body<4, true, 1024 / BATCH_LANES, false, false>(it, sm); break;
+        default: search_body<8, true, 1024 / BATCH_LANES, false, false>(it, sm); break;
+    }
+}
+
+// Chunked runs: block i runs one chunk of items[i] (absolute pointers, st != null).
+__global__ void __launch_bounds__(BATCH_LANES) resume_kernel(const Item *items) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    const Item it = items[blockIdx.x];
+    if (it.stream) {
+        search_body<STREAM_ROWS, true, 1024 / BATCH_LANES, true, true>(it, sm);
+        return;
+    }
+    switch (it.rows) {
+        case 2: search_body<2, true, 1024 / BATCH_LANES, true, false>(it, sm); break;
+        case 4: search_body<4, true, 1024 / BATCH_LANES, true, false>(it, sm); break;
+        default: search_body<8, true, 1024 / BATCH_LANES, true, false>(it, sm); break;
+    }
+}
+
+// Streamed search, one per workgroup: block b runs search job0 + b of the launch.
+template <bool TABU>
+__global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    const int job = a.job0 + blockIdx.x;
+    Item it{};
+    it.mats = a.mats;
+    it.tiles = a.tiles;
+    it.table = a.table + (size_t)job * a.m;
+    it.perm_in = a.perms_in + (size_t)job * a.n;
+    it.perm_out = a.perm_out + (size_t)job * a.n;
+    it.cost_out = a.cost_out + job;
+    it.steps_out = a.steps_out ? a.steps_out + job : nullptr;
+    it.n = a.n;
+    it.m = a.m;
+    it.sym = a.sym;
+    it.ntiles = a.ntiles;
+    it.ninterior = a.ninterior;
+    it.rows = STREAM_ROWS;
+    it.iters = a.iters;
+    it.lo = a.lo;
+    it.hi = a.hi;
+    it.seed = a.seed;
+    it.start_id = a.start_base + job;
+    it.stream = 1;
+    it.tile_d = a.tile_work + (size_t)blockIdx.x * a.tile_stride;
+    it.tile_u = it.tile_d + a.tile_stride / 2;
+    search_body<STREAM_ROWS, TABU, 1024 / BATCH_LANES, false, true>(it, sm);
 }
 
 template <int ROWS, bool TABU>
@@ -795,6 +962,31 @@ hipError_t launch_batch(const BatchArgs &b, size_t smem, hipStream_t st) {
     if (b.count <= 0) return hipSuccess;
     hipLaunchKernelGGL(batch_kernel, dim3(b.count), dim3(BATCH_LANES), smem, st, b);
     return report(hipGetLastError(), "batch kernel launch");
+}
+
+hipError_t launch_resume(const Item *d_items, int count, size_t smem, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(resume_kernel, dim3(count), dim3(BATCH_LANES), smem, st, d_items);
+    return report(hipGetLastError(), "resume kernel launch");
+}
+
+size_t stream_smem_bytes(int n, int sym) {
+    return (size_t)smem_plan(n, padded_n(n, STREAM_ROWS), BATCH_LANES, sym, true).total;
+}
+
+int stream_shape_ok(int n, int sym, size_t max_smem) {
+    return families(sym) * n <= 1024 && stream_smem_bytes(n, sym) <= max_smem ? 1 : 0;
+}
+
+// grid = searches in this launch; a.tile_work holds grid * a.tile_stride int4.
+hipError_t launch_stream(bool tabu, const SearchArgs &a, int grid, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    const size_t smem = stream_smem_bytes(a.n, a.sym);
+    if (tabu)
+        hipLaunchKernelGGL(stream_kernel<true>, dim3(grid), dim3(BATCH_LANES), smem, st, a);
+    else
+        hipLaunchKernelGGL(stream_kernel<false>, dim3(grid), dim3(BATCH_LANES), smem, st, a);
+    return report(hipGetLastError(), "stream kernel launch");
 }
 
 size_t search_smem_bytes(int n, int rows, int lanes, int sym) {

@@ -107,6 +107,24 @@ __global__ void __launch_bounds__(256) table_batch_kernel(BatchArgs b) {
     table_body(n, Fm, Dm, perm, a.table);
 }
 
+// Tables of starting items of a chunked run: block i writes items[i]'s neighbourhood
+// into its `table`.
+__global__ void __launch_bounds__(256) table_items_kernel(const Item *items) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    __shared__ int bad;
+    const Item &it = items[blockIdx.x];
+    TableArgs a{it.mats, it.perm_in, nullptr, const_cast<int32_t *>(it.table), it.n, it.m, 1};
+    const int n = it.n, rs = row_stride(n), t = threadIdx.x;
+    uint8_t *Fm = sm, *Dm = sm + n * rs;
+    int *perm = reinterpret_cast<int *>(sm + 2 * n * rs);
+    int *pinv = perm + n;
+    if (!stage_f_d_perm(a, 0, Fm, Dm, perm, pinv, &bad)) {
+        for (int i = t; i < it.m; i += blockDim.x) a.table[i] = 0;
+        return;
+    }
+    table_body(n, Fm, Dm, perm, a.table);
+}
+
 __device__ void table_body(int n, const uint8_t *Fm, const uint8_t *Dm, const int *perm, int32_t *out) {
     const int rs = row_stride(n), t = threadIdx.x;
     for (int u = 0; u < n - 1; ++u) {
@@ -140,6 +158,12 @@ hipError_t launch_table_batch(const BatchArgs &b, size_t smem, hipStream_t st) {
     if (b.count <= 0) return hipSuccess;
     hipLaunchKernelGGL(table_batch_kernel, dim3(b.count), dim3(256), smem, st, b);
     return report(hipGetLastError(), "batch table kernel launch");
+}
+
+hipError_t launch_table_items(const Item *d_items, int count, size_t smem, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(table_items_kernel, dim3(count), dim3(256), smem, st, d_items);
+    return report(hipGetLastError(), "item table kernel launch");
 }
 
 hipError_t launch_cost(const TableArgs &a, hipStream_t st) {

@@ -32,7 +32,11 @@ EXPORTS = [
     "qap_tabu_async", "qap_tabu_plain_async", "qap_2opt_with_table_async", "qap_tabu_with_table_async",
     "qap_set_tile_rows", "qap_get_tile_rows", "qap_batch_create", "qap_batch_size", "qap_batch_run_async",
     "qap_batch_tables_async", "qap_batch_search_async", "qap_batch_destroy", "qap_tabu_batch",
+    "qap_tune_tile_rows", "qap_server_create", "qap_server_footprint", "qap_server_submit", "qap_server_step",
+    "qap_server_result", "qap_server_stats", "qap_server_destroy",
 ]
+
+ALGOS = {"tabu": 0, "2opt": 1, "batch": 2}
 
 _lib = None
 _lock = threading.Lock()
@@ -78,6 +82,15 @@ def lib():
                                                              _vp, _vp]),
                 "qap_set_tile_rows": (ctypes.c_int, [_vp, i32, i32]),
                 "qap_get_tile_rows": (ctypes.c_int, [_vp, i32, _i32p]),
+                "qap_tune_tile_rows": (ctypes.c_int, [_vp, i32, i32, i32, ctypes.POINTER(ctypes.c_float)]),
+                "qap_server_create": (ctypes.c_int, [i64, i32, ctypes.c_double, ctypes.POINTER(_vp)]),
+                "qap_server_footprint": (i64, [_vp, i32, i32]),
+                "qap_server_submit": (ctypes.c_int, [_vp, _i32p, _i32p, i32, _i32p, i32, i32, i32, u64, _i64p]),
+                "qap_server_step": (ctypes.c_int, [_vp, _i32p, _i32p]),
+                "qap_server_result": (ctypes.c_int, [_vp, i64, _i32p, _i64p, _i32p,
+                                                     ctypes.POINTER(ctypes.c_double)]),
+                "qap_server_stats": (ctypes.c_int, [_vp, _i64p]),
+                "qap_server_destroy": (ctypes.c_int, [_vp]),
                 "qap_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), i32, _i32p, i32, _i32p, _i32p, _u64p,
                                                     _i32p, ctypes.POINTER(_vp)]),
                 "qap_batch_size": (ctypes.c_int, [_vp, _i64p, _i64p]),
@@ -97,6 +110,14 @@ def lib():
 
 def _check(rc: int, what: str) -> int:
     if rc < 0:
+        raise QapError(rc, what)
+    return rc
+
+
+def _check_rows(rc: int, what: str) -> int:
+    """Tile rows are returned as 2, 4, 8, 16 or -8 (the streamed kernel); other negative
+    values are error codes."""
+    if rc < 0 and rc != -8:
         raise QapError(rc, what)
     return rc
 
@@ -141,6 +162,7 @@ class Handle:
         self._h = h
         self.n = n
         self.m = n * (n - 1) // 2
+        self.sym = bool((F == F.T).all() and (D == D.T).all())
 
     @property
     def ptr(self):
@@ -165,15 +187,22 @@ class Handle:
     def __exit__(self, *exc):
         self.close()
 
-    # -- tile shape (thread configuration)
+    # -- tile shape (thread configuration); algo is "tabu", "2opt" or "batch"
     def set_tile_rows(self, algo: str, rows: int):
-        _check(lib().qap_set_tile_rows(self.ptr, 0 if algo == "tabu" else 1, int(rows)), "qap_set_tile_rows")
+        _check(lib().qap_set_tile_rows(self.ptr, ALGOS[algo], int(rows)), "qap_set_tile_rows")
 
     def tile_rows(self, algo: str):
         lanes = ctypes.c_int32(0)
-        rows = _check(lib().qap_get_tile_rows(self.ptr, 0 if algo == "tabu" else 1, ctypes.byref(lanes)),
-                      "qap_get_tile_rows")
+        rows = _check_rows(lib().qap_get_tile_rows(self.ptr, ALGOS[algo], ctypes.byref(lanes)), "qap_get_tile_rows")
         return rows, lanes.value
+
+    def tune_tile_rows(self, algo: str, k: int = 256, iters: int = 300):
+        """Time every fitting shape on the device and keep the fastest (``qap_tune_tile_rows``).
+        Returns (rows, {rows: ms} for the shapes that fit)."""
+        ms = (ctypes.c_float * 5)()
+        rows = _check_rows(lib().qap_tune_tile_rows(self.ptr, ALGOS[algo], int(k), int(iters), ms),
+                           "qap_tune_tile_rows")
+        return rows, {r: float(t) for r, t in zip((2, 4, 8, 16, -8), ms) if t >= 0}
 
     # -- blocking host calls
     def cost(self, perms) -> np.ndarray:
@@ -317,3 +346,71 @@ def tabu_batch(handles, perms, ks, iters, lo, hi, seeds):
                                 _ptr(hi, _i32p), _ptr(seeds, _u64p), _ptr(best, _i64p), _ptr(done, _i32p)),
            "qap_tabu_batch")
     return p, best, done
+
+
+class Server:
+    """Continuous-batching tabu server (``qap_server_*``): submit requests, call step()
+    repeatedly, collect results by ticket."""
+
+    def __init__(self, pool_bytes: int = 1 << 30, max_active: int = 256, chunk_ms: float = 2.0):
+        s = _vp()
+        _check(lib().qap_server_create(int(pool_bytes), int(max_active), float(chunk_ms), ctypes.byref(s)),
+               "qap_server_create")
+        self._s = s
+        self._n = {}
+
+    def footprint(self, n: int, sym: bool = False) -> int:
+        """Device bytes a request of size n takes from the pool while admitted."""
+        return _check(lib().qap_server_footprint(self._s, int(n), int(bool(sym))), "qap_server_footprint")
+
+    def submit(self, F, D, start, iters: int, lo: int, hi: int, seed: int) -> int:
+        F = _arr(F, np.int32)
+        n = F.shape[0]
+        D = _arr(D, np.int32, (n, n))
+        start = _arr(start, np.int32, (n,))
+        t = ctypes.c_int64(0)
+        _check(lib().qap_server_submit(self._s, _ptr(F, _i32p), _ptr(D, _i32p), n, _ptr(start, _i32p), int(iters),
+                                       int(lo), int(hi), int(seed), ctypes.byref(t)), "qap_server_submit")
+        self._n[t.value] = n
+        return t.value
+
+    def step(self):
+        """One admission + chunk; returns (finished, running, queued)."""
+        a, p = ctypes.c_int32(0), ctypes.c_int32(0)
+        f = _check(lib().qap_server_step(self._s, ctypes.byref(a), ctypes.byref(p)), "qap_server_step")
+        return f, a.value, p.value
+
+    def result(self, ticket: int):
+        """None while queued or running, else (best permutation, best cost, moves, latency ms, queued ms)."""
+        n = self._n[ticket]
+        perm = np.zeros(n, dtype=np.int32)
+        best, moves = ctypes.c_int64(0), ctypes.c_int32(0)
+        lat = (ctypes.c_double * 2)()
+        rc = _check(lib().qap_server_result(self._s, int(ticket), _ptr(perm, _i32p), ctypes.byref(best),
+                                            ctypes.byref(moves), lat), "qap_server_result")
+        if rc == 0:
+            return None
+        del self._n[ticket]
+        return perm, best.value, moves.value, lat[0], lat[1]
+
+    def stats(self) -> dict:
+        out = np.zeros(6, dtype=np.int64)
+        _check(lib().qap_server_stats(self._s, _ptr(out, _i64p)), "qap_server_stats")
+        return dict(zip(("running", "queued", "pool_used", "pool_bytes", "steps", "chunks"), out.tolist()))
+
+    def close(self):
+        if getattr(self, "_s", None) is not None:
+            lib().qap_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

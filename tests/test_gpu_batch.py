@@ -111,8 +111,11 @@ def test_batch_rejects_unsupported_and_bad_input():
     rng = np.random.default_rng(5)
     F, D = W.random_instance(rng, 256, 0, 99)
     with qap.Handle(F, D) as big, qap.Handle(*W.random_instance(rng, 10, 0, 9)) as small:
-        with pytest.raises(qap.QapError) as ei:
-            qap.Batch([small, big], [1, 1], 100, [1, 1], [3, 30], [1, 2])
+        with pytest.raises(qap.QapError) as ei:   # register tiles of 2 rows cannot hold n = 256
+            qap.Batch([small, big], [1, 1], 100, [1, 1], [3, 30], [1, 2], rows=[2, 2])
+        assert ei.value.code == qap.QAP_E_UNSUPPORTED
+        with pytest.raises(qap.QapError) as ei:   # 16-row tiles do not exist in the batched kernel
+            qap.Batch([small], [1], 100, [1], [3], [1], rows=[16])
         assert ei.value.code == qap.QAP_E_UNSUPPORTED
         bad = np.arange(10, dtype=np.int32)
         bad[3] = 4
@@ -173,5 +176,44 @@ def test_batch_full_size_graph_replay_sampled():
         n = insts[t].n
         got = ep[off[t] + j * n: off[t] + (j + 1) * n]
         assert (got == r[0]).all() and ec[t * k + j] == r[1] and ed[t * k + j] == r[2], (t, j)
+    for h in hs:
+        h.close()
+
+
+@pytest.mark.parametrize("n,sym", [(24, False), (64, False), (100, True), (150, False)])
+def test_tuner_picks_a_fitting_shape_and_results_do_not_change(n, sym):
+    rng = np.random.default_rng(n)
+    F, D = W.random_instance(rng, n, 0, 99, symmetric=sym)
+    perms = W.starts(rng, n, 3)
+    lo, hi = W.tabu_tenure_range(n)
+    note("tuner n=%d sym=%s" % (n, sym))
+    with qap.Handle(F, D) as h:
+        ref = h.tabu(perms, 300, lo, hi, 11)
+        for algo in ("tabu", "2opt", "batch"):
+            rows, times = h.tune_tile_rows(algo, k=32, iters=100)
+            assert rows in times and all(t > 0 for t in times.values()), (algo, times)
+            assert rows == min(times, key=times.get)
+            assert h.tile_rows(algo)[0] == rows
+        got = h.tabu(perms, 300, lo, hi, 11)
+        assert all((a == b).all() for a, b in zip(ref, got))
+        p, c, d = qap.tabu_batch([h], perms.reshape(-1), [3], 300, [lo], [hi], [11])
+        assert (p.reshape(3, n) == ref[0]).all() and (c == ref[1]).all() and (d == ref[2]).all()
+
+
+def test_tile_cache_round_trip(tmp_path):
+    from paper_2307_11248_amd.autotune import TileCache
+    rng = np.random.default_rng(3)
+    insts = [W.random_instance(rng, n, 0, 99) for n in (30, 30, 77)]
+    hs = [qap.Handle(F, D) for F, D in insts]
+    path = str(tmp_path / "tiles.json")
+    note("tile cache round trip")
+    c1 = TileCache(path, k=32, iters=100)
+    rows1 = c1.apply_all(hs, "batch")
+    c1.save()
+    assert c1.tuned == 2 and rows1[0] == rows1[1]
+    c2 = TileCache(path, k=32, iters=100)
+    rows2 = c2.apply_all(hs, "batch")
+    assert c2.tuned == 0 and rows2 == rows1
+    assert [h.tile_rows("batch")[0] for h in hs] == rows1
     for h in hs:
         h.close()

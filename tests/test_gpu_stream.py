@@ -1,0 +1,115 @@
+"""GPU parity of the streamed kernels, which serve every n up to 256.
+
+Above n = 176 the register tiles of one workgroup no longer hold the neighbourhood, and
+for asymmetric instances above about 180 the four u8 matrices no longer fit in LDS.  The
+streamed kernels keep the tiles in global memory (several passes per iteration) and read
+D in place.  Every case is compared bit for bit with the oracle: plain searches, searches
+inside a batch next to register-tile searches, and served requests.
+"""
+import os
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_11248_amd import qap
+from paper_2307_11248_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+WORKERS = max(1, min(16, os.cpu_count() or 1))
+
+
+def note(msg):
+    sys.__stderr__.write("[gpu-case] %s\n" % msg)
+    sys.__stderr__.flush()
+
+
+def pmap(f, items):
+    with ThreadPoolExecutor(WORKERS) as ex:
+        return list(ex.map(f, items))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.init()
+    yield
+
+
+@pytest.mark.parametrize("n,sym,diag", [(177, False, False), (193, True, False), (200, False, True),
+                                        (256, False, False), (256, True, True)])
+def test_large_n_tabu_and_two_opt(n, sym, diag):
+    rng = np.random.default_rng(7000 + n)
+    F, D = W.random_instance(rng, n, 0, 99, symmetric=sym, diag=diag)
+    perms = W.starts(rng, n, 3)
+    lo, hi = W.tabu_tenure_range(n)
+    iters = 400
+    note("streamed n=%d sym=%s" % (n, sym))
+    with qap.Handle(F, D) as h:
+        assert h.tile_rows("tabu")[0] == -8 and h.tile_rows("2opt")[0] == -8
+        p, c, d = h.tabu(perms, iters, lo, hi, 123)
+        q, qc, qs = h.two_opt(perms, max_iters=60)
+    res = pmap(lambda j: oracle.tabu(F, D, perms[j], iters, lo, hi, 123, j), range(3))
+    for j, r in enumerate(res):
+        assert (p[j] == r[0]).all() and c[j] == r[1] and d[j] == r[2], j
+    res = pmap(lambda j: oracle.two_opt(F, D, perms[j], max_iters=60), range(3))
+    for j, r in enumerate(res):
+        assert (q[j] == r[0]).all() and qc[j] == r[1] and qs[j] == r[2], j
+
+
+def test_large_n_batch_next_to_register_tiles():
+    rng = np.random.default_rng(77)
+    sizes = [256, 40, 190, 100]
+    insts = [W.random_instance(rng, n, 0, 99) for n in sizes]
+    starts = [W.starts(rng, n, 2) for n in sizes]
+    tl = [W.tabu_tenure_range(n) for n in sizes]
+    seeds = [5, 6, 7, 8]
+    iters = 300
+    note("streamed in a batch, sizes %s" % sizes)
+    hs = [qap.Handle(F, D) for F, D in insts]
+    assert [h.tile_rows("batch")[0] for h in hs] == [-8, 2, -8, 4]
+    perms = np.concatenate([s.reshape(-1) for s in starts])
+    p, c, d = qap.tabu_batch(hs, perms, [2] * 4, iters, [a for a, _ in tl], [b for _, b in tl], seeds)
+    jobs = [(i, j) for i in range(4) for j in range(2)]
+    res = pmap(lambda a: oracle.tabu(insts[a[0]][0], insts[a[0]][1], starts[a[0]][a[1]], iters,
+                                     tl[a[0]][0], tl[a[0]][1], seeds[a[0]], a[1]), jobs)
+    off = 0
+    for row, ((i, j), r) in enumerate(zip(jobs, res)):
+        n = sizes[i]
+        assert (p[off:off + n] == r[0]).all() and c[row] == r[1] and d[row] == r[2], (i, j)
+        off += n
+    for h in hs:
+        h.close()
+
+
+def test_large_n_served_alone_and_in_mix():
+    rng = np.random.default_rng(78)
+    reqs = []
+    for n in (256, 60, 230, 120, 181):
+        F = W.sparse_matrix(rng, n, 0.5, 0, 99)
+        D = W.uniform_matrix(rng, n, 0, 99)
+        lo, hi = W.tabu_tenure_range(n)
+        reqs.append((F, D, W.starts(rng, n, 1)[0], 500, lo, hi, int(rng.integers(0, 2**62))))
+    note("streamed requests served in a mix")
+    res = {}
+    with qap.Server(1 << 28, 16, 0.1) as s:
+        tickets = [s.submit(*r) for r in reqs]
+        for _ in range(100000):
+            if len(res) == len(reqs):
+                break
+            s.step()
+            for t in tickets:
+                if t not in res:
+                    r = s.result(t)
+                    if r is not None:
+                        res[t] = r
+        assert len(res) == len(reqs), "server made no progress"
+        assert s.stats()["chunks"] > len(reqs)
+    for t, (F, D, p, it, lo, hi, seed) in zip(tickets, reqs):
+        bp, bc, done, _ = oracle.tabu(F, D, p, it, lo, hi, seed, 0)
+        got = res[t]
+        assert (got[0] == bp).all() and got[1] == bc and got[2] == done
