@@ -40,12 +40,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3-2opt", "c3-tabu", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3-2opt", "c3-tabu", "c4", "c5"])
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-start comparison")
     ap.add_argument("--cpu-starts", type=int, default=32)
     ap.add_argument("--no-tune", action="store_true", help="uneven batch: the default tile shape for every n")
+    ap.add_argument("--chunk-ms", type=float, default=2.0, help="serving: device time per chunk of a search")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: requests in the arrival stream")
     ap.add_argument("--tune-cache", default=None, help="uneven batch: JSON cache of tuned tile shapes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (to scale HBM byte counters)")
@@ -236,6 +238,96 @@ def run_batch(args, w):
     print(json.dumps(out), flush=True)
 
 
+def run_serve(args):
+    """The serving stream: Poisson arrivals replayed in real time into the server."""
+    import torch
+    from paper_2307_11248_amd import qap
+    from paper_2307_11248_amd import workloads as W
+    reqs = W.c5_stream(count=args.requests)
+    N = len(reqs)
+    srv = qap.Server(8 << 30, 256, args.chunk_ms)
+    # warm-up: a few requests through the same server (kernels loaded, pool touched)
+    for r in reqs[:args.warmup * 4]:
+        lo, hi = W.tabu_tenure_range(r.inst.n)
+        t = srv.submit(r.inst.F, r.inst.D, r.inst.perms[0], 200, lo, hi, r.inst.seed)
+        while srv.result(t) is None:
+            srv.step()
+    torch.cuda.synchronize()
+    tickets, outstanding, lat, results = {}, {}, {}, {}
+    i = 0
+    t0 = time.perf_counter()
+    while len(results) < N:
+        now = time.perf_counter() - t0
+        while i < N and reqs[i].arrival_s <= now:
+            r = reqs[i]
+            lo, hi = W.tabu_tenure_range(r.inst.n)
+            t = srv.submit(r.inst.F, r.inst.D, r.inst.perms[0], r.iters, lo, hi, r.inst.seed)
+            tickets[t] = outstanding[t] = i
+            i += 1
+        if len(tickets) == len(results):          # idle: wait for the next arrival
+            if i < N:
+                time.sleep(max(0.0, reqs[i].arrival_s - (time.perf_counter() - t0)))
+            continue
+        f, _, _ = srv.step()
+        t_done = time.perf_counter() - t0
+        if f:
+            for t in [t for t in outstanding]:
+                res = srv.result(t)
+                if res is not None:
+                    j = outstanding.pop(t)
+                    results[j] = res
+                    lat[j] = (t_done - reqs[j].arrival_s) * 1e3
+    wall = time.perf_counter() - t0
+    stats = srv.stats()
+    ms = np.array([r.inst.n * (r.inst.n - 1) // 2 for r in reqs], dtype=np.int64)
+    moves = np.array([results[j][2] for j in range(N)], dtype=np.int64)
+    evals = int((ms * (moves + 1)).sum())
+    L = np.array([lat[j] for j in range(N)])
+    # a sample of requests run alone (qap_tabu, start id 0) must give the same results
+    same = True
+    for j in range(0, N, max(1, N // 8)):
+        r = reqs[j]
+        lo, hi = W.tabu_tenure_range(r.inst.n)
+        with qap.Handle(r.inst.F, r.inst.D) as h:
+            bp, bc, bd = h.tabu(r.inst.perms, r.iters, lo, hi, r.inst.seed)
+        same = same and bool((bp[0] == results[j][0]).all() and bc[0] == results[j][1] and bd[0] == results[j][2])
+    ns = [r.inst.n for r in reqs]
+    out = {"metric": METRIC, "value": evals / wall, "unit": "evals/s", "n_gpus": 1, "steps": 1,
+           "warmup": args.warmup, "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "c5_serving_stream", "requests": N, "rate_per_s": 200.0,
+                      "n_range": [min(ns), max(ns)], "iters_range": [min(r.iters for r in reqs),
+                                                                     max(r.iters for r in reqs)],
+                      "chunk_ms": args.chunk_ms, "max_active": 256, "pool_bytes": 8 << 30},
+           "solves_per_s": N / wall,
+           "latency_ms": {"p50": float(np.percentile(L, 50)), "p99": float(np.percentile(L, 99)),
+                          "mean": float(L.mean()), "max": float(L.max())},
+           "server": stats, "identical_alone_sample": same}
+    if not args.no_cpu:
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+        cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        sample = list(range(0, N, max(1, N // args.cpu_starts)))[:args.cpu_starts]
+
+        def one(j):
+            r = reqs[j]
+            lo, hi = W.tabu_tenure_range(r.inst.n)
+            return oracle.tabu(r.inst.F, r.inst.D, r.inst.perms[0], r.iters, lo, hi, r.inst.seed, 0)
+
+        t1 = time.perf_counter()
+        with ThreadPoolExecutor(cores) as ex:
+            cres = list(ex.map(one, sample))
+        cdt = time.perf_counter() - t1
+        cev = sum(int(ms[j]) * (c[2] + 1) for j, c in zip(sample, cres))
+        out["cpu_baseline"] = {"value": cev / cdt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+                               "sample": "%d requests of the stream, each run to its iteration budget "
+                                         "(%.1f s wall)" % (len(sample), cdt)}
+        out["bit_exact_sample"] = all((results[j][0] == c[0]).all() and results[j][1] == c[1]
+                                      for j, c in zip(sample, cres))
+    srv.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -254,6 +346,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": nbytes, "copy_calibration_bytes_written": nbytes}))
         return
+    if args.workload == "c5":
+        return run_serve(args)
     w = load_workload(args.workload)
     if len(w.instances) > 1:
         return run_batch(args, w)
