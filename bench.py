@@ -34,6 +34,29 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 VALU_PER_EVAL = {"tabu": 8, "2opt": 6}
 BYTES_PER_EVAL = 8   # an int32 delta read and written per entry per step if kept in HBM
 
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# runs scaled by a plain copy's counts (x2 and x1; see the summaries under profiles/),
+# valid only for the kernel sources they were taken with.
+KERNEL_SOURCES = ["paper_2307_11248_amd/csrc/qap_search.hip", "paper_2307_11248_amd/csrc/qap_internal.h"]
+TRAFFIC = {
+    "c2_n64_dense_tabu": {"bytes": 1487872 + 40960, "sources": "97c30e6b9d38a700"},
+    "c4_batched_uneven_tabu": {"bytes": 227851520 + 1719120, "sources": "97c30e6b9d38a700"},
+}
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload):
+    t = TRAFFIC.get(workload)
+    return t["bytes"] if t is not None and t["sources"] == kernel_digest() else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -195,7 +218,7 @@ def run_batch(args, w):
     value = evals_step / (ms_step / 1e3)
     valu = VALU_PER_EVAL["tabu"] * search_evals / (search_ms / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": round(valu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s",
-            "frac": round(valu / PEAK_VALU_TOPS, 4), "traffic": None, "kernel": "batch_kernel",
+            "frac": round(valu / PEAK_VALU_TOPS, 4), "traffic": traffic_for(w.name), "kernel": "batch_kernel",
             "kernel_ms": round(search_ms, 4), "ops_per_eval": VALU_PER_EVAL["tabu"],
             "hbm_equivalent": {"achieved": round(BYTES_PER_EVAL * search_evals / (search_ms / 1e3) / 1e9, 1),
                                "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -410,7 +433,7 @@ def main():
     search_evals = int(moves.sum()) * m
     valu = VALU_PER_EVAL[algo] * search_evals / (search_ms / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": round(valu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s",
-            "frac": round(valu / PEAK_VALU_TOPS, 4), "traffic": None,
+            "frac": round(valu / PEAK_VALU_TOPS, 4), "traffic": traffic_for(w.name),
             "kernel": "search_kernel<%d,%s>" % (rows, "true" if algo == "tabu" else "false"),
             "kernel_ms": round(search_ms, 4),
             "ops_per_eval": VALU_PER_EVAL[algo],
