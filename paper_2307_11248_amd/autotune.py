@@ -62,7 +62,10 @@ class TileCache:
                 return rows
             except qap.QapError:
                 pass                      # the cached shape no longer fits: measure again
-        rows, times = h.tune_tile_rows(algo, self.k, self.iters)
+        # the batched kernels run several searches per compute unit: time enough searches
+        # to fill the device, so the choice reflects throughput, not one search's latency
+        starts = max(self.k, 1024) if algo == "batch" else self.k
+        rows, times = h.tune_tile_rows(algo, starts, self.iters)
         self.entries[k] = {"rows": rows, "ms": {str(r): t for r, t in times.items()}}
         self.tuned += 1
         return rows

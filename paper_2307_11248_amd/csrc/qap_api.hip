@@ -166,7 +166,7 @@ int make_tables(qap_ctx *h, const int32_t *d_perms, int k, int32_t **d_table, hi
     hipError_t e = report(hipMallocAsync((void **)d_table, (size_t)k * h->m * sizeof(int32_t) + 16, st),
                           "hipMallocAsync");
     if (e != hipSuccess) return dev_err(e);
-    TableArgs ta{h->d_mats, d_perms, nullptr, *d_table, h->n, h->m, k};
+    TableArgs ta{h->d_mats, d_perms, nullptr, *d_table, h->n, h->m, k, h->sym};
     e = launch_table(ta, st);
     if (e != hipSuccess) { (void)hipFreeAsync(*d_table, st); return dev_err(e); }
     return QAP_OK;
@@ -286,8 +286,23 @@ struct qap_batch {
     Item *d_items = nullptr;
     int32_t *d_table = nullptr;
     int4 *d_tile_work = nullptr;    // tile state of the streamed searches
-    size_t smem = 0, table_smem = 0;
+    size_t table_smem = 0;
+    // items are grouped by kernel variant (tile shape); one launch per non-empty group,
+    // the groups forked onto side streams so that they share the device
+    int group_begin[BV_COUNT] = {}, group_count[BV_COUNT] = {};
+    size_t group_smem[BV_COUNT] = {};
+    hipStream_t side[BV_COUNT] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[BV_COUNT] = {};
 };
+
+namespace {
+
+int item_variant(const Item &it) {
+    if (it.stream) return BV_STREAM;
+    return it.rows == 2 ? BV_R2 : (it.rows == 4 ? BV_R4 : BV_R8);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -420,7 +435,7 @@ int qap_tune_tile_rows(qap_handle h, int32_t algo, int32_t k, int32_t iters, flo
             e = hipMemcpyAsync(dw.p, ds.p, hp.size() * 4, hipMemcpyDeviceToDevice, c.st);
             int32_t *w = (int32_t *)dw.p;
             if (e == hipSuccess && algo < 2) {
-                TableArgs ta{h->d_mats, w, nullptr, (int32_t *)dt.p, n, h->m, k};
+                TableArgs ta{h->d_mats, w, nullptr, (int32_t *)dt.p, n, h->m, k, h->sym};
                 e = launch_table(ta, c.st);
             } else if (e == hipSuccess) {
                 rc = qap_batch_tables_async(b, w, c.st);
@@ -455,13 +470,13 @@ int qap_tune_tile_rows(qap_handle h, int32_t algo, int32_t k, int32_t iters, flo
 
 int qap_cost_async(qap_handle h, const int32_t *d_perms, int32_t k, int64_t *d_costs, void *stream) {
     if (!h || k < 0 || (k > 0 && (!d_perms || !d_costs))) return QAP_E_INVALID;
-    TableArgs a{h->d_mats, d_perms, d_costs, nullptr, h->n, h->m, k};
+    TableArgs a{h->d_mats, d_perms, d_costs, nullptr, h->n, h->m, k, h->sym};
     return dev_err(launch_cost(a, (hipStream_t)stream));
 }
 
 int qap_delta_table_async(qap_handle h, const int32_t *d_perms, int32_t k, int32_t *d_table, void *stream) {
     if (!h || k < 0 || (k > 0 && (!d_perms || !d_table))) return QAP_E_INVALID;
-    TableArgs a{h->d_mats, d_perms, nullptr, d_table, h->n, h->m, k};
+    TableArgs a{h->d_mats, d_perms, nullptr, d_table, h->n, h->m, k, h->sym};
     return dev_err(launch_table(a, (hipStream_t)stream));
 }
 
@@ -596,7 +611,7 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
     *out = nullptr;
     std::vector<Item> items;
     long long perm_off = 0, out_off = 0, table_off = 0, tile_off = 0;
-    size_t smem = 0, tsmem = 0;
+    size_t gsmem[BV_COUNT] = {}, tsmem = 0;
     for (int i = 0; i < m; ++i) {
         qap_ctx *h = hs[i];
         if (!h || k_per[i] < 0 || lo_per[i] < 0 || lo_per[i] > hi_per[i]) return QAP_E_INVALID;
@@ -606,7 +621,8 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
         const TileSet &ts = shape_tiles(h, ri);
         const size_t sm = streamed ? stream_smem_bytes(h->n, h->sym)
                                    : search_smem_bytes(h->n, kRowsChoices[ri], BATCH_LANES, h->sym);
-        smem = std::max(smem, sm);
+        const int var = streamed ? BV_STREAM : ri;   // BV_R2, BV_R4, BV_R8 follow kRowsChoices
+        gsmem[var] = std::max(gsmem[var], sm);
         tsmem = std::max(tsmem, table_smem_bytes(h->n));
         for (int j = 0; j < k_per[i]; ++j) {
             Item it{};
@@ -637,8 +653,11 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
             table_off += h->m;
         }
     }
-    // longest first: the hardware starts blocks in index order
+    // grouped by kernel variant; longest first inside a group (the hardware starts blocks
+    // in index order)
     std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
+        const int va = item_variant(a), vb = item_variant(b);
+        if (va != vb) return va < vb;
         return (long long)a.n * a.n > (long long)b.n * b.n;
     });
     qap_batch *b = new (std::nothrow) qap_batch;
@@ -647,11 +666,28 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
     b->perm_ints = perm_off;
     b->table_ints = table_off;
     b->tile_int4 = tile_off;
-    b->smem = smem;
     b->table_smem = tsmem;
+    for (int i = (int)items.size() - 1; i >= 0; --i) {
+        const int v = item_variant(items[i]);
+        b->group_begin[v] = i;
+        ++b->group_count[v];
+    }
+    int ngroups = 0;
+    for (int v = 0; v < BV_COUNT; ++v) {
+        b->group_smem[v] = gsmem[v];
+        ngroups += b->group_count[v] > 0;
+    }
     hipError_t e = hipSuccess;
+    if (ngroups > 1) {
+        e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+        for (int v = 0; v < BV_COUNT && e == hipSuccess; ++v) {
+            if (!b->group_count[v]) continue;
+            e = hipStreamCreateWithFlags(&b->side[v], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[v], hipEventDisableTiming);
+        }
+    }
     if (b->count > 0) {
-        e = hipMalloc((void **)&b->d_items, items.size() * sizeof(Item));
+        if (e == hipSuccess) e = hipMalloc((void **)&b->d_items, items.size() * sizeof(Item));
         if (e == hipSuccess) e = hipMalloc((void **)&b->d_table, (size_t)table_off * sizeof(int32_t) + 16);
         if (e == hipSuccess && tile_off > 0) e = hipMalloc((void **)&b->d_tile_work, (size_t)tile_off * sizeof(int4));
         if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice);
@@ -682,8 +718,25 @@ extern "C" int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int6
                                       void *stream) {
     if (!b || (b->count > 0 && (!d_perms || !d_best))) return QAP_E_INVALID;
     if (b->count == 0) return QAP_OK;
-    BatchArgs a{b->d_items, b->count, d_perms, d_best, d_done, b->d_table, b->d_tile_work};
-    return dev_err(launch_batch(a, b->smem, (hipStream_t)stream));
+    hipStream_t st = (hipStream_t)stream;
+    int ngroups = 0;
+    for (int v = 0; v < BV_COUNT; ++v) ngroups += b->group_count[v] > 0;
+    hipError_t e = hipSuccess;
+    if (ngroups > 1) e = hipEventRecord(b->ev_fork, st);
+    for (int v = 0; v < BV_COUNT && e == hipSuccess; ++v) {
+        if (!b->group_count[v]) continue;
+        BatchArgs a{b->d_items + b->group_begin[v], b->group_count[v], d_perms, d_best, d_done, b->d_table,
+                    b->d_tile_work};
+        if (ngroups == 1) {
+            e = launch_batch_group(v, a, b->group_smem[v], st);
+            continue;
+        }
+        e = hipStreamWaitEvent(b->side[v], b->ev_fork, 0);
+        if (e == hipSuccess) e = launch_batch_group(v, a, b->group_smem[v], b->side[v]);
+        if (e == hipSuccess) e = hipEventRecord(b->ev_join[v], b->side[v]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[v], 0);
+    }
+    return dev_err(e);
 }
 
 extern "C" int qap_batch_run_async(qap_batch_handle b, int32_t *d_perms, int64_t *d_best, int32_t *d_done,
@@ -697,6 +750,11 @@ extern "C" int qap_batch_destroy(qap_batch_handle b) {
     if (b->d_items) (void)hipFree(b->d_items);
     if (b->d_table) (void)hipFree(b->d_table);
     if (b->d_tile_work) (void)hipFree(b->d_tile_work);
+    for (int v = 0; v < BV_COUNT; ++v) {
+        if (b->side[v]) (void)hipStreamDestroy(b->side[v]);
+        if (b->ev_join[v]) (void)hipEventDestroy(b->ev_join[v]);
+    }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     delete b;
     return QAP_OK;
 }

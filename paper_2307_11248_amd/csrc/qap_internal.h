@@ -84,6 +84,7 @@ struct TableArgs {
     int64_t *costs;          // [k] or null
     int32_t *table;          // [k][m] or null
     int n, m, k;
+    int sym;                 // F and D both symmetric
 };
 
 // Arguments of the search kernels (2opt and tabu).
@@ -188,7 +189,10 @@ size_t search_smem_bytes(int n, int rows, int lanes, int sym);
 // Lanes of the persistent batched kernel, and whether a tile shape can serve n there.
 constexpr int BATCH_LANES = 512;
 int batch_shape_ok(int n, int rows, int ntiles, int sym);
-hipError_t launch_batch(const BatchArgs &b, size_t smem, hipStream_t st);
+// Kernel variants of the batched launch, one per tile shape: register tiles of 2, 4, 8
+// rows and the streamed form.  One launch per variant, items of that shape only.
+enum { BV_R2 = 0, BV_R4, BV_R8, BV_STREAM, BV_COUNT };
+hipError_t launch_batch_group(int variant, const BatchArgs &b, size_t smem, hipStream_t st);
 int search_max_lanes(int rows);
 // Streamed kernels (any n up to 256): tiles of STREAM_ROWS x 4 slots kept in global memory
 // between passes, D read from global memory, BATCH_LANES lanes per search.

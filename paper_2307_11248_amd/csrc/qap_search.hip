@@ -136,7 +136,7 @@ __device__ inline unsigned dot_rows(const uint8_t *a, const uint8_t *b, int rs) 
     return acc;
 }
 
-// Two dot products sharing the row `a`, over rows of rs bytes (a multiple of 16); the
+// Two dot products sharing the row `a`, over the first rs bytes (a multiple of 16); the
 // loads of the next 16-byte column block are issued before the current one is used.
 __device__ inline void dot_rows2(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
                                  unsigned &o2) {
@@ -189,6 +189,7 @@ __device__ __attribute__((always_inline)) void search_body(const Item &a, unsign
     __shared__ int s_bad;
     __shared__ int s_chunk_end;   // chunked runs: set by thread 0 once the clock budget is spent
     const int n = a.n, rs = row_stride(n), L = blockDim.x, t = threadIdx.x;
+    const int nb16 = (n + 15) & ~15;   // bytes of a row the dot products read (zero past n)
     const int lane = t & 63, wid = t >> 6, W = L >> 6;
     const int sym = a.sym;
     const int nq = families(sym), lq = sym ? 1 : 2;
@@ -269,9 +270,9 @@ __device__ __attribute__((always_inline)) void search_body(const Item &a, unsign
     // ---- RD_u = sum_k D[u][k] G[u][k], CD_u = sum_k D[k][u] G[k][u]; cost (Eq. 1) = sum RD_u
     long long part = 0;
     for (int u = t; u < n; u += L) {
-        const int rd = (int)dot_rows(Dm + u * rs, Gm + u * rs, rs);
+        const int rd = (int)dot_rows(Dm + u * rs, Gm + u * rs, nb16);
         rpr[u] = rd;
-        rps[u] = sym ? rd : (int)dot_rows(DmT + u * rs, GmT + u * rs, rs);
+        rps[u] = sym ? rd : (int)dot_rows(DmT + u * rs, GmT + u * rs, nb16);
         part += rd;
     }
     part = wave_sum64(part);
@@ -525,7 +526,7 @@ __device__ __attribute__((always_inline)) void search_body(const Item &a, unsign
             const uint8_t *side1 = f < 2 ? Df + r * rs : Gf + s * rs;
             const uint8_t *side2 = f < 2 ? Df + s * rs : Gf + r * rs;
             unsigned d1, d2;
-            dot_rows2(shared, side1, side2, rs, d1, d2);
+            dot_rows2(shared, side1, side2, nb16, d1, d2);
             // (a_s - a_r) and (c_r - c_s) for the sides r and s, chosen without branches
             const int a0 = (u == r ? G_ss : (u == s ? G_rs : g_us)) - (u == r ? G_sr : (u == s ? G_rr : g_ur));
             const int a1 = (u == r ? G_ss : (u == s ? G_sr : g_su)) - (u == r ? G_rs : (u == s ? G_rr : g_ru));
@@ -858,10 +859,16 @@ __global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a)
     search_body<ROWS, TABU, max_tasks<ROWS>(), false, false>(it, sm);
 }
 
-// The batched launch: block i runs item i as one tabu search with the item's tile
-// shape.  Items come sorted by decreasing work, and the hardware hands blocks to compute
-// units in index order as they free up, so the longest searches start first.
-__global__ void __launch_bounds__(BATCH_LANES) batch_kernel(BatchArgs b) {
+// The batched launch, one kernel per tile shape: block i runs items[i] as one tabu
+// search (items come sorted by decreasing work, and the hardware hands blocks to compute
+// units in index order as they free up, so the longest searches start first).  Tiles of
+// 2 and 4 rows ask for four waves per SIMD (at most 128 VGPRs), so two searches share a
+// compute unit and hide each other's latency; 8-row and streamed tiles need more
+// registers and run one search per compute unit.  (A persistent loop over a work queue
+// inside one block was tried: keeping its state live made the register tiles spill.)
+template <int ROWS, int LANES, bool STREAM>
+__global__ void __launch_bounds__(LANES) __attribute__((amdgpu_waves_per_eu(ROWS <= 4 ? 4 : 2)))
+batch_group_kernel(BatchArgs b) {
     extern __shared__ __align__(16) unsigned char sm[];
     Item it = b.items[blockIdx.x];
     it.perm_in = b.perms + it.perm_off;
@@ -869,17 +876,11 @@ __global__ void __launch_bounds__(BATCH_LANES) batch_kernel(BatchArgs b) {
     it.cost_out = b.best + it.out_off;
     it.steps_out = b.done ? b.done + it.out_off : nullptr;
     it.table = b.table + it.table_off;
-    if (it.stream) {
+    if (STREAM) {
         it.tile_d = b.tile_work + it.tile_off;
         it.tile_u = it.tile_d + stream_tile_int4(it.ntiles) / 2;
-        search_body<STREAM_ROWS, true, 1024 / BATCH_LANES, false, true>(it, sm);
-        return;
     }
-    switch (it.rows) {
-        case 2: search_body<2, true, 1024 / BATCH_LANES, false, false>(it, sm); break;
-        case 4: search_body<4, true, 1024 / BATCH_LANES, false, false>(it, sm); break;
-        default: search_body<8, true, 1024 / BATCH_LANES, false, false>(it, sm); break;
-    }
+    search_body<ROWS, true, 1024 / LANES, false, STREAM>(it, sm);
 }
 
 // Chunked runs: block i runs one chunk of items[i] (absolute pointers, st != null).
@@ -958,11 +959,21 @@ int batch_shape_ok(int n, int rows, int ntiles, int sym) {
     return rows <= 8 && ntiles <= BATCH_LANES && families(sym) * n <= BATCH_LANES * (1024 / BATCH_LANES) ? 1 : 0;
 }
 
-hipError_t launch_batch(const BatchArgs &b, size_t smem, hipStream_t st) {
+hipError_t launch_batch_group(int variant, const BatchArgs &b, size_t smem, hipStream_t st) {
     if (b.count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_kernel, dim3(b.count), dim3(BATCH_LANES), smem, st, b);
+    constexpr int L = BATCH_LANES;
+    switch (variant) {
+        case BV_R2: hipLaunchKernelGGL((batch_group_kernel<2, L, false>), dim3(b.count), dim3(L), smem, st, b); break;
+        case BV_R4: hipLaunchKernelGGL((batch_group_kernel<4, L, false>), dim3(b.count), dim3(L), smem, st, b); break;
+        case BV_R8: hipLaunchKernelGGL((batch_group_kernel<8, L, false>), dim3(b.count), dim3(L), smem, st, b); break;
+        case BV_STREAM:
+            hipLaunchKernelGGL((batch_group_kernel<STREAM_ROWS, L, true>), dim3(b.count), dim3(L), smem, st, b);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return report(hipGetLastError(), "batch kernel launch");
 }
+
 
 hipError_t launch_resume(const Item *d_items, int count, size_t smem, hipStream_t st) {
     if (count <= 0) return hipSuccess;

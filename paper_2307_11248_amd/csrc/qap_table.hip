@@ -68,87 +68,245 @@ __global__ void __launch_bounds__(256) cost_kernel(TableArgs a) {
     }
 }
 
-// out[idx(u,v)] = Eq. (2) with the diagonal term for one start, one entry per lane at a
-// time (F, D and the permutation already staged).
-__device__ void table_body(int n, const uint8_t *Fm, const uint8_t *Dm, const int *perm, int32_t *out);
+// ---- whole neighbourhood (a3) as integer contractions on the matrix cores
+//
+// With G = F[p][p] (G[a][b] = F[p_a][p_b]) and T = G.D^T + G^T.D, every delta of Eq. (2)
+// (with its diagonal term) is
+//   delta(i, j) = T_ij + T_ji - T_ii - T_jj + c_ij,
+// c_ij a sum of six products of the entries of D and G at (i, j), (j, i), (i, i), (j, j)
+// (expanding Eq. (2) and collecting the k = i, j terms).  The two n x n x n products
+// run as v_mfma_i32_32x32x16_i8 on entries shifted to int8 (x - 128), with the shift
+// undone exactly from row sums:
+//   sum_k x_k y_k = sum_k x'_k y'_k + 128 (sum_k x'_k + sum_k y'_k) + 128^2 n.
+// A workgroup takes one start.  Phase 0 stages X = G', Y = D' (int8, rows padded to a
+// multiple of 32 with zeros) in LDS, phase 1 X = (G^T)', Y = (D^T)' (skipped when F and
+// D are both symmetric: then the phases are equal).  Each wave owns pairs of 32 x 32
+// output tiles (I <= J) and accumulates S_ij = T_ij + T_ji in place as
+// X_I.Y_J^T + Y_I.X_J^T over both phases, so the transpose costs nothing.
 
-// table[j][idx(u,v)] for every start j of the launch.
-__global__ void __launch_bounds__(256) table_kernel(TableArgs a) {
-    extern __shared__ __align__(16) unsigned char sm[];
-    __shared__ int bad;
-    const int n = a.n, rs = row_stride(n), job = blockIdx.x, t = threadIdx.x;
-    uint8_t *Fm = sm, *Dm = sm + n * rs;
-    int *perm = reinterpret_cast<int *>(sm + 2 * n * rs);
-    int *pinv = perm + n;
-    const bool ok = stage_f_d_perm(a, job, Fm, Dm, perm, pinv, &bad);
-    int32_t *out = a.table + (size_t)job * a.m;
-    if (!ok) {
-        for (int i = t; i < a.m; i += blockDim.x) out[i] = 0;
-        return;
-    }
-    table_body(n, Fm, Dm, perm, out);
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int TB_LANES = 512, TB_W = TB_LANES / 64;
+constexpr int TB_MAXP = 5;   // tile pairs per wave: 36 pairs at n = 256 over 8 waves
+
+__host__ __device__ inline int tb_rows(int n) { return (n + 31) & ~31; }
+
+struct TbPlan {
+    int perm, pinv, x, y, u, td, total;
+};
+
+__host__ __device__ inline TbPlan tb_plan(int n) {
+    const int rs = row_stride(n), np = tb_rows(n);
+    TbPlan q;
+    int o = 0;
+    q.perm = o; o += np * 4;
+    q.pinv = o; o += np * 4;
+    q.u = o;    o += np * 4;
+    q.td = o;   o += np * 4;
+    o = (o + 255) & ~255;
+    q.x = o;    o += np * rs;
+    o = (o + 255) & ~255;
+    q.y = o;    o += np * rs;
+    q.total = o;
+    return q;
 }
 
-// The neighbourhood of every item of a batch: block i stages item i's F, D and start.
-__global__ void __launch_bounds__(256) table_batch_kernel(BatchArgs b) {
-    extern __shared__ __align__(16) unsigned char sm[];
-    __shared__ int bad;
-    const Item &it = b.items[blockIdx.x];
-    TableArgs a{it.mats, b.perms + it.perm_off, nullptr, b.table + it.table_off, it.n, it.m, 1};
-    const int n = it.n, rs = row_stride(n), t = threadIdx.x;
-    uint8_t *Fm = sm, *Dm = sm + n * rs;
-    int *perm = reinterpret_cast<int *>(sm + 2 * n * rs);
-    int *pinv = perm + n;
-    const bool ok = stage_f_d_perm(a, 0, Fm, Dm, perm, pinv, &bad);
-    if (!ok) {
-        for (int i = t; i < it.m; i += blockDim.x) a.table[i] = 0;
-        return;
+// Read and check one start into LDS (perm and its inverse); false if it is not a
+// permutation of 0..n-1.  Ends with a barrier.
+__device__ bool tb_stage_perm(const int32_t *p, int n, int *perm, int *pinv, int *bad) {
+    const int L = blockDim.x, t = threadIdx.x;
+    if (t == 0) *bad = 0;
+    for (int u = t; u < n; u += L) pinv[u] = -1;
+    __syncthreads();
+    for (int u = t; u < n; u += L) {
+        const int v = p[u];
+        perm[u] = v;
+        if (v < 0 || v >= n || atomicExch(&pinv[v], u) != -1) *bad = 1;
     }
-    table_body(n, Fm, Dm, perm, a.table);
+    __syncthreads();
+    return *bad == 0;
 }
 
-// Tables of starting items of a chunked run: block i writes items[i]'s neighbourhood
-// into its `table`.
-__global__ void __launch_bounds__(256) table_items_kernel(const Item *items) {
-    extern __shared__ __align__(16) unsigned char sm[];
-    __shared__ int bad;
-    const Item &it = items[blockIdx.x];
-    TableArgs a{it.mats, it.perm_in, nullptr, const_cast<int32_t *>(it.table), it.n, it.m, 1};
-    const int n = it.n, rs = row_stride(n), t = threadIdx.x;
-    uint8_t *Fm = sm, *Dm = sm + n * rs;
-    int *perm = reinterpret_cast<int *>(sm + 2 * n * rs);
-    int *pinv = perm + n;
-    if (!stage_f_d_perm(a, 0, Fm, Dm, perm, pinv, &bad)) {
-        for (int i = t; i < it.m; i += blockDim.x) a.table[i] = 0;
-        return;
+// (I, J), I <= J, of tile pair q in row-major order over nt x nt tiles
+__device__ inline void tb_pair(int q, int nt, int &I, int &J) {
+    I = 0;
+    while (q >= nt - I) {
+        q -= nt - I;
+        ++I;
     }
-    table_body(n, Fm, Dm, perm, a.table);
+    J = I + q;
 }
 
-__device__ void table_body(int n, const uint8_t *Fm, const uint8_t *Dm, const int *perm, int32_t *out) {
-    const int rs = row_stride(n), t = threadIdx.x;
-    for (int u = 0; u < n - 1; ++u) {
-        const int pu = perm[u];
-        const long long base = pidx(n, u, u + 1);
-        for (int v = u + 1 + t; v < n; v += blockDim.x) {
-            const int pv = perm[v];
-            const uint8_t *du = Dm + u * rs, *dv = Dm + v * rs;
-            const uint8_t *fu = Fm + pu * rs, *fv = Fm + pv * rs;
-            int acc = ((int)dv[v] - (int)du[u]) * ((int)fu[pu] - (int)fv[pv])
-                    + ((int)dv[u] - (int)du[v]) * ((int)fu[pv] - (int)fv[pu]);
-            for (int k = 0; k < n; ++k) {
-                if (k == u || k == v) continue;
-                const int pk = perm[k];
-                const uint8_t *dk = Dm + k * rs, *fk = Fm + pk * rs;
-                acc += ((int)dv[k] - (int)du[k]) * ((int)fu[pk] - (int)fv[pk])
-                     + ((int)dk[v] - (int)dk[u]) * ((int)fk[pu] - (int)fk[pv]);
+__device__ inline long long tb_load8(const uint8_t *p) { return *reinterpret_cast<const long long *>(p); }
+
+// The whole neighbourhood of one start, perm already in LDS (tb_plan layout at sm).
+__device__ __attribute__((always_inline)) void table_mfma_body(const uint8_t *mats, int n, int sym, unsigned char *sm, int32_t *out) {
+    const TbPlan P = tb_plan(n);
+    const int rs = row_stride(n), np = tb_rows(n), nt = np / 32, L = blockDim.x, t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
+    const int *perm = reinterpret_cast<const int *>(sm + P.perm);
+    int *U = reinterpret_cast<int *>(sm + P.u);
+    int *TD = reinterpret_cast<int *>(sm + P.td);
+    uint8_t *X = sm + P.x, *Y = sm + P.y;
+    const int npairs = nt * (nt + 1) / 2;
+    for (int i = t; i < np; i += L) U[i] = TD[i] = 0;
+
+    v16i acc[TB_MAXP];
+#pragma unroll
+    for (int q = 0; q < TB_MAXP; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[q][r] = 0;
+
+    const int phases = sym ? 1 : 2;
+    for (int ph = 0; ph < phases; ++ph) {
+        const uint8_t *Fp = mats + (size_t)(ph ? 1 : 0) * n * rs;   // F, then F^T
+        const uint8_t *Dp = mats + (size_t)(ph ? 3 : 2) * n * rs;   // D, then D^T
+        // raw rows of F_p into Y, then X[i][k] = F_p[p_i][p_k] - 128 gathered from them
+        const int vec = n * rs / 16;
+        for (int v = t; v < vec; v += L)
+            reinterpret_cast<uint4 *>(Y)[v] = reinterpret_cast<const uint4 *>(Fp)[v];
+        __syncthreads();
+        const int wpr = rs / 4;
+        for (int v = t; v < np * wpr; v += L) {
+            const int i = v / wpr, k0 = (v - i * wpr) * 4;
+            unsigned word = 0;
+            if (i < n) {
+                const uint8_t *row = Y + perm[i] * rs;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (k0 + e < n) word |= (unsigned)(row[perm[k0 + e]] ^ 0x80u) << (8 * e);
             }
-            out[base + (v - u - 1)] = acc;
+            reinterpret_cast<unsigned *>(X)[v] = word;
+        }
+        __syncthreads();
+        // Y[i][k] = D_p[i][k] - 128 (the global rows are zero past n: shift real bytes only)
+        const int vpr = rs / 16;
+        for (int v = t; v < np * vpr; v += L) {
+            const int i = v / vpr, c = (v - i * vpr) * 16;
+            uint4 x = make_uint4(0, 0, 0, 0);
+            if (i < n) {
+                x = reinterpret_cast<const uint4 *>(Dp + (size_t)i * rs)[c / 16];
+                unsigned m[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = c + 4 * e, real = n - k;   // bytes k .. k+3, real ones first
+                    m[e] = real >= 4 ? 0x80808080u : (real <= 0 ? 0u : (0x80808080u >> (8 * (4 - real))));
+                }
+                x.x ^= m[0]; x.y ^= m[1]; x.z ^= m[2]; x.w ^= m[3];
+            }
+            reinterpret_cast<uint4 *>(Y)[v] = x;
+        }
+        __syncthreads();
+        // per index: the row sums of X' and Y' and the diagonal term sum_k x_ik y_ik
+        for (int i = t; i < n; i += L) {
+            const int *xr = reinterpret_cast<const int *>(X + i * rs), *yr = reinterpret_cast<const int *>(Y + i * rs);
+            int sx = 0, sy = 0, dxy = 0;
+            for (int c = 0; c < rs / 4; ++c) {
+                const int a = xr[c], b = yr[c];
+                sx = __builtin_amdgcn_sdot4(a, 0x01010101, sx, false);
+                sy = __builtin_amdgcn_sdot4(b, 0x01010101, sy, false);
+                dxy = __builtin_amdgcn_sdot4(a, b, dxy, false);
+            }
+            U[i] += sx + sy;
+            TD[i] += dxy + 128 * (sx + sy) + 16384 * n;
+        }
+        // S += X_I . Y_J^T + Y_I . X_J^T over this phase
+        const int row = lane & 31, kh = 8 * (lane >> 5);
+#pragma unroll
+        for (int q = 0; q < TB_MAXP; ++q) {
+            const int pq = w + q * TB_W;
+            if (pq < npairs) {
+                int I, J;
+                tb_pair(pq, nt, I, J);
+                const uint8_t *xi = X + (I * 32 + row) * rs + kh, *yj = Y + (J * 32 + row) * rs + kh;
+                const uint8_t *yi = Y + (I * 32 + row) * rs + kh, *xj = X + (J * 32 + row) * rs + kh;
+                for (int k0 = 0; k0 < n; k0 += 16) {
+                    acc[q] = __builtin_amdgcn_mfma_i32_32x32x16_i8(tb_load8(xi + k0), tb_load8(yj + k0), acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_i32_32x32x16_i8(tb_load8(yi + k0), tb_load8(xj + k0), acc[q], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();   // sums visible; X, Y free for the next phase
+    }
+
+    // ---- epilogue: delta(i, j) for i < j from the accumulators of this wave.  X and Y
+    //      hold the last phase: G^T and D^T (or G and D when symmetric, then equal to them
+    //      transposed), so G_ab = X[b][a] + 128 and D_ab = Y[b][a] + 128 in both cases.
+    auto gv = [&](int a_, int b_) { return (int)(uint8_t)(X[b_ * rs + a_] ^ 0x80); };
+    auto dv = [&](int a_, int b_) { return (int)(uint8_t)(Y[b_ * rs + a_] ^ 0x80); };
+#pragma unroll
+    for (int q = 0; q < TB_MAXP; ++q) {
+        const int pq = w + q * TB_W;
+        if (pq >= npairs) continue;
+        int I, J;
+        tb_pair(pq, nt, I, J);
+        const int j = J * 32 + (lane & 31);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = I * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (i < j && j < n) {
+                const int s_ij = sym ? 2 * (acc[q][r] + 128 * (U[i] + U[j]) + 32768 * n)
+                                     : acc[q][r] + 128 * (U[i] + U[j]) + 65536 * n;
+                const int t_ii = sym ? 2 * TD[i] : TD[i], t_jj = sym ? 2 * TD[j] : TD[j];
+                const int Dij = dv(i, j), Dji = dv(j, i), Dii = dv(i, i), Djj = dv(j, j);
+                const int Gij = gv(i, j), Gji = gv(j, i), Gii = gv(i, i), Gjj = gv(j, j);
+                const int c = -(Dji - Dii) * (Gii - Gji) - (Djj - Dij) * (Gij - Gjj) - (Dij - Dii) * (Gii - Gij)
+                              - (Djj - Dji) * (Gji - Gjj) + (Dji - Dij) * (Gij - Gji) + (Djj - Dii) * (Gii - Gjj);
+                out[pidx(n, i, j)] = s_ij - t_ii - t_jj + c;
+            }
         }
     }
 }
 
-size_t table_smem(int n) { return (size_t)2 * n * row_stride(n) + (size_t)2 * n * 4; }
+// table[j][idx(u,v)] for every start j of the launch.
+__global__ void __launch_bounds__(TB_LANES) table_kernel(TableArgs a) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    __shared__ int bad;
+    const TbPlan P = tb_plan(a.n);
+    const int job = blockIdx.x, t = threadIdx.x;
+    int32_t *out = a.table + (size_t)job * a.m;
+    if (!tb_stage_perm(a.perms + (size_t)job * a.n, a.n, reinterpret_cast<int *>(sm + P.perm),
+                       reinterpret_cast<int *>(sm + P.pinv), &bad)) {
+        for (int i = t; i < a.m; i += blockDim.x) out[i] = 0;
+        return;
+    }
+    table_mfma_body(a.mats, a.n, a.sym, sm, out);
+}
+
+// The neighbourhood of every item of a batch: block i takes item i's start.
+__global__ void __launch_bounds__(TB_LANES) table_batch_kernel(BatchArgs b) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    __shared__ int bad;
+    const Item &it = b.items[blockIdx.x];
+    const TbPlan P = tb_plan(it.n);
+    int32_t *out = b.table + it.table_off;
+    if (!tb_stage_perm(b.perms + it.perm_off, it.n, reinterpret_cast<int *>(sm + P.perm),
+                       reinterpret_cast<int *>(sm + P.pinv), &bad)) {
+        for (int i = threadIdx.x; i < it.m; i += blockDim.x) out[i] = 0;
+        return;
+    }
+    table_mfma_body(it.mats, it.n, it.sym, sm, out);
+}
+
+// Tables of starting items of a chunked run: block i writes items[i]'s neighbourhood
+// into its `table`.
+__global__ void __launch_bounds__(TB_LANES) table_items_kernel(const Item *items) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    __shared__ int bad;
+    const Item &it = items[blockIdx.x];
+    const TbPlan P = tb_plan(it.n);
+    int32_t *out = const_cast<int32_t *>(it.table);
+    if (!tb_stage_perm(it.perm_in, it.n, reinterpret_cast<int *>(sm + P.perm), reinterpret_cast<int *>(sm + P.pinv),
+                       &bad)) {
+        for (int i = threadIdx.x; i < it.m; i += blockDim.x) out[i] = 0;
+        return;
+    }
+    table_mfma_body(it.mats, it.n, it.sym, sm, out);
+}
+
+size_t table_smem(int n) { return (size_t)tb_plan(n).total; }
+
+size_t cost_smem(int n) { return (size_t)2 * n * row_stride(n) + (size_t)2 * n * 4; }
 
 }  // namespace
 
@@ -156,19 +314,19 @@ size_t table_smem_bytes(int n) { return table_smem(n); }
 
 hipError_t launch_table_batch(const BatchArgs &b, size_t smem, hipStream_t st) {
     if (b.count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(table_batch_kernel, dim3(b.count), dim3(256), smem, st, b);
+    hipLaunchKernelGGL(table_batch_kernel, dim3(b.count), dim3(TB_LANES), smem, st, b);
     return report(hipGetLastError(), "batch table kernel launch");
 }
 
 hipError_t launch_table_items(const Item *d_items, int count, size_t smem, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(table_items_kernel, dim3(count), dim3(256), smem, st, d_items);
+    hipLaunchKernelGGL(table_items_kernel, dim3(count), dim3(TB_LANES), smem, st, d_items);
     return report(hipGetLastError(), "item table kernel launch");
 }
 
 hipError_t launch_cost(const TableArgs &a, hipStream_t st) {
     if (a.k == 0) return hipSuccess;
-    const size_t sm = table_smem(a.n);
+    const size_t sm = cost_smem(a.n);
     hipLaunchKernelGGL(cost_kernel, dim3(a.k), dim3(256), sm, st, a);
     return report(hipGetLastError(), "kernel launch");
 }
@@ -176,7 +334,7 @@ hipError_t launch_cost(const TableArgs &a, hipStream_t st) {
 hipError_t launch_table(const TableArgs &a, hipStream_t st) {
     if (a.k == 0) return hipSuccess;
     const size_t sm = table_smem(a.n);
-    hipLaunchKernelGGL(table_kernel, dim3(a.k), dim3(256), sm, st, a);
+    hipLaunchKernelGGL(table_kernel, dim3(a.k), dim3(TB_LANES), sm, st, a);
     return report(hipGetLastError(), "kernel launch");
 }
 
