@@ -51,15 +51,18 @@ __host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym, boo
     Smem s;
     int o = 0;
     auto take = [&o](int bytes) { int at = o; o += (bytes + 15) & ~15; return at; };
-    auto take_mat = [&o]() { o = (o + 255) & ~255; return o; };   // matrices start on 256-byte boundaries
+    // Matrices start 0, 64, 128, 192 bytes past a 256-byte boundary (G, G^T, D, D^T): the
+    // lanes of one index read the same row of the four matrices at once, and 256 bytes
+    // span every LDS bank, so equal skews would put all four reads in the same banks.
+    auto take_mat = [&o](int skew) { o = ((o + 255) & ~255) + skew; return o; };
     if (dglobal) {
         s.d = s.dt = -1;
     } else {
-        s.d = take_mat(); o += n * rs;
-        s.dt = sym ? s.d : take_mat(); if (!sym) o += n * rs;
+        s.d = take_mat(128); o += n * rs;
+        s.dt = sym ? s.d : take_mat(192); if (!sym) o += n * rs;
     }
-    s.g = take_mat(); o += n * rs;
-    s.gt = sym ? s.g : take_mat(); if (!sym) o += n * rs;
+    s.g = take_mat(0); o += n * rs;
+    s.gt = sym ? s.g : take_mat(64); if (!sym) o += n * rs;
     s.acbe = take(np * 8);
     s.rpr = take(np * 4);
     s.rps = take(np * 4);

@@ -78,6 +78,30 @@ __device__ inline long long wave_min64(long long v) {
     return ((long long)hi << 32) | (unsigned)lo;
 }
 
+// Minimum of a signed 32-bit value over the wave (same DPP steps, one v_min each).
+__device__ inline int wave_min32(int v) {
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false));   // row_shr:1
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xF, 0xF, false));   // row_shr:2
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false));   // row_shr:4
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xF, false));   // row_shr:8
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));   // row_bcast:15
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// The wave's lowest (delta, key) as (delta << 32 | key): the lowest delta first, then
+// the lowest key among the lanes that hold it (read from that lane when it is alone).
+__device__ inline long long wave_min_pair(int d, int key) {
+    const int wd = wave_min32(d);
+    const unsigned long long tie = __ballot(d == wd);
+    int wk;
+    if (__builtin_popcountll(tie) == 1)
+        wk = __builtin_amdgcn_readlane(key, (int)__builtin_ctzll(tie));
+    else
+        wk = wave_min32(d == wd ? key : KEY_NONE);
+    return ((long long)wd << 32) | (unsigned)wk;
+}
+
 __device__ inline long long wave_sum64(long long v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
@@ -184,15 +208,15 @@ __device__ inline void row_bytes(const uint8_t *row, int u0, unsigned (&w)[(ROWS
 // One whole search (or one chunk of it) by the calling workgroup; every lane of the
 // block takes part.  MAXT: (index, family) tasks one lane may carry (blockDim.x * MAXT
 // >= families * n).
-template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM>
-__device__ __attribute__((always_inline)) void search_body(const Item &a, unsigned char *sm) {
+template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool SYM>
+__device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsigned char *sm) {
     __shared__ int s_bad;
     __shared__ int s_chunk_end;   // chunked runs: set by thread 0 once the clock budget is spent
     const int n = a.n, rs = row_stride(n), L = blockDim.x, t = threadIdx.x;
     const int nb16 = (n + 15) & ~15;   // bytes of a row the dot products read (zero past n)
     const int lane = t & 63, wid = t >> 6, W = L >> 6;
-    const int sym = a.sym;
-    const int nq = families(sym), lq = sym ? 1 : 2;
+    constexpr int sym = SYM ? 1 : 0;   // F and D both symmetric (the caller checked a.sym)
+    constexpr int nq = SYM ? 2 : 4, lq = SYM ? 1 : 2;
     const int np = padded_n(n, ROWS);
     const Smem S = smem_plan(n, np, L, sym, STREAM);
     SearchState *const st = RESUME ? a.st : nullptr;   // saved state, chunked runs only
@@ -339,17 +363,42 @@ __device__ __attribute__((always_inline)) void search_body(const Item &a, unsign
         }
     };
     // lowest admissible slot of a tile at iteration itx (aspiration threshold thr), as
-    // (delta << 32 | key), key = u << 9 | v; slots are scanned in key order
+    // (delta << 32 | key), key = u << 9 | v; among equal deltas the lowest slot, i.e. the
+    // lowest key.  Up to 8 rows: one 32-bit key per slot, delta * 2^SB + slot, with
+    // inadmissible and non-move slots at LIM (above every delta, |delta| < 2^26), so one
+    // v_min per slot finds both.
     auto tile_min = [&](const int (&d)[ROWS][4], const int (&u_)[UTR][4], int tu0, int tv0, int itx,
                         int thr) -> long long {
         int bd = INT32_MAX, bs = -1;
+        if constexpr (ROWS <= 8) {
+            constexpr int SB = ROWS == 2 ? 3 : (ROWS == 4 ? 4 : 5);
+            constexpr int LIM = (1 << 26) - 1;
+            int best = INT32_MAX;
 #pragma unroll
-        for (int j = 0; j < ROWS; ++j) {
+            for (int j = 0; j < ROWS; ++j) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int x = d[j][e];
-                const bool adm = TABU ? (u_[j][e] <= itx || x < thr) : true;
-                if (adm && x < bd) { bd = x; bs = j * 4 + e; }
+                for (int e = 0; e < 4; ++e) {
+                    const int x = d[j][e];
+                    const bool adm = TABU ? (u_[j][e] <= itx || x < thr) : true;
+                    const int m = adm ? min(x, LIM) : LIM;
+                    best = min(best, m * (1 << SB) + (j * 4 + e));
+                }
+            }
+            bd = best >> SB;
+            bs = best & ((1 << SB) - 1);
+            if (bd == LIM) {
+                bd = INT32_MAX;
+                bs = -1;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < ROWS; ++j) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int x = d[j][e];
+                    const bool adm = TABU ? (u_[j][e] <= itx || x < thr) : true;
+                    if (adm && x < bd) { bd = x; bs = j * 4 + e; }
+                }
             }
         }
         const int key = bs < 0 ? KEY_NONE : (((tu0 + (bs >> 2)) << 9) | (tv0 + (bs & 3)));
@@ -425,21 +474,26 @@ __device__ __attribute__((always_inline)) void search_body(const Item &a, unsign
         // ---- select: lowest (delta, key) over the admissible slots (streamed kernels
         //      found their lane's candidate while updating the tiles)
         if (!STREAM) sel = active ? tile_min(dl, ut, u0, v0, it, aspiration()) : NO_MOVE;
-        const long long kw = wave_min64(sel);
+        const long long kw = wave_min_pair((int)(sel >> 32), (int)(sel & 0xffffffffLL));
         if (lane == 0) red[wid] = kw;
         __syncthreads();  // B1
         if (RESUME && s_chunk_end) break;   // uniform: every lane reads the same word
-        // workgroup minimum: the W wave minima, two per 16-byte load (slots past W hold
-        // the largest key)
-        long long mk = LLONG_MAX;
+        // workgroup minimum of the wave minima: every slot this block size can use
+        // (16 / MAXT waves at most; slots past W hold the largest key), all loads issued
+        // before the first compare, then a tree
+        constexpr int NP = 8 / MAXT;   // 16-byte loads, two minima each
+        long long mv[2 * NP];
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            if (2 * p < W) {
-                const longlong2 o = reinterpret_cast<const longlong2 *>(red)[p];
-                mk = o.x < mk ? o.x : mk;
-                mk = o.y < mk ? o.y : mk;
-            }
+        for (int p = 0; p < NP; ++p) {
+            const longlong2 o = reinterpret_cast<const longlong2 *>(red)[p];
+            mv[2 * p] = o.x;
+            mv[2 * p + 1] = o.y;
         }
+#pragma unroll
+        for (int w2 = NP; w2 >= 1; w2 >>= 1)
+#pragma unroll
+            for (int p = 0; p < w2; ++p) mv[p] = mv[p + w2] < mv[p] ? mv[p + w2] : mv[p];
+        const long long mk = mv[0];
         // the winner is the same in every lane: keep it in scalar registers
         const int dstar = __builtin_amdgcn_readfirstlane((int)(mk >> 32));
         if (TABU ? (dstar == INT32_MAX) : (dstar >= 0)) {
@@ -488,9 +542,25 @@ __device__ __attribute__((always_inline)) void search_body(const Item &a, unsign
                                  ((unsigned)M[tr ? s * rs + u : u * rs + s] << 8) |
                                  ((unsigned)M[tr ? s * rs + r : r * rs + r] << 16) |
                                  ((unsigned)M[tr ? s * rs + s : r * rs + s] << 24);
+            const int ex = sym ? M[s * rs + s] : 0;
+
+            // dot products with the O(1) correction sum_k a[sigma k] c[k] = a.c + (a_s - a_r)(c_r - c_s),
+            // a a row of G or G^T, c a row of D or D^T:
+            //   f = 0: sum_k G'[u][k] D[b][k]    a = G[sigma u],   c = D[b]
+            //   f = 1: sum_k G'[k][u] D[k][b]    a = G^T[sigma u], c = D^T[b]
+            //   f = 2: sum_k D[u][k] G'[b][k]    a = G[sigma b],   c = D[u]
+            //   f = 3: sum_k D[k][u] G'[k][b]    a = G^T[sigma b], c = D^T[u]
+            // One loop for every family: the row shared by both sides first, then the side rows.
+            // (Issued before the bytes above are used, so their latency hides under the loop.)
+            const uint8_t *Gf = (f & 1) ? GmT : Gm, *Df = (f & 1) ? DmT : Dm;
+            const uint8_t *shared = f < 2 ? Gf + su * rs : Df + u * rs;
+            const uint8_t *side1 = f < 2 ? Df + r * rs : Gf + s * rs;
+            const uint8_t *side2 = f < 2 ? Df + s * rs : Gf + r * rs;
+            unsigned d1, d2;
+            dot_rows2(shared, side1, side2, nb16, d1, d2);
+
             unsigned rd_, rdt_, rg_, rgt_, exd = 0, exg = 0;
             if (sym) {
-                const int ex = M[s * rs + s];
                 rd_ = rdt_ = (unsigned)dpp<0xA0>((int)rec);
                 rg_ = rgt_ = (unsigned)dpp<0xF5>((int)rec);
                 exd = (unsigned)dpp<0xA0>(ex);
@@ -514,19 +584,6 @@ __device__ __attribute__((always_inline)) void search_body(const Item &a, unsign
                 sw_gss = G_ss;
             }
 
-            // dot products with the O(1) correction sum_k a[sigma k] c[k] = a.c + (a_s - a_r)(c_r - c_s),
-            // a a row of G or G^T, c a row of D or D^T:
-            //   f = 0: sum_k G'[u][k] D[b][k]    a = G[sigma u],   c = D[b]
-            //   f = 1: sum_k G'[k][u] D[k][b]    a = G^T[sigma u], c = D^T[b]
-            //   f = 2: sum_k D[u][k] G'[b][k]    a = G[sigma b],   c = D[u]
-            //   f = 3: sum_k D[k][u] G'[k][b]    a = G^T[sigma b], c = D^T[u]
-            // One loop for every family: the row shared by both sides first, then the side rows.
-            const uint8_t *Gf = (f & 1) ? GmT : Gm, *Df = (f & 1) ? DmT : Dm;
-            const uint8_t *shared = f < 2 ? Gf + su * rs : Df + u * rs;
-            const uint8_t *side1 = f < 2 ? Df + r * rs : Gf + s * rs;
-            const uint8_t *side2 = f < 2 ? Df + s * rs : Gf + r * rs;
-            unsigned d1, d2;
-            dot_rows2(shared, side1, side2, nb16, d1, d2);
             // (a_s - a_r) and (c_r - c_s) for the sides r and s, chosen without branches
             const int a0 = (u == r ? G_ss : (u == s ? G_rs : g_us)) - (u == r ? G_sr : (u == s ? G_rr : g_ur));
             const int a1 = (u == r ? G_ss : (u == s ? G_sr : g_su)) - (u == r ? G_rs : (u == s ? G_rr : g_ru));
@@ -829,6 +886,15 @@ __device__ __attribute__((always_inline)) void search_body(const Item &a, unsign
         }
     }
     __syncthreads();
+}
+
+// The search body for both symmetric and general instances (one uniform branch).
+template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM>
+__device__ __attribute__((always_inline)) void search_body(const Item &a, unsigned char *sm) {
+    if (a.sym)
+        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, true>(a, sm);
+    else
+        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, false>(a, sm);
 }
 
 // One search per workgroup: block b runs search job0 + b of the launch.
