@@ -20,10 +20,12 @@ constexpr int TILE_COLS = 4;   // columns of the register tile held by one lane
 // decreases, so this only bounds a run on inconsistent data).
 constexpr int TWO_OPT_MAX_MOVES = 1 << 20;
 
-// Rows are padded to RS bytes, an odd multiple of 16: every row starts 16-byte aligned,
-// and 16 consecutive rows start in 16 different groups of four LDS banks, so the
-// 16-byte row reads of a wave (one row per index) do not collide.
-__host__ __device__ inline int row_stride(int n) { return (((n + 15) >> 4) | 1) << 4; }
+// Rows are padded to RS bytes, an odd multiple of 16 (16 more than n rounded up to 32):
+// every row starts 16-byte aligned, 16 consecutive rows start in 16 different groups of
+// four LDS banks, so the 16-byte row reads of a wave (one row per index) do not
+// collide, and the zero padding covers n rounded up to 32, so row dot products may
+// step 32 bytes at a time.
+__host__ __device__ inline int row_stride(int n) { return ((n + 31) & ~31) + 16; }
 
 // Number of indices (locations or units) addressable by a tile of `rows` x 4.
 __host__ __device__ inline int padded_n(int n, int rows) {

@@ -78,27 +78,35 @@ __device__ inline long long wave_min64(long long v) {
     return ((long long)hi << 32) | (unsigned)lo;
 }
 
-// Minimum of a signed 32-bit value over the wave (same DPP steps, one v_min each).
+// Minimum of a signed 32-bit value over the first `LANES` lanes of the wave (16 or 64),
+// by DPP row shifts and row broadcasts; lanes that shift in from outside a row see
+// INT32_MAX, the identity of min, so each step is one v_min_i32 with a DPP operand.
+template <int LANES>
 __device__ inline int wave_min32(int v) {
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false));   // row_shr:1
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xF, 0xF, false));   // row_shr:2
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false));   // row_shr:4
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xF, false));   // row_shr:8
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));   // row_bcast:15
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));   // row_bcast:31
+    constexpr int I = INT32_MAX;
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x111, 0xF, 0xF, false));   // row_shr:1
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x112, 0xF, 0xF, false));   // row_shr:2
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x114, 0xF, 0xF, false));   // row_shr:4
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x118, 0xF, 0xF, false));   // row_shr:8
+    if constexpr (LANES == 16) return __builtin_amdgcn_readlane(v, 15);
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x142, 0xA, 0xF, false));   // row_bcast:15
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x143, 0xC, 0xF, false));   // row_bcast:31
     return __builtin_amdgcn_readlane(v, 63);
 }
 
-// The wave's lowest (delta, key) as (delta << 32 | key): the lowest delta first, then
-// the lowest key among the lanes that hold it (read from that lane when it is alone).
+// The lowest (delta, key) over the first `LANES` lanes as (delta << 32 | key): the lowest
+// delta first, then the lowest key among the lanes that hold it (read from that lane
+// when it is alone).  Lanes past LANES are ignored.
+template <int LANES>
 __device__ inline long long wave_min_pair(int d, int key) {
-    const int wd = wave_min32(d);
-    const unsigned long long tie = __ballot(d == wd);
+    const int wd = wave_min32<LANES>(d);
+    unsigned long long tie = __ballot(d == wd);
+    if constexpr (LANES == 16) tie &= 0xFFFFull;
     int wk;
     if (__builtin_popcountll(tie) == 1)
         wk = __builtin_amdgcn_readlane(key, (int)__builtin_ctzll(tie));
     else
-        wk = wave_min32(d == wd ? key : KEY_NONE);
+        wk = wave_min32<LANES>(d == wd ? key : KEY_NONE);
     return ((long long)wd << 32) | (unsigned)wk;
 }
 
@@ -160,32 +168,41 @@ __device__ inline unsigned dot_rows(const uint8_t *a, const uint8_t *b, int rs) 
     return acc;
 }
 
-// Two dot products sharing the row `a`, over the first rs bytes (a multiple of 16); the
-// loads of the next 16-byte column block are issued before the current one is used.
+// Two dot products sharing the row `a`, over the first rs bytes (a multiple of 32), 32
+// bytes a step; the loads of the next step are issued before the current one is used.
 __device__ inline void dot_rows2(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
                                  unsigned &o2) {
     unsigned c1 = 0, c2 = 0;
-    uint4 x = *reinterpret_cast<const uint4 *>(a);
-    uint4 y = *reinterpret_cast<const uint4 *>(b1);
-    uint4 z = *reinterpret_cast<const uint4 *>(b2);
-    for (int w = 16; w <= rs; w += 16) {
-        uint4 xn = x, yn = y, zn = z;
+    uint4 x0 = *reinterpret_cast<const uint4 *>(a), x1 = *reinterpret_cast<const uint4 *>(a + 16);
+    uint4 y0 = *reinterpret_cast<const uint4 *>(b1), y1 = *reinterpret_cast<const uint4 *>(b1 + 16);
+    uint4 z0 = *reinterpret_cast<const uint4 *>(b2), z1 = *reinterpret_cast<const uint4 *>(b2 + 16);
+    for (int w = 32; w <= rs; w += 32) {
+        uint4 nx0 = x0, nx1 = x1, ny0 = y0, ny1 = y1, nz0 = z0, nz1 = z1;
         if (w < rs) {
-            xn = *reinterpret_cast<const uint4 *>(a + w);
-            yn = *reinterpret_cast<const uint4 *>(b1 + w);
-            zn = *reinterpret_cast<const uint4 *>(b2 + w);
+            nx0 = *reinterpret_cast<const uint4 *>(a + w);
+            nx1 = *reinterpret_cast<const uint4 *>(a + w + 16);
+            ny0 = *reinterpret_cast<const uint4 *>(b1 + w);
+            ny1 = *reinterpret_cast<const uint4 *>(b1 + w + 16);
+            nz0 = *reinterpret_cast<const uint4 *>(b2 + w);
+            nz1 = *reinterpret_cast<const uint4 *>(b2 + w + 16);
         }
-        c1 = __builtin_amdgcn_udot4(x.x, y.x, c1, false);
-        c1 = __builtin_amdgcn_udot4(x.y, y.y, c1, false);
-        c1 = __builtin_amdgcn_udot4(x.z, y.z, c1, false);
-        c1 = __builtin_amdgcn_udot4(x.w, y.w, c1, false);
-        c2 = __builtin_amdgcn_udot4(x.x, z.x, c2, false);
-        c2 = __builtin_amdgcn_udot4(x.y, z.y, c2, false);
-        c2 = __builtin_amdgcn_udot4(x.z, z.z, c2, false);
-        c2 = __builtin_amdgcn_udot4(x.w, z.w, c2, false);
-        x = xn;
-        y = yn;
-        z = zn;
+        c1 = __builtin_amdgcn_udot4(x0.x, y0.x, c1, false);
+        c1 = __builtin_amdgcn_udot4(x0.y, y0.y, c1, false);
+        c1 = __builtin_amdgcn_udot4(x0.z, y0.z, c1, false);
+        c1 = __builtin_amdgcn_udot4(x0.w, y0.w, c1, false);
+        c2 = __builtin_amdgcn_udot4(x0.x, z0.x, c2, false);
+        c2 = __builtin_amdgcn_udot4(x0.y, z0.y, c2, false);
+        c2 = __builtin_amdgcn_udot4(x0.z, z0.z, c2, false);
+        c2 = __builtin_amdgcn_udot4(x0.w, z0.w, c2, false);
+        c1 = __builtin_amdgcn_udot4(x1.x, y1.x, c1, false);
+        c1 = __builtin_amdgcn_udot4(x1.y, y1.y, c1, false);
+        c1 = __builtin_amdgcn_udot4(x1.z, y1.z, c1, false);
+        c1 = __builtin_amdgcn_udot4(x1.w, y1.w, c1, false);
+        c2 = __builtin_amdgcn_udot4(x1.x, z1.x, c2, false);
+        c2 = __builtin_amdgcn_udot4(x1.y, z1.y, c2, false);
+        c2 = __builtin_amdgcn_udot4(x1.z, z1.z, c2, false);
+        c2 = __builtin_amdgcn_udot4(x1.w, z1.w, c2, false);
+        x0 = nx0; x1 = nx1; y0 = ny0; y1 = ny1; z0 = nz0; z1 = nz1;
     }
     o1 = c1;
     o2 = c2;
@@ -214,6 +231,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     __shared__ int s_chunk_end;   // chunked runs: set by thread 0 once the clock budget is spent
     const int n = a.n, rs = row_stride(n), L = blockDim.x, t = threadIdx.x;
     const int nb16 = (n + 15) & ~15;   // bytes of a row the dot products read (zero past n)
+    const int nb32 = (n + 31) & ~31;   // the same, for the 32-byte steps of the row recomputation
     const int lane = t & 63, wid = t >> 6, W = L >> 6;
     constexpr int sym = SYM ? 1 : 0;   // F and D both symmetric (the caller checked a.sym)
     constexpr int nq = SYM ? 2 : 4, lq = SYM ? 1 : 2;
@@ -458,7 +476,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             sel = c < sel ? c : sel;
         }
     }
-    if (t >= W && t < 16) red[t] = LLONG_MAX;   // unused wave-minimum slots
+    if (t >= W && t < 16) red[t] = NO_MOVE;   // unused wave-minimum slots
     bool stopped = false;
     __syncthreads();
 
@@ -474,26 +492,15 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         // ---- select: lowest (delta, key) over the admissible slots (streamed kernels
         //      found their lane's candidate while updating the tiles)
         if (!STREAM) sel = active ? tile_min(dl, ut, u0, v0, it, aspiration()) : NO_MOVE;
-        const long long kw = wave_min_pair((int)(sel >> 32), (int)(sel & 0xffffffffLL));
+        const long long kw = wave_min_pair<64>((int)(sel >> 32), (int)(sel & 0xffffffffLL));
         if (lane == 0) red[wid] = kw;
         __syncthreads();  // B1
         if (RESUME && s_chunk_end) break;   // uniform: every lane reads the same word
-        // workgroup minimum of the wave minima: every slot this block size can use
-        // (16 / MAXT waves at most; slots past W hold the largest key), all loads issued
-        // before the first compare, then a tree
-        constexpr int NP = 8 / MAXT;   // 16-byte loads, two minima each
-        long long mv[2 * NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const longlong2 o = reinterpret_cast<const longlong2 *>(red)[p];
-            mv[2 * p] = o.x;
-            mv[2 * p + 1] = o.y;
-        }
-#pragma unroll
-        for (int w2 = NP; w2 >= 1; w2 >>= 1)
-#pragma unroll
-            for (int p = 0; p < w2; ++p) mv[p] = mv[p + w2] < mv[p] ? mv[p + w2] : mv[p];
-        const long long mk = mv[0];
+        // workgroup minimum of the 16 wave-minimum slots (slots past W hold the largest
+        // key): lane i of every wave reads slot i, then the same two-pass DPP minimum
+        // over the first 16 lanes
+        const long long rv = red[lane & 15];
+        const long long mk = wave_min_pair<16>((int)(rv >> 32), (int)(rv & 0xffffffffLL));
         // the winner is the same in every lane: keep it in scalar registers
         const int dstar = __builtin_amdgcn_readfirstlane((int)(mk >> 32));
         if (TABU ? (dstar == INT32_MAX) : (dstar >= 0)) {
@@ -557,7 +564,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             const uint8_t *side1 = f < 2 ? Df + r * rs : Gf + s * rs;
             const uint8_t *side2 = f < 2 ? Df + s * rs : Gf + r * rs;
             unsigned d1, d2;
-            dot_rows2(shared, side1, side2, nb16, d1, d2);
+            dot_rows2(shared, side1, side2, nb32, d1, d2);
 
             unsigned rd_, rdt_, rg_, rgt_, exd = 0, exg = 0;
             if (sym) {
@@ -899,7 +906,8 @@ __device__ __attribute__((always_inline)) void search_body(const Item &a, unsign
 
 // One search per workgroup: block b runs search job0 + b of the launch.
 template <int ROWS, bool TABU>
-__global__ void __launch_bounds__(max_lanes<ROWS>()) search_kernel(SearchArgs a) {
+__global__ void __launch_bounds__(max_lanes<ROWS>())
+__attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const int job = a.job0 + blockIdx.x;
     Item it{};
