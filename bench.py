@@ -39,8 +39,8 @@ BYTES_PER_EVAL = 8   # an int32 delta read and written per entry per step if kep
 # valid only for the kernel sources they were taken with.
 KERNEL_SOURCES = ["paper_2307_11248_amd/csrc/qap_search.hip", "paper_2307_11248_amd/csrc/qap_internal.h"]
 TRAFFIC = {
-    "c2_n64_dense_tabu": {"bytes": 1487872 + 40960, "sources": "97c30e6b9d38a700"},
-    "c4_batched_uneven_tabu": {"bytes": 227851520 + 1719120, "sources": "97c30e6b9d38a700"},
+    "c2_n64_dense_tabu": {"bytes": 1503232 + 40960, "sources": "a942a70fd261c498"},
+    "c4_batched_uneven_tabu": {"bytes": 2 * (54912 + 43045 + 29502) * 1024 + (261458 + 409 + 10459) * 1024, "sources": "a942a70fd261c498"},
 }
 
 
