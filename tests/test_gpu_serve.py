@@ -141,3 +141,13 @@ def test_serve_chunked_equals_unchunked():
     assert sa["chunks"] > sb["chunks"] == 2
     for x, y in zip(a, b):
         assert (x[0] == y[0]).all() and x[1:3] == y[1:3]
+
+
+def test_serve_admission_bounded_by_slots():
+    reqs = requests(54, [50, 70, 90, 110, 60, 80], 300, 900)
+    note("serve with two slots")
+    got, peak, saw_queue, stats = serve_all(reqs, max_active=2, chunk_ms=0.1)
+    assert saw_queue and peak <= 2
+    for i, r in enumerate(reqs):
+        ep, ec, ed = alone(r)
+        assert (got[i][0] == ep).all() and got[i][1] == ec and got[i][2] == ed, i
