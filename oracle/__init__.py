@@ -59,6 +59,8 @@ def _load():
             lib.orc_delta.argtypes = [ctypes.c_int, _i32p, _i32p, _i32p, ctypes.c_int, ctypes.c_int]
             lib.orc_delta_table.restype = None
             lib.orc_delta_table.argtypes = [ctypes.c_int, _i32p, _i32p, _i32p, _i64p]
+            lib.orc_delta_table_contraction.restype = None
+            lib.orc_delta_table_contraction.argtypes = [ctypes.c_int, _i32p, _i32p, _i32p, _i64p]
             lib.orc_delta_update.restype = None
             lib.orc_delta_update.argtypes = [ctypes.c_int, _i32p, _i32p, _i32p, ctypes.c_int,
                                              ctypes.c_int, _i64p]
@@ -118,6 +120,16 @@ def delta_table(F, D, perm) -> np.ndarray:
     F, D, p = _mat(F, n), _mat(D, n), _vec(perm, n)
     out = np.zeros(n * (n - 1) // 2, dtype=np.int64)
     _load().orc_delta_table(n, _p32(F), _p32(D), _p32(p), _p64(out))
+    return out
+
+
+def delta_table_contraction(F, D, perm) -> np.ndarray:
+    """The same table from the contraction form T = G.D^T + G^T.D (G = F[p][p]):
+    delta(i, j) = T_ij + T_ji - T_ii - T_jj + c_ij."""
+    n = len(perm)
+    F, D, p = _mat(F, n), _mat(D, n), _vec(perm, n)
+    out = np.zeros(n * (n - 1) // 2, dtype=np.int64)
+    _load().orc_delta_table_contraction(n, _p32(F), _p32(D), _p32(p), _p64(out))
     return out
 
 

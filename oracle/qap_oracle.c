@@ -71,6 +71,55 @@ ORC_EXPORT void orc_delta_table(int n, const int32_t *F, const int32_t *D, const
 }
 
 /*
+ * The whole neighbourhood in contraction form: with G[a][b] = F[p_a][p_b] and
+ * T = G.D^T + G^T.D (two n x n x n products),
+ *   delta(i, j) = T_ij + T_ji - T_ii - T_jj + c_ij,
+ * where c_ij gathers the k = i and k = j terms of Eq. (2) (with its diagonal
+ * term) that the sums over all k count differently:
+ *   c_ij = -(D_ji - D_ii)(G_ii - G_ji) - (D_jj - D_ij)(G_ij - G_jj)
+ *          -(D_ij - D_ii)(G_ii - G_ij) - (D_jj - D_ji)(G_ji - G_jj)
+ *          +(D_ji - D_ij)(G_ij - G_ji) + (D_jj - D_ii)(G_ii - G_jj).
+ * Written out with plain loops; it must equal orc_delta_table exactly.
+ */
+ORC_EXPORT void orc_delta_table_contraction(int n, const int32_t *F, const int32_t *D, const int32_t *p,
+                                            int64_t *out) {
+    int64_t *G = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * n);
+    int64_t *T = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * n);
+    if (!G || !T) {
+        free(G);
+        free(T);
+        return;
+    }
+    for (int a = 0; a < n; a++)
+        for (int b = 0; b < n; b++) G[(size_t)a * n + b] = F[(size_t)p[a] * n + p[b]];
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) {
+            int64_t t = 0;
+            for (int k = 0; k < n; k++)
+                t += G[(size_t)i * n + k] * D[(size_t)j * n + k]      /* (G D^T)_ij */
+                   + G[(size_t)k * n + i] * D[(size_t)k * n + j];     /* (G^T D)_ij */
+            T[(size_t)i * n + j] = t;
+        }
+#define GG(a, b) G[(size_t)(a) * n + (b)]
+#define DD(a, b) ((int64_t)D[(size_t)(a) * n + (b)])
+    for (int i = 0; i < n; i++)
+        for (int j = i + 1; j < n; j++) {
+            const int64_t c = -(DD(j, i) - DD(i, i)) * (GG(i, i) - GG(j, i))
+                              - (DD(j, j) - DD(i, j)) * (GG(i, j) - GG(j, j))
+                              - (DD(i, j) - DD(i, i)) * (GG(i, i) - GG(i, j))
+                              - (DD(j, j) - DD(j, i)) * (GG(j, i) - GG(j, j))
+                              + (DD(j, i) - DD(i, j)) * (GG(i, j) - GG(j, i))
+                              + (DD(j, j) - DD(i, i)) * (GG(i, i) - GG(j, j));
+            out[pidx(n, i, j)] = T[(size_t)i * n + j] + T[(size_t)j * n + i] - T[(size_t)i * n + i] -
+                                 T[(size_t)j * n + j] + c;
+        }
+#undef GG
+#undef DD
+    free(G);
+    free(T);
+}
+
+/*
  * Incremental neighbourhood update after the move (r, s) has been applied
  * (Taillard 1991, the reference the paper follows for its elementary tabu
  * search).  `p_before` is the permutation BEFORE the move; `tab` holds the

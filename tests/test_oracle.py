@@ -264,3 +264,24 @@ def test_tabu_premature_stop_forced():
     for mode in (0, 1):
         _, _, done, _ = oracle.tabu(F, D, [2, 0, 1], 10, 50, 50, 1, 0, mode=mode)
         assert done <= 3
+
+
+@pytest.mark.parametrize("n,sym,diag", [(2, False, True), (3, False, True), (5, True, True), (6, False, True),
+                                        (17, False, False), (40, True, False)])
+def test_contraction_form_equals_eq2_and_cost_differences(n, sym, diag):
+    """The contraction form (the definition the neighbourhood-table kernel computes) must
+    equal Eq. (2) with its diagonal term everywhere, and, for small n, z(swap) - z."""
+    rng = np.random.default_rng(500 + n)
+    F, D = W.random_instance(rng, n, 0, 255, symmetric=sym, diag=diag)
+    for p in W.starts(rng, n, 3):
+        t = oracle.delta_table_contraction(F, D, p)
+        assert (t == oracle.delta_table(F, D, p)).all()
+        if n <= 6:
+            z = oracle.cost(F, D, p)
+            k = 0
+            for r in range(n):
+                for s_ in range(r + 1, n):
+                    q = p.copy()
+                    q[r], q[s_] = q[s_], q[r]
+                    assert t[k] == oracle.cost(F, D, q) - z
+                    k += 1
