@@ -208,6 +208,64 @@ __device__ inline void dot_rows2(const uint8_t *a, const uint8_t *b1, const uint
     o2 = c2;
 }
 
+// dot_rows2 in 16-byte steps (half the registers of the 32-byte form; for kernels held
+// to 128 VGPRs, where the wider steps spill).
+__device__ inline void dot_rows2_16(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
+                                    unsigned &o2) {
+    unsigned c1 = 0, c2 = 0;
+    uint4 x = *reinterpret_cast<const uint4 *>(a);
+    uint4 y = *reinterpret_cast<const uint4 *>(b1);
+    uint4 z = *reinterpret_cast<const uint4 *>(b2);
+    for (int w = 16; w <= rs; w += 16) {
+        uint4 xn = x, yn = y, zn = z;
+        if (w < rs) {
+            xn = *reinterpret_cast<const uint4 *>(a + w);
+            yn = *reinterpret_cast<const uint4 *>(b1 + w);
+            zn = *reinterpret_cast<const uint4 *>(b2 + w);
+        }
+        c1 = __builtin_amdgcn_udot4(x.x, y.x, c1, false);
+        c1 = __builtin_amdgcn_udot4(x.y, y.y, c1, false);
+        c1 = __builtin_amdgcn_udot4(x.z, y.z, c1, false);
+        c1 = __builtin_amdgcn_udot4(x.w, y.w, c1, false);
+        c2 = __builtin_amdgcn_udot4(x.x, z.x, c2, false);
+        c2 = __builtin_amdgcn_udot4(x.y, z.y, c2, false);
+        c2 = __builtin_amdgcn_udot4(x.z, z.z, c2, false);
+        c2 = __builtin_amdgcn_udot4(x.w, z.w, c2, false);
+        x = xn;
+        y = yn;
+        z = zn;
+    }
+    o1 = c1;
+    o2 = c2;
+}
+
+// dot_rows2 for rows of exactly 64 bytes with every load in flight at once: one memory
+// latency instead of two (used where the kernel has registers to spare).
+__device__ inline void dot_rows2_64(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, unsigned &o1,
+                                    unsigned &o2) {
+    unsigned c1 = 0, c2 = 0;
+    uint4 x[4], y[4], z[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        x[h] = *reinterpret_cast<const uint4 *>(a + 16 * h);
+        y[h] = *reinterpret_cast<const uint4 *>(b1 + 16 * h);
+        z[h] = *reinterpret_cast<const uint4 *>(b2 + 16 * h);
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        c1 = __builtin_amdgcn_udot4(x[h].x, y[h].x, c1, false);
+        c1 = __builtin_amdgcn_udot4(x[h].y, y[h].y, c1, false);
+        c1 = __builtin_amdgcn_udot4(x[h].z, y[h].z, c1, false);
+        c1 = __builtin_amdgcn_udot4(x[h].w, y[h].w, c1, false);
+        c2 = __builtin_amdgcn_udot4(x[h].x, z[h].x, c2, false);
+        c2 = __builtin_amdgcn_udot4(x[h].y, z[h].y, c2, false);
+        c2 = __builtin_amdgcn_udot4(x[h].z, z[h].z, c2, false);
+        c2 = __builtin_amdgcn_udot4(x[h].w, z[h].w, c2, false);
+    }
+    o1 = c1;
+    o2 = c2;
+}
+
 // ROWS consecutive bytes of an LDS row starting at u0 (u0 a multiple of ROWS): whole
 // words for ROWS >= 4, else one word and the byte offset of u0 inside it.
 template <int ROWS>
@@ -224,8 +282,9 @@ __device__ inline void row_bytes(const uint8_t *row, int u0, unsigned (&w)[(ROWS
 
 // One whole search (or one chunk of it) by the calling workgroup; every lane of the
 // block takes part.  MAXT: (index, family) tasks one lane may carry (blockDim.x * MAXT
-// >= families * n).
-template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool SYM>
+// >= families * n).  NARROW: the row recomputation reads 16 bytes a step instead of 32
+// (for kernels held to 128 VGPRs, where the wider steps spill).
+template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool SYM, bool NARROW>
 __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsigned char *sm) {
     __shared__ int s_bad;
     __shared__ int s_chunk_end;   // chunked runs: set by thread 0 once the clock budget is spent
@@ -392,6 +451,26 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             constexpr int SB = ROWS == 2 ? 3 : (ROWS == 4 ? 4 : 5);
             constexpr int LIM = (1 << 26) - 1;
             int best = INT32_MAX;
+            if constexpr (ROWS <= 2 && MAXT == 1) {
+                // small tiles with registers to spare: a tree of mins (three dependent
+                // steps for eight slots instead of a chain of eight)
+                int kv[ROWS * 4];
+#pragma unroll
+                for (int j = 0; j < ROWS; ++j) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int x = d[j][e];
+                        const bool adm = TABU ? (u_[j][e] <= itx || x < thr) : true;
+                        const int m = adm ? min(x, LIM) : LIM;
+                        kv[j * 4 + e] = m * (1 << SB) + (j * 4 + e);
+                    }
+                }
+#pragma unroll
+                for (int w2 = ROWS * 2; w2 >= 1; w2 >>= 1)
+#pragma unroll
+                    for (int q = 0; q < w2; ++q) kv[q] = min(kv[q], kv[q + w2]);
+                best = kv[0];
+            } else {
 #pragma unroll
             for (int j = 0; j < ROWS; ++j) {
 #pragma unroll
@@ -401,6 +480,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                     const int m = adm ? min(x, LIM) : LIM;
                     best = min(best, m * (1 << SB) + (j * 4 + e));
                 }
+            }
             }
             bd = best >> SB;
             bs = best & ((1 << SB) - 1);
@@ -564,7 +644,16 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             const uint8_t *side1 = f < 2 ? Df + r * rs : Gf + s * rs;
             const uint8_t *side2 = f < 2 ? Df + s * rs : Gf + r * rs;
             unsigned d1, d2;
-            dot_rows2(shared, side1, side2, nb32, d1, d2);
+            if constexpr (MAXT == 1) {
+                if (nb32 == 64)
+                    dot_rows2_64(shared, side1, side2, d1, d2);
+                else
+                    dot_rows2(shared, side1, side2, nb32, d1, d2);
+            } else if constexpr (NARROW) {
+                dot_rows2_16(shared, side1, side2, nb16, d1, d2);
+            } else {
+                dot_rows2(shared, side1, side2, nb32, d1, d2);
+            }
 
             unsigned rd_, rdt_, rg_, rgt_, exd = 0, exg = 0;
             if (sym) {
@@ -896,12 +985,12 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
 }
 
 // The search body for both symmetric and general instances (one uniform branch).
-template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM>
+template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool NARROW>
 __device__ __attribute__((always_inline)) void search_body(const Item &a, unsigned char *sm) {
     if (a.sym)
-        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, true>(a, sm);
+        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, true, NARROW>(a, sm);
     else
-        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, false>(a, sm);
+        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, false, NARROW>(a, sm);
 }
 
 // One search per workgroup: block b runs search job0 + b of the launch.
@@ -930,7 +1019,7 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
     it.hi = a.hi;
     it.seed = a.seed;
     it.start_id = a.start_base + job;
-    search_body<ROWS, TABU, max_tasks<ROWS>(), false, false>(it, sm);
+    search_body<ROWS, TABU, max_tasks<ROWS>(), false, false, !TABU && ROWS <= 8>(it, sm);
 }
 
 // The batched launch, one kernel per tile shape: block i runs items[i] as one tabu
@@ -954,7 +1043,7 @@ batch_group_kernel(BatchArgs b) {
         it.tile_d = b.tile_work + it.tile_off;
         it.tile_u = it.tile_d + stream_tile_int4(it.ntiles) / 2;
     }
-    search_body<ROWS, true, 1024 / LANES, false, STREAM>(it, sm);
+    search_body<ROWS, true, 1024 / LANES, false, STREAM, ROWS <= 4>(it, sm);
 }
 
 // Chunked runs: block i runs one chunk of items[i] (absolute pointers, st != null).
@@ -962,13 +1051,13 @@ __global__ void __launch_bounds__(BATCH_LANES) resume_kernel(const Item *items) 
     extern __shared__ __align__(16) unsigned char sm[];
     const Item it = items[blockIdx.x];
     if (it.stream) {
-        search_body<STREAM_ROWS, true, 1024 / BATCH_LANES, true, true>(it, sm);
+        search_body<STREAM_ROWS, true, 1024 / BATCH_LANES, true, true, true>(it, sm);
         return;
     }
     switch (it.rows) {
-        case 2: search_body<2, true, 1024 / BATCH_LANES, true, false>(it, sm); break;
-        case 4: search_body<4, true, 1024 / BATCH_LANES, true, false>(it, sm); break;
-        default: search_body<8, true, 1024 / BATCH_LANES, true, false>(it, sm); break;
+        case 2: search_body<2, true, 1024 / BATCH_LANES, true, false, true>(it, sm); break;
+        case 4: search_body<4, true, 1024 / BATCH_LANES, true, false, true>(it, sm); break;
+        default: search_body<8, true, 1024 / BATCH_LANES, true, false, true>(it, sm); break;
     }
 }
 
@@ -999,7 +1088,7 @@ __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     it.stream = 1;
     it.tile_d = a.tile_work + (size_t)blockIdx.x * a.tile_stride;
     it.tile_u = it.tile_d + a.tile_stride / 2;
-    search_body<STREAM_ROWS, TABU, 1024 / BATCH_LANES, false, true>(it, sm);
+    search_body<STREAM_ROWS, TABU, 1024 / BATCH_LANES, false, true, false>(it, sm);
 }
 
 template <int ROWS, bool TABU>
