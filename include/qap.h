@@ -243,7 +243,7 @@ int qap_server_destroy(qap_server_handle s);
 /*
  * Tile shape of the search kernels (the thread-configuration search of Sec. 5.2,
  * re-done for gfx950): each lane of a search's workgroup holds a block of `rows` x 4
- * neighbourhood entries in registers, rows in {2, 4, 8, 16}; rows = -8 selects the
+ * neighbourhood entries in registers, rows in {1, 2, 4, 8, 16}; rows = -8 selects the
  * streamed kernel (tiles of 8 rows kept in global memory and updated in passes, D read
  * from global memory; 512 lanes; serves every n up to QAP_NMAX); 0 restores the
  * library's own choice for this n (the smallest register tile that fits, else the
@@ -263,7 +263,7 @@ int qap_get_tile_rows(qap_handle h, int32_t algo, int32_t *lanes_out);
  * `iters` iterations (2opt: at most `iters` moves) from fixed pseudo-random starts with
  * every shape that fits n, times the search kernel with HIP events (one warm-up run
  * first), stores the fastest as the handle's shape for algo and returns its rows.
- * ms_out (float[5] or NULL) receives the time per rows value 2, 4, 8, 16, -8, or -1
+ * ms_out (float[6] or NULL) receives the time per rows value 1, 2, 4, 8, 16, -8, or -1
  * where a shape does not fit.  Blocking; allocates its own device buffers; results do not
  * depend on the shape, only the time does.
  */

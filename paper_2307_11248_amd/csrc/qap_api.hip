@@ -16,7 +16,7 @@ using namespace qapk;
 
 namespace qaph {
 
-const int kRowsChoices[4] = {2, 4, 8, 16};
+const int kRowsChoices[kShapes] = {1, 2, 4, 8, 16};
 
 struct TileSet {
     int32_t *d_tiles = nullptr;
@@ -90,7 +90,7 @@ struct qap_ctx {
     int n = 0, m = 0, sym = 0, device = 0;
     size_t max_smem = 0;
     uint8_t *d_mats = nullptr;       // [F | F^T | D | D^T] u8, n rows of row_stride(n) bytes
-    TileSet tiles[4];                // one per entry of kRowsChoices
+    TileSet tiles[kShapes];          // one per entry of kRowsChoices
     // per algorithm (0 tabu, 1 2opt, 2 batched tabu): index into kRowsChoices, kStream for
     // the streamed kernel, -1 when no kernel serves this n
     int rows_choice[3] = {0, 0, 0};
@@ -102,11 +102,16 @@ namespace {
 
 // Shape index of the streamed kernel (tiles of STREAM_ROWS rows in global memory); the
 // ABI names it rows = -STREAM_ROWS.
-constexpr int kStream = 4;
+constexpr int kStream = kShapes;
+// The batched kernels serve rows 2, 4 and 8: shape indices kBatchFirst .. kBatchFirst + 2,
+// in the order of the BV_R2, BV_R4, BV_R8 variants.
+constexpr int kBatchFirst = 1;
+// Shape index of the STREAM_ROWS tile list, which the streamed kernel walks.
+constexpr int kStreamList = 3;
 
 int rows_index(int rows) {
     if (rows == -STREAM_ROWS) return kStream;
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kShapes; ++i)
         if (kRowsChoices[i] == rows) return i;
     return -1;
 }
@@ -114,11 +119,11 @@ int rows_index(int rows) {
 int shape_rows(int ri) { return ri == kStream ? -STREAM_ROWS : kRowsChoices[ri]; }
 
 // The tile list a shape uses (the streamed kernel uses the STREAM_ROWS list).
-const TileSet &shape_tiles(const qap_ctx *h, int ri) { return h->tiles[ri == kStream ? 2 : ri]; }
+const TileSet &shape_tiles(const qap_ctx *h, int ri) { return h->tiles[ri == kStream ? kStreamList : ri]; }
 
 bool shape_fits(const qap_ctx *h, int ri) {
     if (ri == kStream) return h->stream_ok != 0;
-    if (ri < 0 || ri > 3) return false;
+    if (ri < 0 || ri >= kShapes) return false;
     const TileSet &ts = h->tiles[ri];
     if (ts.lanes < 64 || ts.lanes > search_max_lanes(kRowsChoices[ri])) return false;
     if (ts.ntiles > ts.lanes) return false;
@@ -128,7 +133,7 @@ bool shape_fits(const qap_ctx *h, int ri) {
 // Default tile shape: the smallest tile that fits (the most lanes per search, hence the
 // shortest dependency chain per iteration).
 int default_rows(const qap_ctx *h) {
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kShapes; ++i)
         if (shape_fits(h, i)) return i;
     return h->stream_ok ? kStream : -1;
 }
@@ -239,7 +244,7 @@ int run_search(qap_ctx *h, int algo, int32_t *d_perms, int k, int iters, int lo,
 // BATCH_LANES lanes, rows 2, 4 or 8).
 bool batch_fits(const qap_ctx *h, int ri) {
     if (ri == kStream) return h->stream_ok != 0;
-    if (ri < 0 || ri > 2) return false;
+    if (ri < kBatchFirst || ri > kBatchFirst + 2) return false;
     const TileSet &ts = h->tiles[ri];
     return ts.d_tiles && batch_shape_ok(h->n, kRowsChoices[ri], ts.ntiles, h->sym) &&
            search_smem_bytes(h->n, kRowsChoices[ri], BATCH_LANES, h->sym) <= h->max_smem;
@@ -247,7 +252,7 @@ bool batch_fits(const qap_ctx *h, int ri) {
 
 // Default batched shape: the smallest tile that fits.
 int batch_default(const qap_ctx *h) {
-    for (int i = 0; i < 3; ++i)
+    for (int i = kBatchFirst; i < kBatchFirst + 3; ++i)
         if (batch_fits(h, i)) return i;
     return h->stream_ok ? kStream : -1;
 }
@@ -340,7 +345,7 @@ int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out) {
     h->max_smem = (size_t)smem;
     hipError_t e = hipMalloc((void **)&h->d_mats, pack.size());
     if (e == hipSuccess) e = hipMemcpy(h->d_mats, pack.data(), pack.size(), hipMemcpyHostToDevice);
-    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+    for (int i = 0; i < kShapes && e == hipSuccess; ++i) {
         int ninner = 0;
         std::vector<int32_t> tl = enumerate_tiles(n, kRowsChoices[i], &ninner);
         TileSet &ts = h->tiles[i];
@@ -398,7 +403,7 @@ int qap_get_tile_rows(qap_handle h, int32_t algo, int32_t *lanes_out) {
 
 int qap_tune_tile_rows(qap_handle h, int32_t algo, int32_t k, int32_t iters, float *ms_out) {
     if (!h || algo < 0 || algo > 2 || k <= 0 || iters <= 0) return QAP_E_INVALID;
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i <= kStream; ++i)
         if (ms_out) ms_out[i] = -1.0f;
     const int n = h->n;
     std::vector<int32_t> hp;
@@ -621,7 +626,7 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
         const TileSet &ts = shape_tiles(h, ri);
         const size_t sm = streamed ? stream_smem_bytes(h->n, h->sym)
                                    : search_smem_bytes(h->n, kRowsChoices[ri], BATCH_LANES, h->sym);
-        const int var = streamed ? BV_STREAM : ri;   // BV_R2, BV_R4, BV_R8 follow kRowsChoices
+        const int var = streamed ? BV_STREAM : ri - kBatchFirst;   // BV_R2, BV_R4, BV_R8
         gsmem[var] = std::max(gsmem[var], sm);
         tsmem = std::max(tsmem, table_smem_bytes(h->n));
         for (int j = 0; j < k_per[i]; ++j) {

@@ -9,7 +9,8 @@
 namespace qaph {
 
 // Tile heights of the search kernels.
-extern const int kRowsChoices[4];
+constexpr int kShapes = 5;   // register tile shapes: rows 1, 2, 4, 8, 16
+extern const int kRowsChoices[kShapes];
 
 // Tiles of `rows` x 4 that hold at least one move (u < v), interior tiles first; each
 // entry is g | b << 16 (row group g, column block b).

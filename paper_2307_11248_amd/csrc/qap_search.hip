@@ -266,20 +266,6 @@ __device__ inline void dot_rows2_64(const uint8_t *a, const uint8_t *b1, const u
     o2 = c2;
 }
 
-// ROWS consecutive bytes of an LDS row starting at u0 (u0 a multiple of ROWS): whole
-// words for ROWS >= 4, else one word and the byte offset of u0 inside it.
-template <int ROWS>
-__device__ inline void row_bytes(const uint8_t *row, int u0, unsigned (&w)[(ROWS + 3) / 4], int &shift) {
-    if (ROWS >= 4) {
-#pragma unroll
-        for (int i = 0; i < (ROWS + 3) / 4; ++i) w[i] = *reinterpret_cast<const unsigned *>(row + u0 + 4 * i);
-        shift = 0;
-    } else {
-        w[0] = *reinterpret_cast<const unsigned *>(row + (u0 & ~3));
-        shift = u0 & 3;
-    }
-}
-
 // One whole search (or one chunk of it) by the calling workgroup; every lane of the
 // block takes part.  MAXT: (index, family) tasks one lane may carry (blockDim.x * MAXT
 // >= families * n).  NARROW: the row recomputation reads 16 bytes a step instead of 32
@@ -448,7 +434,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                         int thr) -> long long {
         int bd = INT32_MAX, bs = -1;
         if constexpr (ROWS <= 8) {
-            constexpr int SB = ROWS == 2 ? 3 : (ROWS == 4 ? 4 : 5);
+            constexpr int SB = ROWS == 1 ? 2 : (ROWS == 2 ? 3 : (ROWS == 4 ? 4 : 5));
             constexpr int LIM = (1 << 26) - 1;
             int best = INT32_MAX;
             if constexpr (ROWS <= 2 && MAXT == 1) {
@@ -813,22 +799,32 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 const int4 c23 = reinterpret_cast<const int4 *>(acbe + 2 * v0)[1];
                 acv[0] = c01.x; bev[0] = c01.y; acv[1] = c01.z; bev[1] = c01.w;
                 acv[2] = c23.x; bev[2] = c23.y; acv[3] = c23.z; bev[3] = c23.w;
+                if constexpr (ROWS == 1) {
+                    const int2 w = reinterpret_cast<const int2 *>(acbe + 2 * u0)[0];
+                    acu[0] = w.x; beu[0] = w.y;
+                } else {
 #pragma unroll
-                for (int j = 0; j < ROWS; j += 2) {
-                    const int4 w = reinterpret_cast<const int4 *>(acbe + 2 * (u0 + j))[0];
-                    acu[j] = w.x; beu[j] = w.y; acu[j + 1] = w.z; beu[j + 1] = w.w;
+                    for (int j = 0; j < ROWS; j += 2) {
+                        const int4 w = reinterpret_cast<const int4 *>(acbe + 2 * (u0 + j))[0];
+                        acu[j] = w.x; beu[j] = w.y; acu[j + 1] = w.z; beu[j + 1] = w.w;
+                    }
                 }
             }
             // recomputed deltas of rows/columns r and s at this tile's indices (stored + K)
             const int4 rv = *reinterpret_cast<const int4 *>(rpr + v0);
             const int4 sv = *reinterpret_cast<const int4 *>(rps + v0);
             int rpru[ROWS], rpsu[ROWS];
+            if constexpr (ROWS == 1) {
+                rpru[0] = rpr[u0];
+                rpsu[0] = rps[u0];
+            } else {
 #pragma unroll
-            for (int j = 0; j < ROWS; j += 2) {
-                const int2 x2 = *reinterpret_cast<const int2 *>(rpr + u0 + j);
-                const int2 y2 = *reinterpret_cast<const int2 *>(rps + u0 + j);
-                rpru[j] = x2.x; rpru[j + 1] = x2.y;
-                rpsu[j] = y2.x; rpsu[j + 1] = y2.y;
+                for (int j = 0; j < ROWS; j += 2) {
+                    const int2 x2 = *reinterpret_cast<const int2 *>(rpr + u0 + j);
+                    const int2 y2 = *reinterpret_cast<const int2 *>(rps + u0 + j);
+                    rpru[j] = x2.x; rpru[j + 1] = x2.y;
+                    rpsu[j] = y2.x; rpsu[j + 1] = y2.y;
+                }
             }
 #pragma unroll
             for (int j = 0; j < ROWS; ++j) {
@@ -896,11 +892,16 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 }
             }
             if (boundary) {
+                // padding slots back to BIG; the tests run on opaque copies of the tile
+                // origin so that they are made here rather than kept as one mask per
+                // slot through the whole loop (scalar registers the loop needs)
+                int pu = u0, pv = v0;
+                asm volatile("" : "+v"(pu), "+v"(pv));
 #pragma unroll
                 for (int j = 0; j < ROWS; ++j)
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        if (u0 + j >= n || v0 + e >= n) dl[j][e] = BIG;
+                        if (pu + j >= n || pv + e >= n) dl[j][e] = BIG;
             }
             return tabu_set;
         };
@@ -1171,6 +1172,8 @@ hipError_t launch_search(int rows, bool tabu, const SearchArgs &a, int grid, int
     if (grid <= 0) return hipSuccess;
     const size_t smem = search_smem_bytes(a.n, rows, lanes, a.sym);
     switch (rows * 2 + (tabu ? 1 : 0)) {
+        case 2: return launch_one<1, false>(a, grid, lanes, smem, st);
+        case 3: return launch_one<1, true>(a, grid, lanes, smem, st);
         case 4: return launch_one<2, false>(a, grid, lanes, smem, st);
         case 5: return launch_one<2, true>(a, grid, lanes, smem, st);
         case 8: return launch_one<4, false>(a, grid, lanes, smem, st);

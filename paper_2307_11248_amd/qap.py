@@ -115,7 +115,7 @@ def _check(rc: int, what: str) -> int:
 
 
 def _check_rows(rc: int, what: str) -> int:
-    """Tile rows are returned as 2, 4, 8, 16 or -8 (the streamed kernel); other negative
+    """Tile rows are returned as 1, 2, 4, 8, 16 or -8 (the streamed kernel); other negative
     values are error codes."""
     if rc < 0 and rc != -8:
         raise QapError(rc, what)
@@ -199,10 +199,10 @@ class Handle:
     def tune_tile_rows(self, algo: str, k: int = 256, iters: int = 300):
         """Time every fitting shape on the device and keep the fastest (``qap_tune_tile_rows``).
         Returns (rows, {rows: ms} for the shapes that fit)."""
-        ms = (ctypes.c_float * 5)()
+        ms = (ctypes.c_float * 6)()
         rows = _check_rows(lib().qap_tune_tile_rows(self.ptr, ALGOS[algo], int(k), int(iters), ms),
                            "qap_tune_tile_rows")
-        return rows, {r: float(t) for r, t in zip((2, 4, 8, 16, -8), ms) if t >= 0}
+        return rows, {r: float(t) for r, t in zip((1, 2, 4, 8, 16, -8), ms) if t >= 0}
 
     # -- blocking host calls
     def cost(self, perms) -> np.ndarray:

@@ -84,10 +84,10 @@ def test_two_opt_config1_full():
 
 
 def tile_shapes(h, algo):
-    """Every tile shape that serves this n: register tiles of 2, 4, 8, 16 rows, and the
+    """Every tile shape that serves this n: register tiles of 1, 2, 4, 8, 16 rows, and the
     streamed kernel (-8: tiles of 8 rows kept in global memory between passes)."""
     out = []
-    for rows in (2, 4, 8, 16, -8):
+    for rows in (1, 2, 4, 8, 16, -8):
         try:
             h.set_tile_rows(algo, rows)
             out.append(rows)
