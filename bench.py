@@ -383,7 +383,7 @@ def main():
     algo = w.algo
     if args.tile_rows:
         h.set_tile_rows(algo, args.tile_rows)
-    rows, lanes = h.tile_rows(algo)
+    rows, lanes = h.launch_tile_rows(algo, k)   # the shape the launch of all k starts uses
 
     stream = torch.cuda.Stream()
     starts = torch.from_numpy(I.perms).cuda()

@@ -246,16 +246,24 @@ int qap_server_destroy(qap_server_handle s);
  * neighbourhood entries in registers, rows in {1, 2, 4, 8, 16}; rows = -8 selects the
  * streamed kernel (tiles of 8 rows kept in global memory and updated in passes, D read
  * from global memory; 512 lanes; serves every n up to QAP_NMAX); 0 restores the
- * library's own choice for this n (the smallest register tile that fits, else the
- * streamed kernel).  algo: 0 = tabu, 1 = 2opt, 2 = this instance inside a batch
+ * library's own choice, made per launch for tabu and 2opt: among the register tiles that
+ * fit n, the one that needs the fewest rounds of workgroups over the compute units for
+ * the launch's k starts (HIP's occupancy query), ties going to the smallest tile; else
+ * the streamed kernel.  A shape set here (or by the autotuner) holds for every launch.  algo: 0 = tabu, 1 = 2opt, 2 = this instance inside a batch
  * (qap_batch_create with rows_per NULL or 0; rows 2, 4, 8 or -8, fixed workgroup of 512
  * lanes).  Returns QAP_E_UNSUPPORTED if the shape does not fit this n (lanes or LDS).
  */
 int qap_set_tile_rows(qap_handle h, int32_t algo, int32_t rows);
 
 /* Tile rows currently used for algo, and the lanes per search in *lanes_out (may be
- * NULL). */
+ * NULL); in the automatic mode, the shape of a launch of one start.  Same as
+ * qap_launch_tile_rows(h, algo, 1, lanes_out). */
 int qap_get_tile_rows(qap_handle h, int32_t algo, int32_t *lanes_out);
+
+/* Tile rows (and lanes per search in *lanes_out, may be NULL) that a launch of k >= 1
+ * starts of algo uses: the shape set for algo, or the automatic choice for k.
+ * QAP_E_INVALID for bad arguments, QAP_E_UNSUPPORTED if no kernel serves n. */
+int qap_launch_tile_rows(qap_handle h, int32_t algo, int32_t k, int32_t *lanes_out);
 
 /*
  * Autotuner of the tile shape (replaces the paper's search over thread counts and block

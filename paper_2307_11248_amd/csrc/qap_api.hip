@@ -95,6 +95,10 @@ struct qap_ctx {
     // the streamed kernel, -1 when no kernel serves this n
     int rows_choice[3] = {0, 0, 0};
     int rows_default[3] = {0, 0, 0};
+    // tabu and 2opt: the shape is picked per launch (launch_shape) until one is set
+    int auto_rows[2] = {1, 1};
+    int cus = 0;                     // compute units of the device
+    int blocks_cache[2][kShapes];    // workgroups per compute unit per shape, -1 = not asked yet
     int stream_ok = 0;               // the streamed kernel serves this n
 };
 
@@ -138,6 +142,32 @@ int default_rows(const qap_ctx *h) {
     return h->stream_ok ? kStream : -1;
 }
 
+// Shape a launch of k tabu (algo 0) or 2opt (algo 1) searches uses: the handle's shape
+// once one is set, else the fitting register shape that needs the fewest rounds of
+// workgroups over the device's compute units, ties going to the smallest tile (the most
+// lanes per search, hence the shortest dependency chain per iteration); the streamed
+// kernel when no register shape fits.  A small tile is fastest while every search has a
+// compute unit of its own; with many more searches than compute units a larger tile on
+// fewer lanes lets more searches share a compute unit.
+int launch_shape(qap_ctx *h, int algo, int k) {
+    if (algo == 2 || !h->auto_rows[algo]) return h->rows_choice[algo];
+    int best = -1;
+    long long best_rounds = 0;
+    for (int ri = 0; ri < kShapes; ++ri) {
+        if (!shape_fits(h, ri)) continue;
+        int &nb = h->blocks_cache[algo][ri];
+        if (nb < 0) nb = search_blocks_per_cu(h->n, kRowsChoices[ri], algo == 0, h->tiles[ri].lanes, h->sym);
+        if (nb <= 0 || h->cus <= 0) continue;
+        const long long per_round = (long long)nb * h->cus;
+        const long long rounds = ((long long)k + per_round - 1) / per_round;
+        if (best < 0 || rounds < best_rounds) {
+            best = ri;
+            best_rounds = rounds;
+        }
+    }
+    return best >= 0 ? best : h->rows_choice[algo];
+}
+
 
 // RAII device buffer for the blocking entry points.
 struct DevBuf {
@@ -153,8 +183,9 @@ struct HostCall {
     hipError_t init() { return hipStreamCreateWithFlags(&st, hipStreamNonBlocking); }
 };
 
-SearchArgs base_args(qap_ctx *h, int algo) {
-    const TileSet &ts = shape_tiles(h, h->rows_choice[algo]);
+// Arguments shared by every search of a launch with tile shape ri (its tile list).
+SearchArgs base_args(const qap_ctx *h, int ri) {
+    const TileSet &ts = shape_tiles(h, ri);
     SearchArgs a{};
     a.mats = h->d_mats;
     a.n = h->n;
@@ -180,7 +211,10 @@ int make_tables(qap_ctx *h, const int32_t *d_perms, int k, int32_t **d_table, hi
 hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t *d_table, int k, int iters,
                            int lo, int hi, uint64_t seed, int64_t start_base, int64_t *d_cost, int32_t *d_steps,
                            hipStream_t st, bool plain) {
-    SearchArgs a = base_args(h, algo);
+    // one shape for the whole launch: its kernel and its tile list
+    const int ri = launch_shape(h, algo, k);
+    if (ri < 0) return hipErrorInvalidValue;
+    SearchArgs a = base_args(h, ri);
     a.table = d_table;
     a.perms_in = d_perms;
     a.perm_out = d_perms;
@@ -191,7 +225,6 @@ hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t
     a.hi = hi;
     a.seed = seed;
     a.start_base = start_base;
-    const int ri = h->rows_choice[algo];
     hipError_t e = hipSuccess;
     if (ri == kStream) {
         // tile state in stream-ordered scratch, one slice per search of a launch
@@ -343,6 +376,12 @@ int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out) {
         return QAP_E_DEVICE;
     }
     h->max_smem = (size_t)smem;
+    if (hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) {
+        delete h;
+        return QAP_E_DEVICE;
+    }
+    for (auto &row : h->blocks_cache)
+        for (int &x : row) x = -1;
     hipError_t e = hipMalloc((void **)&h->d_mats, pack.size());
     if (e == hipSuccess) e = hipMemcpy(h->d_mats, pack.data(), pack.size(), hipMemcpyHostToDevice);
     for (int i = 0; i < kShapes && e == hipSuccess; ++i) {
@@ -384,19 +423,25 @@ int qap_set_tile_rows(qap_handle h, int32_t algo, int32_t rows) {
     if (!h || algo < 0 || algo > 2) return QAP_E_INVALID;
     if (rows == 0) {
         h->rows_choice[algo] = h->rows_default[algo];
+        if (algo < 2) h->auto_rows[algo] = 1;
         return QAP_OK;
     }
     const int ri = rows_index(rows);
     if (ri < 0) return QAP_E_INVALID;
     if (!algo_fits(h, algo, ri)) return QAP_E_UNSUPPORTED;
     h->rows_choice[algo] = ri;
+    if (algo < 2) h->auto_rows[algo] = 0;
     return QAP_OK;
 }
 
 int qap_get_tile_rows(qap_handle h, int32_t algo, int32_t *lanes_out) {
-    if (!h || algo < 0 || algo > 2) return QAP_E_INVALID;
-    const int ri = h->rows_choice[algo];
-    if (ri < 0) return QAP_E_UNSUPPORTED;
+    return qap_launch_tile_rows(h, algo, 1, lanes_out);
+}
+
+int qap_launch_tile_rows(qap_handle h, int32_t algo, int32_t k, int32_t *lanes_out) {
+    if (!h || algo < 0 || algo > 2 || k < 1) return QAP_E_INVALID;
+    if (h->rows_choice[algo] < 0) return QAP_E_UNSUPPORTED;
+    const int ri = launch_shape(h, algo, k);
     if (lanes_out) *lanes_out = (algo == 2 || ri == kStream) ? BATCH_LANES : h->tiles[ri].lanes;
     return shape_rows(ri);
 }
@@ -422,6 +467,8 @@ int qap_tune_tile_rows(qap_handle h, int32_t algo, int32_t k, int32_t iters, flo
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e == hipSuccess) e = hipMemcpyAsync(ds.p, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, c.st);
     const int saved = h->rows_choice[algo];
+    const int saved_auto = algo < 2 ? h->auto_rows[algo] : 0;
+    if (algo < 2) h->auto_rows[algo] = 0;   // time exactly the shape set below
     int best = -1, rc = QAP_OK;
     float best_ms = 0.0f;
     for (int ri = 0; ri <= kStream && e == hipSuccess && rc == QAP_OK; ++ri) {
@@ -466,6 +513,7 @@ int qap_tune_tile_rows(qap_handle h, int32_t algo, int32_t k, int32_t iters, flo
         }
     }
     h->rows_choice[algo] = best >= 0 ? best : saved;
+    if (algo < 2 && best < 0) h->auto_rows[algo] = saved_auto;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return dev_err(e);

@@ -199,6 +199,9 @@ int batch_shape_ok(int n, int rows, int ntiles, int sym);
 enum { BV_R2 = 0, BV_R4, BV_R8, BV_STREAM, BV_COUNT };
 hipError_t launch_batch_group(int variant, const BatchArgs &b, size_t smem, hipStream_t st);
 int search_max_lanes(int rows);
+// Workgroups of the register-tile search kernel for this shape that fit on one compute
+// unit at once (HIP's occupancy query; 0 if it fails).
+int search_blocks_per_cu(int n, int rows, bool tabu, int lanes, int sym);
 // Streamed kernels (any n up to 256): tiles of STREAM_ROWS x 4 slots kept in global memory
 // between passes, D read from global memory, BATCH_LANES lanes per search.
 constexpr int STREAM_ROWS = 8;

@@ -42,8 +42,10 @@ namespace {
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
+// Workgroup cap per tile shape, which also caps the registers of a lane: 1024 lanes (4
+// waves per SIMD) leave 128 VGPRs, 768 (3 per SIMD) 168, 512 (2) 256.
 template <int ROWS>
-constexpr int max_lanes() { return ROWS <= 2 ? 1024 : (ROWS <= 8 ? 512 : 256); }
+constexpr int max_lanes() { return ROWS <= 2 ? 1024 : (ROWS == 4 ? 768 : (ROWS <= 8 ? 512 : 256)); }
 
 // (index, family) tasks one lane may carry: enough for 4 n <= 1024 tasks at the lane cap.
 template <int ROWS>
@@ -1100,7 +1102,36 @@ hipError_t launch_one(const SearchArgs &a, int grid, int lanes, size_t smem, hip
 
 }  // namespace
 
-int search_max_lanes(int rows) { return rows <= 2 ? max_lanes<2>() : (rows <= 8 ? max_lanes<8>() : max_lanes<16>()); }
+int search_max_lanes(int rows) {
+    return rows <= 2 ? max_lanes<2>() : (rows == 4 ? max_lanes<4>() : (rows <= 8 ? max_lanes<8>() : max_lanes<16>()));
+}
+
+namespace {
+template <int ROWS, bool TABU>
+int blocks_one(int lanes, size_t smem) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search_kernel<ROWS, TABU>, lanes, smem) != hipSuccess)
+        return 0;
+    return nb;
+}
+}  // namespace
+
+int search_blocks_per_cu(int n, int rows, bool tabu, int lanes, int sym) {
+    const size_t smem = search_smem_bytes(n, rows, lanes, sym);
+    switch (rows * 2 + (tabu ? 1 : 0)) {
+        case 2: return blocks_one<1, false>(lanes, smem);
+        case 3: return blocks_one<1, true>(lanes, smem);
+        case 4: return blocks_one<2, false>(lanes, smem);
+        case 5: return blocks_one<2, true>(lanes, smem);
+        case 8: return blocks_one<4, false>(lanes, smem);
+        case 9: return blocks_one<4, true>(lanes, smem);
+        case 16: return blocks_one<8, false>(lanes, smem);
+        case 17: return blocks_one<8, true>(lanes, smem);
+        case 32: return blocks_one<16, false>(lanes, smem);
+        case 33: return blocks_one<16, true>(lanes, smem);
+        default: return 0;
+    }
+}
 
 // Block size for a tile shape: at least one lane per tile; one lane per (index, family)
 // task when the workgroup limit allows, else up to MAXT tasks per lane.  Returns 0 when

@@ -27,10 +27,10 @@ QAP_E_UNSUPPORTED = -6
 QAP_NMAX = 256
 
 EXPORTS = [
-    "qap_strerror", "qap_create", "qap_destroy", "qap_size", "qap_cost", "qap_cost_async",
-    "qap_delta_table", "qap_delta_table_async", "qap_2opt", "qap_2opt_async", "qap_tabu",
-    "qap_tabu_async", "qap_tabu_plain_async", "qap_2opt_with_table_async", "qap_tabu_with_table_async",
-    "qap_set_tile_rows", "qap_get_tile_rows", "qap_batch_create", "qap_batch_size", "qap_batch_run_async",
+    "qap_strerror", "qap_create", "qap_destroy", "qap_size", "qap_cost", "qap_cost_async", "qap_delta_table",
+    "qap_delta_table_async", "qap_2opt", "qap_2opt_async", "qap_tabu", "qap_tabu_async",
+    "qap_tabu_plain_async", "qap_2opt_with_table_async", "qap_tabu_with_table_async", "qap_set_tile_rows",
+    "qap_get_tile_rows", "qap_launch_tile_rows", "qap_batch_create", "qap_batch_size", "qap_batch_run_async",
     "qap_batch_tables_async", "qap_batch_search_async", "qap_batch_destroy", "qap_tabu_batch",
     "qap_tune_tile_rows", "qap_server_create", "qap_server_footprint", "qap_server_submit", "qap_server_step",
     "qap_server_result", "qap_server_stats", "qap_server_destroy",
@@ -82,6 +82,7 @@ def lib():
                                                              _vp, _vp]),
                 "qap_set_tile_rows": (ctypes.c_int, [_vp, i32, i32]),
                 "qap_get_tile_rows": (ctypes.c_int, [_vp, i32, _i32p]),
+                "qap_launch_tile_rows": (ctypes.c_int, [_vp, i32, i32, _i32p]),
                 "qap_tune_tile_rows": (ctypes.c_int, [_vp, i32, i32, i32, ctypes.POINTER(ctypes.c_float)]),
                 "qap_server_create": (ctypes.c_int, [i64, i32, ctypes.c_double, ctypes.POINTER(_vp)]),
                 "qap_server_footprint": (i64, [_vp, i32, i32]),
@@ -194,6 +195,13 @@ class Handle:
     def tile_rows(self, algo: str):
         lanes = ctypes.c_int32(0)
         rows = _check_rows(lib().qap_get_tile_rows(self.ptr, ALGOS[algo], ctypes.byref(lanes)), "qap_get_tile_rows")
+        return rows, lanes.value
+
+    def launch_tile_rows(self, algo: str, k: int):
+        """(rows, lanes per search) that a launch of k starts uses (``qap_launch_tile_rows``)."""
+        lanes = ctypes.c_int32(0)
+        rows = _check_rows(lib().qap_launch_tile_rows(self.ptr, ALGOS[algo], int(k), ctypes.byref(lanes)),
+                           "qap_launch_tile_rows")
         return rows, lanes.value
 
     def tune_tile_rows(self, algo: str, k: int = 256, iters: int = 300):

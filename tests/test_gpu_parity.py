@@ -97,6 +97,34 @@ def tile_shapes(h, algo):
     return out
 
 
+def test_automatic_shape_per_launch():
+    """Without a shape set, each launch picks its tile from its number of starts (fewest
+    rounds of workgroups over the compute units, ties to the smallest tile): a launch of
+    one start reports the handle's shape, an explicit shape holds for every launch size,
+    and the 1024-start 2opt launch of the n = 128 workload returns what every explicit
+    shape returns, and what the oracle returns on a sample."""
+    w = W.c3_euclid128_2opt(k=1024)
+    I = w.instances[0]
+    note("automatic shape n=128 k=1024")
+    with qap.Handle(I.F, I.D) as h:
+        shapes = tile_shapes(h, "2opt")
+        for algo in ("tabu", "2opt"):
+            assert h.launch_tile_rows(algo, 1) == h.tile_rows(algo)
+            for k in (1, 256, 1024, 4096):
+                assert h.launch_tile_rows(algo, k)[0] in tile_shapes(h, algo)
+        h.set_tile_rows("2opt", shapes[-1])
+        assert all(h.launch_tile_rows("2opt", k)[0] == shapes[-1] for k in (1, 1024))
+        h.set_tile_rows("2opt", 0)
+        p, c, st = h.two_opt(I.perms)
+        for rows in shapes:
+            h.set_tile_rows("2opt", rows)
+            pe, ce, ste = h.two_opt(I.perms[:64])
+            assert (pe == p[:64]).all() and (ce == c[:64]).all() and (ste == st[:64]).all(), rows
+        h.set_tile_rows("2opt", 0)
+    ep, ec, est = oracle_2opt_many(I.F, I.D, I.perms[::256])
+    assert (p[::256] == ep).all() and (c[::256] == ec).all() and (st[::256] == est).all()
+
+
 @pytest.mark.parametrize("n,sym,diag", [(2, False, False), (3, False, False), (4, True, True), (5, False, False),
                                         (9, False, True), (13, True, False), (17, False, False),
                                         (40, False, True), (64, True, False), (101, False, False),
