@@ -107,8 +107,7 @@ namespace {
 // Shape index of the streamed kernel (tiles of STREAM_ROWS rows in global memory); the
 // ABI names it rows = -STREAM_ROWS.
 constexpr int kStream = kShapes;
-// The batched kernels serve rows 2, 4 and 8: shape indices kBatchFirst .. kBatchFirst + 2,
-// in the order of the BV_R2, BV_R4, BV_R8 variants.
+// The batched kernels serve rows 2, 4 and 8: shape indices kBatchFirst .. kBatchFirst + 2.
 constexpr int kBatchFirst = 1;
 // Shape index of the STREAM_ROWS tile list, which the streamed kernel walks.
 constexpr int kStreamList = 3;
@@ -335,10 +334,7 @@ struct qap_batch {
 
 namespace {
 
-int item_variant(const Item &it) {
-    if (it.stream) return BV_STREAM;
-    return it.rows == 2 ? BV_R2 : (it.rows == 4 ? BV_R4 : BV_R8);
-}
+int item_variant(const Item &it) { return batch_variant(it.n, it.rows, it.stream != 0, it.ntiles, it.sym); }
 
 }  // namespace
 
@@ -442,7 +438,14 @@ int qap_launch_tile_rows(qap_handle h, int32_t algo, int32_t k, int32_t *lanes_o
     if (!h || algo < 0 || algo > 2 || k < 1) return QAP_E_INVALID;
     if (h->rows_choice[algo] < 0) return QAP_E_UNSUPPORTED;
     const int ri = launch_shape(h, algo, k);
-    if (lanes_out) *lanes_out = (algo == 2 || ri == kStream) ? BATCH_LANES : h->tiles[ri].lanes;
+    if (lanes_out) {
+        if (ri == kStream)
+            *lanes_out = BATCH_LANES;
+        else if (algo == 2)   // the batched workgroup this instance's searches get
+            *lanes_out = batch_variant_lanes(batch_variant(h->n, kRowsChoices[ri], false, h->tiles[ri].ntiles, h->sym));
+        else
+            *lanes_out = h->tiles[ri].lanes;
+    }
     return shape_rows(ri);
 }
 
@@ -672,9 +675,10 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
         if (ri < 0 || !batch_fits(h, ri)) return QAP_E_UNSUPPORTED;
         const bool streamed = ri == kStream;
         const TileSet &ts = shape_tiles(h, ri);
+        const int rows = streamed ? STREAM_ROWS : kRowsChoices[ri];
+        const int var = batch_variant(h->n, rows, streamed, ts.ntiles, h->sym);
         const size_t sm = streamed ? stream_smem_bytes(h->n, h->sym)
-                                   : search_smem_bytes(h->n, kRowsChoices[ri], BATCH_LANES, h->sym);
-        const int var = streamed ? BV_STREAM : ri - kBatchFirst;   // BV_R2, BV_R4, BV_R8
+                                   : search_smem_bytes(h->n, rows, batch_variant_lanes(var), h->sym);
         gsmem[var] = std::max(gsmem[var], sm);
         tsmem = std::max(tsmem, table_smem_bytes(h->n));
         for (int j = 0; j < k_per[i]; ++j) {

@@ -194,9 +194,15 @@ size_t search_smem_bytes(int n, int rows, int lanes, int sym);
 // Lanes of the persistent batched kernel, and whether a tile shape can serve n there.
 constexpr int BATCH_LANES = 512;
 int batch_shape_ok(int n, int rows, int ntiles, int sym);
-// Kernel variants of the batched launch, one per tile shape: register tiles of 2, 4, 8
-// rows and the streamed form.  One launch per variant, items of that shape only.
-enum { BV_R2 = 0, BV_R4, BV_R8, BV_STREAM, BV_COUNT };
+// Kernel variants of the batched launch: register tiles of 2, 4, 8 rows and the streamed
+// form on BATCH_LANES lanes, and for searches that need fewer lanes (a lane per tile and
+// per (index, family) task) tiles of 2 rows on 128 or 256 lanes and of 4 rows on 256, so
+// that more small searches share a compute unit.  One launch per variant.
+enum { BV_R2 = 0, BV_R4, BV_R8, BV_STREAM, BV_R2_128, BV_R2_256, BV_R4_256, BV_COUNT };
+// Variant of a batched search: rows 2, 4, 8 or the streamed form, ntiles tiles.
+int batch_variant(int n, int rows, bool streamed, int ntiles, int sym);
+// Lanes of a workgroup of that variant.
+int batch_variant_lanes(int variant);
 hipError_t launch_batch_group(int variant, const BatchArgs &b, size_t smem, hipStream_t st);
 int search_max_lanes(int rows);
 // Workgroups of the register-tile search kernel for this shape that fit on one compute

@@ -632,13 +632,13 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             const uint8_t *side1 = f < 2 ? Df + r * rs : Gf + s * rs;
             const uint8_t *side2 = f < 2 ? Df + s * rs : Gf + r * rs;
             unsigned d1, d2;
-            if constexpr (MAXT == 1) {
+            if constexpr (NARROW) {
+                dot_rows2_16(shared, side1, side2, nb16, d1, d2);
+            } else if constexpr (MAXT == 1) {
                 if (nb32 == 64)
                     dot_rows2_64(shared, side1, side2, d1, d2);
                 else
                     dot_rows2(shared, side1, side2, nb32, d1, d2);
-            } else if constexpr (NARROW) {
-                dot_rows2_16(shared, side1, side2, nb16, d1, d2);
             } else {
                 dot_rows2(shared, side1, side2, nb32, d1, d2);
             }
@@ -1022,7 +1022,7 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
     it.hi = a.hi;
     it.seed = a.seed;
     it.start_id = a.start_base + job;
-    search_body<ROWS, TABU, max_tasks<ROWS>(), false, false, !TABU && ROWS <= 8>(it, sm);
+    search_body<ROWS, TABU, max_tasks<ROWS>(), false, false, !TABU && ROWS == 8>(it, sm);
 }
 
 // The batched launch, one kernel per tile shape: block i runs items[i] as one tabu
@@ -1032,7 +1032,7 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
 // compute unit and hide each other's latency; 8-row and streamed tiles need more
 // registers and run one search per compute unit.  (A persistent loop over a work queue
 // inside one block was tried: keeping its state live made the register tiles spill.)
-template <int ROWS, int LANES, bool STREAM>
+template <int ROWS, int LANES, int MAXT, bool STREAM>
 __global__ void __launch_bounds__(LANES) __attribute__((amdgpu_waves_per_eu(ROWS <= 4 ? 4 : 2)))
 batch_group_kernel(BatchArgs b) {
     extern __shared__ __align__(16) unsigned char sm[];
@@ -1046,7 +1046,7 @@ batch_group_kernel(BatchArgs b) {
         it.tile_d = b.tile_work + it.tile_off;
         it.tile_u = it.tile_d + stream_tile_int4(it.ntiles) / 2;
     }
-    search_body<ROWS, true, 1024 / LANES, false, STREAM, ROWS <= 4>(it, sm);
+    search_body<ROWS, true, MAXT, false, STREAM, ROWS <= 4 && (MAXT > 1 || ROWS == 4)>(it, sm);
 }
 
 // Chunked runs: block i runs one chunk of items[i] (absolute pointers, st != null).
@@ -1150,19 +1150,41 @@ int search_lanes(int n, int rows, int ntiles, int sym) {
     return lanes <= maxl ? lanes : 0;
 }
 
+int batch_variant(int n, int rows, bool streamed, int ntiles, int sym) {
+    if (streamed) return BV_STREAM;
+    // lanes a one-task workgroup needs: one per tile and one per (index, family) task
+    const int need = ntiles > families(sym) * n ? ntiles : families(sym) * n;
+    if (rows == 2) return need <= 128 ? BV_R2_128 : (need <= 256 ? BV_R2_256 : BV_R2);
+    if (rows == 4) return need <= 256 ? BV_R4_256 : BV_R4;
+    return BV_R8;
+}
+
+int batch_variant_lanes(int variant) {
+    return variant == BV_R2_128 ? 128 : (variant == BV_R2_256 || variant == BV_R4_256 ? 256 : BATCH_LANES);
+}
+
 int batch_shape_ok(int n, int rows, int ntiles, int sym) {
     return rows <= 8 && ntiles <= BATCH_LANES && families(sym) * n <= BATCH_LANES * (1024 / BATCH_LANES) ? 1 : 0;
 }
 
 hipError_t launch_batch_group(int variant, const BatchArgs &b, size_t smem, hipStream_t st) {
     if (b.count <= 0) return hipSuccess;
-    constexpr int L = BATCH_LANES;
+    constexpr int L = BATCH_LANES, T = 1024 / BATCH_LANES;
     switch (variant) {
-        case BV_R2: hipLaunchKernelGGL((batch_group_kernel<2, L, false>), dim3(b.count), dim3(L), smem, st, b); break;
-        case BV_R4: hipLaunchKernelGGL((batch_group_kernel<4, L, false>), dim3(b.count), dim3(L), smem, st, b); break;
-        case BV_R8: hipLaunchKernelGGL((batch_group_kernel<8, L, false>), dim3(b.count), dim3(L), smem, st, b); break;
+        case BV_R2: hipLaunchKernelGGL((batch_group_kernel<2, L, T, false>), dim3(b.count), dim3(L), smem, st, b); break;
+        case BV_R4: hipLaunchKernelGGL((batch_group_kernel<4, L, T, false>), dim3(b.count), dim3(L), smem, st, b); break;
+        case BV_R8: hipLaunchKernelGGL((batch_group_kernel<8, L, T, false>), dim3(b.count), dim3(L), smem, st, b); break;
+        case BV_R2_128:
+            hipLaunchKernelGGL((batch_group_kernel<2, 128, 1, false>), dim3(b.count), dim3(128), smem, st, b);
+            break;
+        case BV_R2_256:
+            hipLaunchKernelGGL((batch_group_kernel<2, 256, 1, false>), dim3(b.count), dim3(256), smem, st, b);
+            break;
+        case BV_R4_256:
+            hipLaunchKernelGGL((batch_group_kernel<4, 256, 1, false>), dim3(b.count), dim3(256), smem, st, b);
+            break;
         case BV_STREAM:
-            hipLaunchKernelGGL((batch_group_kernel<STREAM_ROWS, L, true>), dim3(b.count), dim3(L), smem, st, b);
+            hipLaunchKernelGGL((batch_group_kernel<STREAM_ROWS, L, T, true>), dim3(b.count), dim3(L), smem, st, b);
             break;
         default: return hipErrorInvalidValue;
     }

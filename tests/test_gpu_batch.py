@@ -86,6 +86,34 @@ def test_batch_equals_oracle_mixed_n(sizes, k, iters):
         h.close()
 
 
+def test_batch_every_kernel_variant_equals_oracle():
+    """Shapes chosen so that every batched kernel variant runs: tiles of 2 rows on 128,
+    256 and 512 lanes, of 4 rows on 256 and 512, of 8 rows, and the streamed form (a
+    search gets the smallest workgroup with a lane per tile and per (index, family) task)."""
+    sizes = [30, 60, 50, 100, 70, 130, 190]
+    rows = [2, 2, 4, 4, 2, 8, -8]
+    lanes = [128, 256, 256, 512, 512, 512, 512]
+    k = [2, 2, 2, 2, 2, 1, 1]
+    iters = 300
+    insts, lohi, seeds = mixed_batch(7 + sum(sizes), sizes, k)
+    note("batch variants sizes=%s rows=%s" % (sizes, rows))
+    hs = [qap.Handle(F, D) for F, D, _ in insts]
+    for h, r, want in zip(hs, rows, lanes):
+        h.set_tile_rows("batch", r)
+        assert h.tile_rows("batch") == (r, want), (h.n, r)
+    perms = np.concatenate([P.reshape(-1) for _, _, P in insts]).astype(np.int32)
+    p, c, d = qap.tabu_batch(hs, perms, k, iters, [a for a, _ in lohi], [b for _, b in lohi], seeds)
+    jobs, res = oracle_rows(insts, k, iters, lohi, seeds)
+    off = 0
+    for (i, j), r in zip(jobs, res):
+        n = insts[i][0].shape[0]
+        row = sum(k[:i]) + j
+        assert (p[off:off + n] == r[0]).all() and c[row] == r[1] and d[row] == r[2], (i, j, n)
+        off += n
+    for h in hs:
+        h.close()
+
+
 def test_batch_invariance_against_single_instance_searches():
     w = W.c4_batch(m=24, k=4, iters=1200)
     note("batch invariance: 24 instances of the uneven workload, 4 starts x 1200 iterations")
