@@ -327,6 +327,9 @@ struct qap_batch {
     // items are grouped by kernel variant (tile shape); one launch per non-empty group,
     // the groups forked onto side streams so that they share the device
     int group_begin[BV_COUNT] = {}, group_count[BV_COUNT] = {};
+    // launch order of the groups: the one whose longest search is the longest first (the
+    // hardware hands out compute units roughly in launch order)
+    int group_order[BV_COUNT] = {};
     size_t group_smem[BV_COUNT] = {};
     hipStream_t side[BV_COUNT] = {};
     hipEvent_t ev_fork = nullptr, ev_join[BV_COUNT] = {};
@@ -733,7 +736,12 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
     for (int v = 0; v < BV_COUNT; ++v) {
         b->group_smem[v] = gsmem[v];
         ngroups += b->group_count[v] > 0;
+        b->group_order[v] = v;
     }
+    auto longest = [&](int v) {   // n^2 of the group's first (longest) item
+        return b->group_count[v] ? (long long)items[b->group_begin[v]].n * items[b->group_begin[v]].n : -1LL;
+    };
+    std::stable_sort(b->group_order, b->group_order + BV_COUNT, [&](int x, int y) { return longest(x) > longest(y); });
     hipError_t e = hipSuccess;
     if (ngroups > 1) {
         e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
@@ -780,7 +788,8 @@ extern "C" int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int6
     for (int v = 0; v < BV_COUNT; ++v) ngroups += b->group_count[v] > 0;
     hipError_t e = hipSuccess;
     if (ngroups > 1) e = hipEventRecord(b->ev_fork, st);
-    for (int v = 0; v < BV_COUNT && e == hipSuccess; ++v) {
+    for (int g = 0; g < BV_COUNT && e == hipSuccess; ++g) {
+        const int v = b->group_order[g];
         if (!b->group_count[v]) continue;
         BatchArgs a{b->d_items + b->group_begin[v], b->group_count[v], d_perms, d_best, d_done, b->d_table,
                     b->d_tile_work};
