@@ -113,6 +113,24 @@ def test_tile_cache_keys_reuse_and_stale_entries(tmp_path, monkeypatch):
     assert h3.tuned == 1
 
 
+def test_sweep_quality_and_stand_ins():
+    """The parameter sweep's host side: the quality gap, the best-of-k-seeds average, and
+    the two n = 40 stand-in instances (uniform; sparse symmetric flows with Euclidean
+    distances) with the paper's tenure range."""
+    from paper_2307_11248_amd import sweep
+    assert sweep.gap(110, 100) == 10.0 and sweep.gap(100, 100) == 0.0
+    costs = [[120, 110, 130, 100], [105, 125, 100, 100]]
+    assert sweep.seed_quality([c[:1] for c in costs], 100) == 12.5
+    assert sweep.seed_quality([c[:2] for c in costs], 100) == 7.5
+    assert sweep.seed_quality(costs, 100) == 0.0
+    inst = sweep.stand_ins()
+    (Fa, Da), (Fb, Db) = inst["a-like"], inst["b-like"]
+    assert Fa.shape == Da.shape == (40, 40) and not (Fa == Fa.T).all()
+    assert (Fb == Fb.T).all() and (Db == Db.T).all() and (Fb == 0).mean() > 0.5
+    assert max(Fa.max(), Da.max(), Fb.max(), Db.max()) <= 255
+    assert W.paper_tenure_range(40) == (4, 13)
+
+
 def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
