@@ -144,6 +144,20 @@ int qap_tabu_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int
                    int32_t *d_done, void *stream);
 
 /*
+ * qap_tabu_async that also keeps the frequency memory of Sec. 4.3: the number of times
+ * each pair of locations was exchanged (the lower triangle of Tabuarr).  As in the paper
+ * the counts are recorded and returned but decide nothing: the searches and their
+ * results are those of qap_tabu_async.
+ *   d_freq  device int32[k][n(n-1)/2], overwritten: row j holds start j's counts at packed
+ *           pair index r*n - r*(r+1)/2 + (s - r - 1) for r < s (the order of
+ *           qap_delta_table); the counts sum to the moves made.
+ * QAP_E_INVALID if d_freq is NULL with k > 0; otherwise as qap_tabu_async.
+ */
+int qap_tabu_freq_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo,
+                        int32_t hi, uint64_t seed, int64_t start_base, int64_t *d_best,
+                        int32_t *d_done, int32_t *d_freq, void *stream);
+
+/*
  * The plain delivery of qap_tabu_async: the same arithmetic and results, but one kernel
  * launch per start, issued back to back on `stream` (the launch shape the paper uses
  * for its per-search kernels, Sec. 4.4, one search at a time).  Kept as the baseline

@@ -110,6 +110,7 @@ struct SearchArgs {
     int job0;                // search index of block 0
     int4 *tile_work;         // streamed kernels: per search, tile_stride int4 of tile state
     long long tile_stride;
+    int32_t *freq;           // tabu: [k][m] exchange counts per search, or null
 };
 
 // With QAP_VERBOSE set in the environment, report a failed HIP call on stderr.
@@ -168,6 +169,9 @@ struct Item {
     int4 *tile_d, *tile_u;
     int stream;               // 1: the streamed kernel (tiles of STREAM_ROWS rows)
     long long tile_off;       // batched launches: offset of tile_d in the launch's tile work
+    // tabu: the frequency memory, m counts of how often each pair of locations was
+    // exchanged (packed pair index), zeroed when the search starts; null: not kept
+    int32_t *freq;
 };
 
 // The batched launch: one block per item of `items`; per-start buffers are shared by

@@ -271,8 +271,9 @@ __device__ inline void dot_rows2_64(const uint8_t *a, const uint8_t *b1, const u
 // One whole search (or one chunk of it) by the calling workgroup; every lane of the
 // block takes part.  MAXT: (index, family) tasks one lane may carry (blockDim.x * MAXT
 // >= families * n).  NARROW: the row recomputation reads 16 bytes a step instead of 32
-// (for kernels held to 128 VGPRs, where the wider steps spill).
-template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool SYM, bool NARROW>
+// (for kernels held to 128 VGPRs, where the wider steps spill).  FREQ: tabu keeps the
+// frequency memory in a.freq (compiled only into the kernels that need it).
+template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool SYM, bool NARROW, bool FREQ = false>
 __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsigned char *sm) {
     __shared__ int s_bad;
     __shared__ int s_chunk_end;   // chunked runs: set by thread 0 once the clock budget is spent
@@ -312,6 +313,8 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     }
     if (t == 0) s_bad = 0;
     for (int u = t; u < np; u += L) pinv[u] = -1;
+    if (FREQ && a.freq)
+        for (int i = t; i < a.m; i += L) a.freq[i] = 0;
     __syncthreads();
     const int32_t *pin = resume ? a.st_perm : a.perm_in;
     for (int u = t; u < n; u += L) {
@@ -580,6 +583,10 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         const bool improved = TABU && (cur + dstar < best);
         cur += dstar;
         if (improved) best = cur;
+        // frequency memory: one more exchange of locations r and s (a vector atomic that
+        // nothing waits for; the zeroing above finished before the first barrier)
+        if (FREQ && a.freq && t == 0)
+            __hip_atomic_fetch_add(a.freq + pidx(n, r, s), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         // words of rows r and s of G and G^T for the exchange in C (read now, G is not
         // written before B2); lanes 0 .. RS/4-1 of wave 0, which all hold task 0
@@ -988,16 +995,16 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
 }
 
 // The search body for both symmetric and general instances (one uniform branch).
-template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool NARROW>
+template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool NARROW, bool FREQ = false>
 __device__ __attribute__((always_inline)) void search_body(const Item &a, unsigned char *sm) {
     if (a.sym)
-        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, true, NARROW>(a, sm);
+        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, true, NARROW, FREQ>(a, sm);
     else
-        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, false, NARROW>(a, sm);
+        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, false, NARROW, FREQ>(a, sm);
 }
 
 // One search per workgroup: block b runs search job0 + b of the launch.
-template <int ROWS, bool TABU>
+template <int ROWS, bool TABU, bool FREQ = false>
 __global__ void __launch_bounds__(max_lanes<ROWS>())
 __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char sm[];
@@ -1010,6 +1017,7 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
     it.perm_out = a.perm_out + (size_t)job * a.n;
     it.cost_out = a.cost_out + job;
     it.steps_out = a.steps_out ? a.steps_out + job : nullptr;
+    it.freq = FREQ ? a.freq + (size_t)job * a.m : nullptr;
     it.st = nullptr;
     it.n = a.n;
     it.m = a.m;
@@ -1022,7 +1030,7 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
     it.hi = a.hi;
     it.seed = a.seed;
     it.start_id = a.start_base + job;
-    search_body<ROWS, TABU, max_tasks<ROWS>(), false, false, !TABU && ROWS == 8>(it, sm);
+    search_body<ROWS, TABU, max_tasks<ROWS>(), false, false, !TABU && ROWS == 8, FREQ>(it, sm);
 }
 
 // The batched launch, one kernel per tile shape: block i runs items[i] as one tabu
@@ -1065,7 +1073,7 @@ __global__ void __launch_bounds__(BATCH_LANES) resume_kernel(const Item *items) 
 }
 
 // Streamed search, one per workgroup: block b runs search job0 + b of the launch.
-template <bool TABU>
+template <bool TABU, bool FREQ = false>
 __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const int job = a.job0 + blockIdx.x;
@@ -1077,6 +1085,7 @@ __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     it.perm_out = a.perm_out + (size_t)job * a.n;
     it.cost_out = a.cost_out + job;
     it.steps_out = a.steps_out ? a.steps_out + job : nullptr;
+    it.freq = FREQ ? a.freq + (size_t)job * a.m : nullptr;
     it.n = a.n;
     it.m = a.m;
     it.sym = a.sym;
@@ -1091,12 +1100,12 @@ __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     it.stream = 1;
     it.tile_d = a.tile_work + (size_t)blockIdx.x * a.tile_stride;
     it.tile_u = it.tile_d + a.tile_stride / 2;
-    search_body<STREAM_ROWS, TABU, 1024 / BATCH_LANES, false, true, false>(it, sm);
+    search_body<STREAM_ROWS, TABU, 1024 / BATCH_LANES, false, true, false, FREQ>(it, sm);
 }
 
-template <int ROWS, bool TABU>
+template <int ROWS, bool TABU, bool FREQ = false>
 hipError_t launch_one(const SearchArgs &a, int grid, int lanes, size_t smem, hipStream_t st) {
-    hipLaunchKernelGGL((search_kernel<ROWS, TABU>), dim3(grid), dim3(lanes), smem, st, a);
+    hipLaunchKernelGGL((search_kernel<ROWS, TABU, FREQ>), dim3(grid), dim3(lanes), smem, st, a);
     return report(hipGetLastError(), "kernel launch");
 }
 
@@ -1210,7 +1219,9 @@ int stream_shape_ok(int n, int sym, size_t max_smem) {
 hipError_t launch_stream(bool tabu, const SearchArgs &a, int grid, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
     const size_t smem = stream_smem_bytes(a.n, a.sym);
-    if (tabu)
+    if (tabu && a.freq)
+        hipLaunchKernelGGL((stream_kernel<true, true>), dim3(grid), dim3(BATCH_LANES), smem, st, a);
+    else if (tabu)
         hipLaunchKernelGGL(stream_kernel<true>, dim3(grid), dim3(BATCH_LANES), smem, st, a);
     else
         hipLaunchKernelGGL(stream_kernel<false>, dim3(grid), dim3(BATCH_LANES), smem, st, a);
@@ -1224,6 +1235,16 @@ size_t search_smem_bytes(int n, int rows, int lanes, int sym) {
 hipError_t launch_search(int rows, bool tabu, const SearchArgs &a, int grid, int lanes, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
     const size_t smem = search_smem_bytes(a.n, rows, lanes, a.sym);
+    if (tabu && a.freq) {   // the frequency memory: its own instantiations
+        switch (rows) {
+            case 1: return launch_one<1, true, true>(a, grid, lanes, smem, st);
+            case 2: return launch_one<2, true, true>(a, grid, lanes, smem, st);
+            case 4: return launch_one<4, true, true>(a, grid, lanes, smem, st);
+            case 8: return launch_one<8, true, true>(a, grid, lanes, smem, st);
+            case 16: return launch_one<16, true, true>(a, grid, lanes, smem, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (rows * 2 + (tabu ? 1 : 0)) {
         case 2: return launch_one<1, false>(a, grid, lanes, smem, st);
         case 3: return launch_one<1, true>(a, grid, lanes, smem, st);

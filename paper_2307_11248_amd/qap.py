@@ -28,7 +28,7 @@ QAP_NMAX = 256
 
 EXPORTS = [
     "qap_strerror", "qap_create", "qap_destroy", "qap_size", "qap_cost", "qap_cost_async", "qap_delta_table",
-    "qap_delta_table_async", "qap_2opt", "qap_2opt_async", "qap_tabu", "qap_tabu_async",
+    "qap_delta_table_async", "qap_2opt", "qap_2opt_async", "qap_tabu", "qap_tabu_async", "qap_tabu_freq_async",
     "qap_tabu_plain_async", "qap_2opt_with_table_async", "qap_tabu_with_table_async", "qap_set_tile_rows",
     "qap_get_tile_rows", "qap_launch_tile_rows", "qap_batch_create", "qap_batch_size", "qap_batch_run_async",
     "qap_batch_tables_async", "qap_batch_search_async", "qap_batch_destroy", "qap_tabu_batch",
@@ -75,6 +75,8 @@ def lib():
                 "qap_2opt_async": (ctypes.c_int, [_vp, _vp, i32, i32, _vp, _vp, _vp]),
                 "qap_tabu": (ctypes.c_int, [_vp, _i32p, i32, i32, i32, i32, u64, _i64p, _i32p]),
                 "qap_tabu_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, _vp, _vp, _vp]),
+                "qap_tabu_freq_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, _vp, _vp, _vp,
+                                                        _vp]),
                 "qap_tabu_plain_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, _vp, _vp,
                                                         _vp]),
                 "qap_2opt_with_table_async": (ctypes.c_int, [_vp, _vp, _vp, i32, i32, _vp, _vp, _vp]),
@@ -267,6 +269,15 @@ class Handle:
         _check(f(self.ptr, _dptr(d_perms, "int32"), d_perms.shape[0], int(iters), int(lo), int(hi), int(seed),
                  int(start_base), _dptr(d_best, "int64"), _dptr(d_done, "int32"), _stream_ptr(stream)),
                "qap_tabu_async")
+
+    def tabu_freq_async(self, d_perms, iters, lo, hi, seed, d_best, d_freq, d_done=None, start_base: int = 0,
+                        stream=None):
+        """tabu_async that also fills d_freq (int32[k][n(n-1)/2]) with the number of
+        exchanges of each pair of locations (``qap_tabu_freq_async``)."""
+        _check(lib().qap_tabu_freq_async(self.ptr, _dptr(d_perms, "int32"), d_perms.shape[0], int(iters), int(lo),
+                                         int(hi), int(seed), int(start_base), _dptr(d_best, "int64"),
+                                         _dptr(d_done, "int32"), _dptr(d_freq, "int32"), _stream_ptr(stream)),
+               "qap_tabu_freq_async")
 
     def two_opt_with_table_async(self, d_perms, d_table, d_costs, d_steps=None, max_iters: int = 0, stream=None):
         _check(lib().qap_2opt_with_table_async(self.ptr, _dptr(d_perms, "int32"), _dptr(d_table, "int32"),

@@ -304,3 +304,36 @@ def test_tabu_config3_full_size_sampled():
     sample = [0, 200]
     ep, ec, ed = oracle_tabu_many(I.F, I.D, I.perms[sample], w.iters, lo, hi, I.seed, sample)
     assert (p[sample] == ep).all() and (c[sample] == ec).all() and (d[sample] == ed).all()
+
+
+@pytest.mark.parametrize("n,sym,rows", [(12, False, 0), (40, True, 1), (64, False, 2), (130, False, 4),
+                                        (200, False, -8)])
+def test_tabu_frequency_memory_counts_the_oracle_moves(n, sym, rows):
+    """The frequency memory (Sec. 4.3, lower triangle of Tabuarr) counts, per pair of
+    locations, the exchanges the search made: it must equal the count of the oracle's
+    moves, and keeping it must not change the search."""
+    import torch
+    F, D, rng = rand_inst(5000 + n, n, sym)
+    k, iters, seed = 3, 250, 777
+    perms = W.starts(rng, n, k)
+    lo, hi = W.tabu_tenure_range(n)
+    m = n * (n - 1) // 2
+    note("tabu frequency memory n=%d rows=%d" % (n, rows))
+    with qap.Handle(F, D) as h:
+        if rows:
+            h.set_tile_rows("tabu", rows)
+        dp = torch.from_numpy(perms).cuda()
+        db = torch.zeros(k, dtype=torch.int64, device="cuda")
+        dd = torch.zeros(k, dtype=torch.int32, device="cuda")
+        df = torch.full((k, m), -1, dtype=torch.int32, device="cuda")
+        h.tabu_freq_async(dp, iters, lo, hi, seed, db, df, dd)
+        torch.cuda.synchronize()
+        got_p, got_c, got_d, got_f = dp.cpu().numpy(), db.cpu().numpy(), dd.cpu().numpy(), df.cpu().numpy()
+    for j in range(k):
+        bp, bc, done, tr = oracle.tabu(F, D, perms[j], iters, lo, hi, seed, start=j, trace_cap=iters)
+        want = np.zeros(m, dtype=np.int64)
+        for r, s, _, _ in tr:
+            a, b = min(r, s), max(r, s)
+            want[a * n - a * (a + 1) // 2 + (b - a - 1)] += 1
+        assert (got_f[j] == want).all() and got_f[j].sum() == done, j
+        assert (got_p[j] == bp).all() and got_c[j] == bc and got_d[j] == done, j
