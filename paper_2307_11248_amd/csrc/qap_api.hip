@@ -280,8 +280,10 @@ bool batch_fits(const qap_ctx *h, int ri) {
     if (ri == kStream) return h->stream_ok != 0;
     if (ri < kBatchFirst || ri > kBatchFirst + 2) return false;
     const TileSet &ts = h->tiles[ri];
-    return ts.d_tiles && batch_shape_ok(h->n, kRowsChoices[ri], ts.ntiles, h->sym) &&
-           search_smem_bytes(h->n, kRowsChoices[ri], BATCH_LANES, h->sym) <= h->max_smem;
+    const int rows = kRowsChoices[ri];
+    const int lanes = batch_variant_lanes(batch_variant(h->n, rows, false, ts.ntiles, h->sym));
+    return ts.d_tiles && batch_shape_ok_wide(h->n, rows, ts.ntiles, h->sym) &&
+           search_smem_bytes(h->n, rows, lanes, h->sym) <= h->max_smem;
 }
 
 // Default batched shape: the smallest tile that fits.

@@ -201,8 +201,13 @@ int batch_shape_ok(int n, int rows, int ntiles, int sym);
 // Kernel variants of the batched launch: register tiles of 2, 4, 8 rows and the streamed
 // form on BATCH_LANES lanes, and for searches that need fewer lanes (a lane per tile and
 // per (index, family) task) tiles of 2 rows on 128 or 256 lanes and of 4 rows on 256, so
-// that more small searches share a compute unit.  One launch per variant.
-enum { BV_R2 = 0, BV_R4, BV_R8, BV_STREAM, BV_R2_128, BV_R2_256, BV_R4_256, BV_COUNT };
+// that more small searches share a compute unit; tiles of 4 rows also on 768 lanes (one
+// task per lane, three waves per SIMD) for searches with more than BATCH_LANES tiles.
+// One launch per variant.
+enum { BV_R2 = 0, BV_R4, BV_R8, BV_STREAM, BV_R2_128, BV_R2_256, BV_R4_256, BV_R4_768, BV_COUNT };
+// Whether a batched launch serves tile shape rows for this n (batch_shape_ok, or tiles of
+// 4 rows on the 768-lane variant).
+int batch_shape_ok_wide(int n, int rows, int ntiles, int sym);
 // Variant of a batched search: rows 2, 4, 8 or the streamed form, ntiles tiles.
 int batch_variant(int n, int rows, bool streamed, int ntiles, int sym);
 // Lanes of a workgroup of that variant.

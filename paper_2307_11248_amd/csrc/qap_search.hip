@@ -1041,7 +1041,7 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
 // registers and run one search per compute unit.  (A persistent loop over a work queue
 // inside one block was tried: keeping its state live made the register tiles spill.)
 template <int ROWS, int LANES, int MAXT, bool STREAM>
-__global__ void __launch_bounds__(LANES) __attribute__((amdgpu_waves_per_eu(ROWS <= 4 ? 4 : 2)))
+__global__ void __launch_bounds__(LANES) __attribute__((amdgpu_waves_per_eu(LANES > 512 ? 3 : (ROWS <= 4 ? 4 : 2))))
 batch_group_kernel(BatchArgs b) {
     extern __shared__ __align__(16) unsigned char sm[];
     Item it = b.items[blockIdx.x];
@@ -1054,7 +1054,7 @@ batch_group_kernel(BatchArgs b) {
         it.tile_d = b.tile_work + it.tile_off;
         it.tile_u = it.tile_d + stream_tile_int4(it.ntiles) / 2;
     }
-    search_body<ROWS, true, MAXT, false, STREAM, ROWS <= 4 && (MAXT > 1 || ROWS == 4)>(it, sm);
+    search_body<ROWS, true, MAXT, false, STREAM, ROWS <= 4 && LANES <= 512 && (MAXT > 1 || ROWS == 4)>(it, sm);
 }
 
 // Chunked runs: block i runs one chunk of items[i] (absolute pointers, st != null).
@@ -1164,12 +1164,17 @@ int batch_variant(int n, int rows, bool streamed, int ntiles, int sym) {
     // lanes a one-task workgroup needs: one per tile and one per (index, family) task
     const int need = ntiles > families(sym) * n ? ntiles : families(sym) * n;
     if (rows == 2) return need <= 128 ? BV_R2_128 : (need <= 256 ? BV_R2_256 : BV_R2);
-    if (rows == 4) return need <= 256 ? BV_R4_256 : BV_R4;
+    if (rows == 4) return need <= 256 ? BV_R4_256 : (ntiles <= BATCH_LANES ? BV_R4 : BV_R4_768);
     return BV_R8;
 }
 
 int batch_variant_lanes(int variant) {
+    if (variant == BV_R4_768) return 768;
     return variant == BV_R2_128 ? 128 : (variant == BV_R2_256 || variant == BV_R4_256 ? 256 : BATCH_LANES);
+}
+
+int batch_shape_ok_wide(int n, int rows, int ntiles, int sym) {
+    return batch_shape_ok(n, rows, ntiles, sym) || (rows == 4 && ntiles <= 768 && families(sym) * n <= 768) ? 1 : 0;
 }
 
 int batch_shape_ok(int n, int rows, int ntiles, int sym) {
@@ -1191,6 +1196,9 @@ hipError_t launch_batch_group(int variant, const BatchArgs &b, size_t smem, hipS
             break;
         case BV_R4_256:
             hipLaunchKernelGGL((batch_group_kernel<4, 256, 1, false>), dim3(b.count), dim3(256), smem, st, b);
+            break;
+        case BV_R4_768:
+            hipLaunchKernelGGL((batch_group_kernel<4, 768, 1, false>), dim3(b.count), dim3(768), smem, st, b);
             break;
         case BV_STREAM:
             hipLaunchKernelGGL((batch_group_kernel<STREAM_ROWS, L, T, true>), dim3(b.count), dim3(L), smem, st, b);

@@ -88,12 +88,12 @@ def test_batch_equals_oracle_mixed_n(sizes, k, iters):
 
 def test_batch_every_kernel_variant_equals_oracle():
     """Shapes chosen so that every batched kernel variant runs: tiles of 2 rows on 128,
-    256 and 512 lanes, of 4 rows on 256 and 512, of 8 rows, and the streamed form (a
+    256 and 512 lanes, of 4 rows on 256, 512 and 768, of 8 rows, and the streamed form (a
     search gets the smallest workgroup with a lane per tile and per (index, family) task)."""
-    sizes = [30, 60, 50, 100, 70, 130, 190]
-    rows = [2, 2, 4, 4, 2, 8, -8]
-    lanes = [128, 256, 256, 512, 512, 512, 512]
-    k = [2, 2, 2, 2, 2, 1, 1]
+    sizes = [30, 60, 50, 100, 70, 130, 190, 140]
+    rows = [2, 2, 4, 4, 2, 8, -8, 4]
+    lanes = [128, 256, 256, 512, 512, 512, 512, 768]
+    k = [2, 2, 2, 2, 2, 1, 1, 2]
     iters = 300
     insts, lohi, seeds = mixed_batch(7 + sum(sizes), sizes, k)
     note("batch variants sizes=%s rows=%s" % (sizes, rows))
