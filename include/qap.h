@@ -263,9 +263,12 @@ int qap_server_destroy(qap_server_handle s);
  * library's own choice, made per launch for tabu and 2opt: among the register tiles that
  * fit n, the one that needs the fewest rounds of workgroups over the compute units for
  * the launch's k starts (HIP's occupancy query), ties going to the smallest tile; else
- * the streamed kernel.  A shape set here (or by the autotuner) holds for every launch.  algo: 0 = tabu, 1 = 2opt, 2 = this instance inside a batch
- * (qap_batch_create with rows_per NULL or 0; rows 2, 4, 8 or -8, fixed workgroup of 512
- * lanes).  Returns QAP_E_UNSUPPORTED if the shape does not fit this n (lanes or LDS).
+ * the streamed kernel.  A shape set here (or by the autotuner) holds for every launch.
+ * algo: 0 = tabu, 1 = 2opt, 2 = this instance inside a batch (qap_batch_create with
+ * rows_per NULL or 0; rows 2, 4, 8 or -8; each search gets the smallest batched
+ * workgroup with a lane per tile and per (index, family) task: 128, 256 or 512 lanes,
+ * 768 for tiles of 4 rows beyond 512 tiles).  Returns QAP_E_UNSUPPORTED if the shape
+ * does not fit this n (lanes or LDS).
  */
 int qap_set_tile_rows(qap_handle h, int32_t algo, int32_t rows);
 
