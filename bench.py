@@ -39,12 +39,12 @@ BYTES_PER_EVAL = 8   # an int32 delta read and written per entry per step if kep
 # valid only for the kernel sources they were taken with.
 KERNEL_SOURCES = ["paper_2307_11248_amd/csrc/qap_search.hip", "paper_2307_11248_amd/csrc/qap_internal.h"]
 TRAFFIC = {
-    "c2_n64_dense_tabu": {"bytes": 2 * 721 * 1024 + 40 * 1024, "sources": "28982645e3fc4856"},
-    # sum over the six kernels of one launch (tile shapes 2, 4, 8 rows on 512 lanes; 2 rows
-    # on 256 and 128; 4 rows on 256)
-    "c4_batched_uneven_tabu": {"bytes": int((2 * (16603.0 + 48981.6 + 43037.4 + 9542.7 + 1803.1 + 1905.8)
-                                             + (265.4 + 600.3 + 408.6 + 247.7 + 84.5 + 45.2)) * 1024),
-                               "sources": "28982645e3fc4856"},
+    "c2_n64_dense_tabu": {"bytes": 2 * 728 * 1024 + 40 * 1024, "sources": "f54794d88ea3d177"},
+    # sum over the six kernels of one launch (tiles of 2 rows on 128, 256 and 512 lanes, of
+    # 4 rows on 256, 512 and 768)
+    "c4_batched_uneven_tabu": {"bytes": int((2 * (1611.2 + 9547.7 + 16607.5 + 2086.6 + 48970.8 + 43354.9)
+                                             + (77.0 + 247.7 + 265.4 + 52.7 + 600.8 + 408.0)) * 1024),
+                               "sources": "f54794d88ea3d177"},
 }
 
 
