@@ -340,3 +340,73 @@ ORC_EXPORT int orc_tabu(int n, const int32_t *F, const int32_t *D, const int32_t
     free(tab); free(until); free(cand); free(p);
     return 0;
 }
+
+/*
+ * Tabu search that keeps the frequency memory of Sec. 4.3 -- freq[i], the number of
+ * moves made with packed index i (the paper's lower triangle of Tabuarr) -- and may use
+ * it to diversify.  The paper records the counts but diversifies only through the
+ * dynamic tenure, leaving a frequency-based rule to future work (Sec. 7); the rule here
+ * is this build's reading of that intent:
+ *   last = the iteration at which the best cost last improved (0 before any).
+ *   div > 0 and it - last > div: a diversification move.  Among the moves that are not
+ *     tabu (Tabuarr <= it; no aspiration) the one exchanged least often so far is taken,
+ *     ties to the lowest packed index, whatever its delta; afterwards last = it.  If
+ *     every move is tabu the iteration follows the ordinary rule.
+ *   Otherwise (and always when div = 0) the ordinary rule of orc_tabu.
+ * Everything else (tenure, best update, early stop, results, trace) is as in orc_tabu,
+ * mode 1.  freq (int32[n(n-1)/2]) receives the counts.  Returns 0, or -1 if memory ran
+ * out.
+ */
+ORC_EXPORT int orc_tabu_freq(int n, const int32_t *F, const int32_t *D, const int32_t *p0,
+                             int32_t iters, int32_t lo, int32_t hi, uint64_t seed, uint64_t start,
+                             int32_t div, int32_t *best_perm, int64_t *best_cost, int32_t *iters_done,
+                             int32_t *freq, int64_t *trace, int32_t trace_cap) {
+    int64_t m = (int64_t)n * (n - 1) / 2;
+    int64_t *tab = malloc(sizeof(int64_t) * (m > 0 ? m : 1));
+    int64_t *until = calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
+    int32_t *p = malloc(sizeof(int32_t) * n);
+    if (!tab || !until || !p) { free(tab); free(until); free(p); return -1; }
+    for (int64_t i = 0; i < m; i++) freq[i] = 0;
+    memcpy(p, p0, sizeof(int32_t) * n);
+    memcpy(best_perm, p0, sizeof(int32_t) * n);
+    int64_t cur = orc_cost(n, F, D, p), best = cur;
+    int32_t done = 0, last = 0;
+    if (m > 0) orc_delta_table(n, F, D, p, tab);
+    for (int32_t it = 1; it <= iters && m > 0; it++) {
+        int64_t pick = -1;
+        int diversify = div > 0 && it - last > div;
+        if (diversify) {
+            for (int64_t i = 0; i < m; i++) {
+                if (until[i] > it) continue;                   /* tabu */
+                if (pick < 0 || freq[i] < freq[pick]) pick = i;
+            }
+            if (pick < 0) diversify = 0;                       /* all tabu: ordinary rule */
+        }
+        if (!diversify) {
+            for (int64_t i = 0; i < m; i++) {
+                if (!(until[i] <= it || cur + tab[i] < best)) continue;
+                if (pick < 0 || tab[i] < tab[pick]) pick = i;
+            }
+        }
+        if (pick < 0) break;
+        int r, s;
+        pair_of(n, pick, &r, &s);
+        int64_t dz = tab[pick];
+        orc_delta_update(n, F, D, p, r, s, tab);
+        int32_t tmp = p[r]; p[r] = p[s]; p[s] = tmp;
+        cur += dz;
+        if (cur < best) { best = cur; memcpy(best_perm, p, sizeof(int32_t) * n); last = it; }
+        if (diversify) last = it;
+        until[pick] = (int64_t)it + orc_tenure(seed, (uint64_t)it, start, lo, hi);
+        freq[pick] += 1;
+        if (trace && done < trace_cap) {
+            trace[4 * done] = r; trace[4 * done + 1] = s;
+            trace[4 * done + 2] = dz; trace[4 * done + 3] = cur;
+        }
+        done = it;
+    }
+    *best_cost = best;
+    if (iters_done) *iters_done = done;
+    free(tab); free(until); free(p);
+    return 0;
+}

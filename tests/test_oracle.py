@@ -285,3 +285,82 @@ def test_contraction_form_equals_eq2_and_cost_differences(n, sym, diag):
                     q[r], q[s_] = q[s_], q[r]
                     assert t[k] == oracle.cost(F, D, q) - z
                     k += 1
+
+
+def py_tabu_freq(F, D, p0, iters, lo, hi, seed, start, div):
+    """Independent numpy re-simulation of the tabu rules with the frequency memory and the
+    frequency-based diversification move (the least exchanged non-tabu pair, lowest index
+    on ties, when the best cost has not improved for more than div iterations; div = 0
+    never), on tiny inputs: every neighbourhood by full recomputation of Eq. (1), tenure
+    from numpy's Philox."""
+    n = len(p0)
+    m = n * (n - 1) // 2
+    p = np.array(p0).copy()
+    cur = np_cost(F, D, p)
+    best, bestp, last = cur, p.copy(), 0
+    until = [0] * m
+    freq = [0] * m
+    moves = []
+    pairs = [(r, s) for r in range(n) for s in range(r + 1, n)]
+    for it in range(1, iters + 1):
+        deltas = np_all_swap_deltas(F, D, p)
+        pick = None
+        diversify = div > 0 and it - last > div
+        if diversify:
+            free = [k for k in range(m) if until[k] <= it]
+            if free:
+                pick = min(free, key=lambda k: (freq[k], k))
+            else:
+                diversify = False
+        if not diversify:
+            allowed = [k for k in range(m) if until[k] <= it or cur + int(deltas[k]) < best]
+            if allowed:
+                pick = min(allowed, key=lambda k: (int(deltas[k]), k))
+        if pick is None:
+            break
+        r, s = pairs[pick]
+        d = int(deltas[pick])
+        p[r], p[s] = p[s], p[r]
+        cur += d
+        if cur < best:
+            best, bestp, last = cur, p.copy(), it
+        if diversify:
+            last = it
+        x = int(np.random.Philox(key=seed, counter=it + (start << 64) - 1).random_raw(1)[0])
+        until[pick] = it + lo + (((x >> 32) * (hi - lo + 1)) >> 32)
+        freq[pick] += 1
+        moves.append((r, s, d, cur))
+    return bestp, best, len(moves), np.array(freq), moves
+
+
+@pytest.mark.parametrize("seed,n,lo,hi,iters,div", [(0, 5, 1, 3, 60, 3), (1, 6, 2, 4, 80, 5), (2, 7, 1, 2, 70, 2),
+                                                     (3, 8, 5, 9, 60, 4), (4, 4, 6, 6, 20, 1), (5, 6, 1, 3, 50, 0)])
+def test_tabu_frequency_memory_and_diversification_match_resimulation(seed, n, lo, hi, iters, div):
+    """The oracle's frequency memory and diversification rule, pinned to an independent
+    re-simulation; with div = 0 it is the plain tabu search, counts aside."""
+    rng = np.random.default_rng(300 + seed)
+    F, D = W.random_instance(rng, n, 0, 20, symmetric=bool(seed % 2))
+    p0 = rng.permutation(n).astype(np.int32)
+    bp, bc, done, freq, tr = oracle.tabu_freq(F, D, p0, iters, lo, hi, seed + 11, start=seed, div=div,
+                                              trace_cap=iters)
+    ep, ec, ed, ef, em = py_tabu_freq(F, D, p0, iters, lo, hi, seed + 11, seed, div)
+    assert bc == ec and done == ed and (bp == ep).all() and (freq == ef).all()
+    assert [tuple(int(x) for x in row) for row in tr] == em
+    assert freq.sum() == done
+    if div == 0:
+        pp, pc, pd, ptr = oracle.tabu(F, D, p0, iters, lo, hi, seed + 11, start=seed, trace_cap=iters)
+        assert pc == bc and pd == done and (pp == bp).all() and (ptr == tr).all()
+
+
+def test_diversification_changes_the_trajectory():
+    """With a short patience the rule must actually fire: on this instance the trajectory
+    with div = 2 differs from the plain one, and its diversification moves are the least
+    used non-tabu pairs (checked by the re-simulation above on the same input)."""
+    rng = np.random.default_rng(77)
+    F, D = W.random_instance(rng, 7, 0, 30)
+    p0 = rng.permutation(7).astype(np.int32)
+    a = oracle.tabu_freq(F, D, p0, 120, 1, 3, 5, div=0, trace_cap=120)
+    b = oracle.tabu_freq(F, D, p0, 120, 1, 3, 5, div=2, trace_cap=120)
+    assert not np.array_equal(a[4], b[4])
+    ep, ec, ed, ef, em = py_tabu_freq(F, D, p0, 120, 1, 3, 5, 0, 2)
+    assert (b[3] == ef).all() and b[1] == ec
