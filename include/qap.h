@@ -145,16 +145,23 @@ int qap_tabu_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int
 
 /*
  * qap_tabu_async that also keeps the frequency memory of Sec. 4.3: the number of times
- * each pair of locations was exchanged (the lower triangle of Tabuarr).  As in the paper
- * the counts are recorded and returned but decide nothing: the searches and their
- * results are those of qap_tabu_async.
+ * each pair of locations was exchanged (the lower triangle of Tabuarr), and may use it
+ * to diversify, which the paper leaves to future work (Sec. 7).
+ *   div     0: the counts decide nothing, as in the paper (the searches and results are
+ *           those of qap_tabu_async).  > 0: whenever the best cost has not improved for
+ *           more than div iterations (counted from the last new best or the last such
+ *           move), the next move is the non-tabu pair exchanged least often so far, ties
+ *           to the lowest packed index, whatever its delta and without aspiration; if
+ *           every move is tabu, the ordinary move is made.
  *   d_freq  device int32[k][n(n-1)/2], overwritten: row j holds start j's counts at packed
  *           pair index r*n - r*(r+1)/2 + (s - r - 1) for r < s (the order of
  *           qap_delta_table); the counts sum to the moves made.
- * QAP_E_INVALID if d_freq is NULL with k > 0; otherwise as qap_tabu_async.
+ * QAP_E_INVALID if d_freq is NULL with k > 0 or div < 0; QAP_E_UNSUPPORTED if div > 0
+ * and the launch would use the streamed kernel (n above the register tiles' reach);
+ * otherwise as qap_tabu_async.
  */
 int qap_tabu_freq_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo,
-                        int32_t hi, uint64_t seed, int64_t start_base, int64_t *d_best,
+                        int32_t hi, uint64_t seed, int64_t start_base, int32_t div, int64_t *d_best,
                         int32_t *d_done, int32_t *d_freq, void *stream);
 
 /*

@@ -111,6 +111,7 @@ struct SearchArgs {
     int4 *tile_work;         // streamed kernels: per search, tile_stride int4 of tile state
     long long tile_stride;
     int32_t *freq;           // tabu: [k][m] exchange counts per search, or null
+    int div;                 // with freq: diversification patience (0: none)
 };
 
 // With QAP_VERBOSE set in the environment, report a failed HIP call on stderr.
@@ -172,6 +173,9 @@ struct Item {
     // tabu: the frequency memory, m counts of how often each pair of locations was
     // exchanged (packed pair index), zeroed when the search starts; null: not kept
     int32_t *freq;
+    // with freq (register-tile kernels): after more than div iterations without a new
+    // best, the next move is the least exchanged non-tabu pair; 0: never
+    int div;
 };
 
 // The batched launch: one block per item of `items`; per-start buffers are shared by

@@ -277,6 +277,8 @@ template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool SYM, boo
 __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsigned char *sm) {
     __shared__ int s_bad;
     __shared__ int s_chunk_end;   // chunked runs: set by thread 0 once the clock budget is spent
+    __shared__ long long s_red2[FREQ ? 16 : 1];   // diversification: wave minima of (count, key)
+    __shared__ int s_dd;                          // diversification: delta of the chosen move
     const int n = a.n, rs = row_stride(n), L = blockDim.x, t = threadIdx.x;
     const int nb16 = (n + 15) & ~15;   // bytes of a row the dot products read (zero past n)
     const int nb32 = (n + 31) & ~31;   // the same, for the 32-byte steps of the row recomputation
@@ -548,6 +550,9 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         }
     }
     if (t >= W && t < 16) red[t] = NO_MOVE;   // unused wave-minimum slots
+    if constexpr (FREQ)
+        if (t >= W && t < 16) s_red2[t] = NO_MOVE;
+    int last_imp = 0;   // diversification: the iteration of the last new best
     bool stopped = false;
     __syncthreads();
 
@@ -573,16 +578,73 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         const long long rv = red[lane & 15];
         const long long mk = wave_min_pair<16>((int)(rv >> 32), (int)(rv & 0xffffffffLL));
         // the winner is the same in every lane: keep it in scalar registers
-        const int dstar = __builtin_amdgcn_readfirstlane((int)(mk >> 32));
+        int dstar = __builtin_amdgcn_readfirstlane((int)(mk >> 32));
+        int kstar = __builtin_amdgcn_readfirstlane((int)(mk & 0xffffffffLL));
+        bool diversified = false;
+        if constexpr (FREQ && !STREAM) {
+            if (a.div > 0 && it - last_imp > a.div) {
+                // diversification move: the non-tabu pair exchanged least often so far,
+                // lowest key on ties (a pair's own slot has a lower key than its mirror
+                // slot, so the winner is never a mirror).  The counts are read at device
+                // scope: the adds of earlier moves were made in L2.
+                long long dsel = NO_MOVE;
+                if (active) {
+                    // opaque copies of the tile origin: the count addresses are made here,
+                    // not kept through the whole loop as invariants
+                    int pu = u0, pv = v0;
+                    asm volatile("" : "+v"(pu), "+v"(pv));
+#pragma unroll
+                    for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int u = pu + j, v = pv + e;
+                            if (u < n && v < n && u != v && ut[j][e] <= it) {
+                                const int cnt = __hip_atomic_load(a.freq + pidx(n, min(u, v), max(u, v)),
+                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                const long long c = ((long long)cnt << 32) | (unsigned)((u << 9) | v);
+                                dsel = c < dsel ? c : dsel;
+                            }
+                            // one load in flight at a time: this rare path must not add to the
+                            // registers the loop holds
+                            asm volatile("" ::: "memory");
+                        }
+                }
+                const long long dw = wave_min_pair<64>((int)(dsel >> 32), (int)(dsel & 0xffffffffLL));
+                if (lane == 0) s_red2[wid] = dw;
+                __syncthreads();  // B1 of the diversification move
+                const long long rv2 = s_red2[lane & 15];
+                const long long mk2 = wave_min_pair<16>((int)(rv2 >> 32), (int)(rv2 & 0xffffffffLL));
+                const int fmin = __builtin_amdgcn_readfirstlane((int)(mk2 >> 32));
+                if (fmin != INT32_MAX) {   // else every move is tabu: the ordinary move
+                    const int kd = __builtin_amdgcn_readfirstlane((int)(mk2 & 0xffffffffLL));
+                    const int ud = kd >> 9, vd = kd & 511;
+                    // the lane holding the pair's own slot publishes its delta
+                    if (active && ud >= u0 && ud < u0 + ROWS && vd >= v0 && vd < v0 + TILE_COLS) {
+                        int x = 0;
+#pragma unroll
+                        for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (u0 + j == ud && v0 + e == vd) x = dl[j][e];
+                        s_dd = x;
+                    }
+                    __syncthreads();  // the delta is visible
+                    dstar = __builtin_amdgcn_readfirstlane(s_dd);
+                    kstar = kd;
+                    diversified = true;
+                }
+            }
+        }
         if (TABU ? (dstar == INT32_MAX) : (dstar >= 0)) {
             stopped = true;
             break;
         }
-        const int kstar = __builtin_amdgcn_readfirstlane((int)(mk & 0xffffffffLL));
         const int r = min(kstar >> 9, kstar & 511), s = max(kstar >> 9, kstar & 511);
         const bool improved = TABU && (cur + dstar < best);
         cur += dstar;
         if (improved) best = cur;
+        if constexpr (FREQ)
+            if (improved || diversified) last_imp = it;
         // frequency memory: one more exchange of locations r and s (a vector atomic that
         // nothing waits for; the zeroing above finished before the first barrier)
         if (FREQ && a.freq && t == 0)
@@ -1018,6 +1080,7 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
     it.cost_out = a.cost_out + job;
     it.steps_out = a.steps_out ? a.steps_out + job : nullptr;
     it.freq = FREQ ? a.freq + (size_t)job * a.m : nullptr;
+    it.div = FREQ ? a.div : 0;
     it.st = nullptr;
     it.n = a.n;
     it.m = a.m;
@@ -1086,6 +1149,7 @@ __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     it.cost_out = a.cost_out + job;
     it.steps_out = a.steps_out ? a.steps_out + job : nullptr;
     it.freq = FREQ ? a.freq + (size_t)job * a.m : nullptr;
+    it.div = FREQ ? a.div : 0;
     it.n = a.n;
     it.m = a.m;
     it.sym = a.sym;

@@ -337,3 +337,52 @@ def test_tabu_frequency_memory_counts_the_oracle_moves(n, sym, rows):
             want[a * n - a * (a + 1) // 2 + (b - a - 1)] += 1
         assert (got_f[j] == want).all() and got_f[j].sum() == done, j
         assert (got_p[j] == bp).all() and got_c[j] == bc and got_d[j] == done, j
+
+
+@pytest.mark.parametrize("n,sym,rows,div", [(12, False, 0, 3), (40, True, 1, 6), (64, False, 2, 10),
+                                            (64, False, 1, 4), (101, True, 4, 8), (130, False, 8, 12),
+                                            (150, False, 16, 9)])
+def test_tabu_frequency_diversification_equals_oracle(n, sym, rows, div):
+    """With div > 0 the frequency memory drives a diversification move (the least
+    exchanged non-tabu pair after more than div iterations without a new best): best
+    permutations, costs, moves made and counts equal the oracle's, on every register tile
+    shape; the rule changes the search for at least one start."""
+    import torch
+    F, D, rng = rand_inst(6000 + n + div, n, sym)
+    k, iters, seed = 4, 300, 4242
+    perms = W.starts(rng, n, k)
+    lo, hi = W.tabu_tenure_range(n)
+    m = n * (n - 1) // 2
+    note("tabu diversification n=%d rows=%d div=%d" % (n, rows, div))
+    with qap.Handle(F, D) as h:
+        if rows:
+            h.set_tile_rows("tabu", rows)
+        dp = torch.from_numpy(perms).cuda()
+        db = torch.zeros(k, dtype=torch.int64, device="cuda")
+        dd = torch.zeros(k, dtype=torch.int32, device="cuda")
+        df = torch.full((k, m), -1, dtype=torch.int32, device="cuda")
+        h.tabu_freq_async(dp, iters, lo, hi, seed, db, df, dd, div=div)
+        torch.cuda.synchronize()
+        got_p, got_c, got_d, got_f = dp.cpu().numpy(), db.cpu().numpy(), dd.cpu().numpy(), df.cpu().numpy()
+    changed = False
+    for j in range(k):
+        bp, bc, done, freq, _ = oracle.tabu_freq(F, D, perms[j], iters, lo, hi, seed, start=j, div=div)
+        assert (got_p[j] == bp).all() and got_c[j] == bc and got_d[j] == done, j
+        assert (got_f[j] == freq).all(), j
+        plain = oracle.tabu_freq(F, D, perms[j], iters, lo, hi, seed, start=j, div=0)
+        changed |= not (plain[3] == freq).all()
+    assert changed
+
+
+def test_tabu_diversification_rejected_on_the_streamed_kernel():
+    import torch
+    F, D, rng = rand_inst(6200, 200, False)
+    perms = W.starts(rng, 200, 1)
+    note("tabu diversification streamed n=200")
+    with qap.Handle(F, D) as h:
+        dp = torch.from_numpy(perms).cuda()
+        db = torch.zeros(1, dtype=torch.int64, device="cuda")
+        df = torch.zeros((1, 200 * 199 // 2), dtype=torch.int32, device="cuda")
+        with pytest.raises(qap.QapError) as ei:
+            h.tabu_freq_async(dp, 10, 180, 220, 1, db, df, div=5)
+        assert ei.value.code == qap.QAP_E_UNSUPPORTED
