@@ -79,7 +79,7 @@ def _load():
             lib.orc_tabu_freq.restype = ctypes.c_int
             lib.orc_tabu_freq.argtypes = [ctypes.c_int, _i32p, _i32p, _i32p, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32,
-                                          _i32p, _i64p, _i32p, _i32p, _i64p, ctypes.c_int32]
+                                          ctypes.c_int32, _i32p, _i64p, _i32p, _i32p, _i64p, ctypes.c_int32]
             _lib = lib
     return _lib
 
@@ -192,10 +192,11 @@ def tabu(F, D, perm, iters, lo, hi, seed, start=0, mode=1, trace_cap=0):
     return bp, int(bc[0]), d, tr[:4 * min(d, trace_cap)].reshape(-1, 4)
 
 
-def tabu_freq(F, D, perm, iters, lo, hi, seed, start=0, div=0, trace_cap=0):
+def tabu_freq(F, D, perm, iters, lo, hi, seed, start=0, div=0, trace_cap=0, attr=0):
     """Tabu search keeping the frequency memory, with the frequency-based diversification
     move every time the best cost has not improved for more than div iterations (div = 0:
-    none).  Returns (best_perm, best_cost, iters_done, freq, trace)."""
+    none); attr 0 makes pairs of locations tabu, 1 the units just moved.  Returns
+    (best_perm, best_cost, iters_done, freq, trace)."""
     n = len(perm)
     F, D, p0 = _mat(F, n), _mat(D, n), _vec(perm, n)
     m = n * (n - 1) // 2
@@ -205,7 +206,7 @@ def tabu_freq(F, D, perm, iters, lo, hi, seed, start=0, div=0, trace_cap=0):
     freq = np.zeros(max(m, 1), dtype=np.int32)
     tr = np.zeros(max(trace_cap, 1) * 4, dtype=np.int64)
     rc = _load().orc_tabu_freq(n, _p32(F), _p32(D), _p32(p0), int(iters), int(lo), int(hi), int(seed),
-                               int(start), int(div), _p32(bp), _p64(bc), _p32(done), _p32(freq),
+                               int(start), int(div), int(attr), _p32(bp), _p64(bc), _p32(done), _p32(freq),
                                _p64(tr) if trace_cap else None, int(trace_cap))
     if rc != 0:
         raise MemoryError("oracle tabu_freq: out of memory")

@@ -343,8 +343,8 @@ ORC_EXPORT int orc_tabu(int n, const int32_t *F, const int32_t *D, const int32_t
 
 /*
  * Tabu search that keeps the frequency memory of Sec. 4.3 -- freq[i], the number of
- * moves made with packed index i (the paper's lower triangle of Tabuarr) -- and may use
- * it to diversify.  The paper records the counts but diversifies only through the
+ * moves made with packed index i (the paper's lower triangle of Tabuarr) -- may use it
+ * to diversify, and may use a unit-based tabu attribute instead of the pair one.  The paper records the counts but diversifies only through the
  * dynamic tenure, leaving a frequency-based rule to future work (Sec. 7); the rule here
  * is this build's reading of that intent:
  *   last = the iteration at which the best cost last improved (0 before any).
@@ -353,19 +353,25 @@ ORC_EXPORT int orc_tabu(int n, const int32_t *F, const int32_t *D, const int32_t
  *     ties to the lowest packed index, whatever its delta; afterwards last = it.  If
  *     every move is tabu the iteration follows the ordinary rule.
  *   Otherwise (and always when div = 0) the ordinary rule of orc_tabu.
- * Everything else (tenure, best update, early stop, results, trace) is as in orc_tabu,
- * mode 1.  freq (int32[n(n-1)/2]) receives the counts.  Returns 0, or -1 if memory ran
- * out.
+ * attr selects what is tabu:
+ *   0: the pair of locations, as in orc_tabu (Tabuarr(r, s) = it + t after the move).
+ *   1: the units, in the manner of Zhu et al.'s unit marking (cited in Sec. 3): after the
+ *      move of iteration it the two units it moved are marked until it + t, and a move
+ *      is tabu while either of the units it would move is marked (mark > it).
+ * Everything else (tenure, aspiration, best update, early stop, results, trace) is as in
+ * orc_tabu, mode 1.  freq (int32[n(n-1)/2]) receives the counts.  Returns 0, or -1 if
+ * memory ran out.
  */
 ORC_EXPORT int orc_tabu_freq(int n, const int32_t *F, const int32_t *D, const int32_t *p0,
                              int32_t iters, int32_t lo, int32_t hi, uint64_t seed, uint64_t start,
-                             int32_t div, int32_t *best_perm, int64_t *best_cost, int32_t *iters_done,
-                             int32_t *freq, int64_t *trace, int32_t trace_cap) {
+                             int32_t div, int32_t attr, int32_t *best_perm, int64_t *best_cost,
+                             int32_t *iters_done, int32_t *freq, int64_t *trace, int32_t trace_cap) {
     int64_t m = (int64_t)n * (n - 1) / 2;
     int64_t *tab = malloc(sizeof(int64_t) * (m > 0 ? m : 1));
     int64_t *until = calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
+    int64_t *mark = calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));   /* per unit */
     int32_t *p = malloc(sizeof(int32_t) * n);
-    if (!tab || !until || !p) { free(tab); free(until); free(p); return -1; }
+    if (!tab || !until || !mark || !p) { free(tab); free(until); free(mark); free(p); return -1; }
     for (int64_t i = 0; i < m; i++) freq[i] = 0;
     memcpy(p, p0, sizeof(int32_t) * n);
     memcpy(best_perm, p0, sizeof(int32_t) * n);
@@ -374,6 +380,15 @@ ORC_EXPORT int orc_tabu_freq(int n, const int32_t *F, const int32_t *D, const in
     if (m > 0) orc_delta_table(n, F, D, p, tab);
     for (int32_t it = 1; it <= iters && m > 0; it++) {
         int64_t pick = -1;
+        /* the tabu attribute of each move at this iteration */
+        if (attr == 1) {
+            for (int64_t i = 0; i < m; i++) {
+                int a, b;
+                pair_of(n, i, &a, &b);
+                int64_t ma = mark[p[a]], mb = mark[p[b]];
+                until[i] = ma > mb ? ma : mb;
+            }
+        }
         int diversify = div > 0 && it - last > div;
         if (diversify) {
             for (int64_t i = 0; i < m; i++) {
@@ -397,7 +412,9 @@ ORC_EXPORT int orc_tabu_freq(int n, const int32_t *F, const int32_t *D, const in
         cur += dz;
         if (cur < best) { best = cur; memcpy(best_perm, p, sizeof(int32_t) * n); last = it; }
         if (diversify) last = it;
-        until[pick] = (int64_t)it + orc_tenure(seed, (uint64_t)it, start, lo, hi);
+        int64_t tt = (int64_t)it + orc_tenure(seed, (uint64_t)it, start, lo, hi);
+        if (attr == 1) { mark[p[r]] = tt; mark[p[s]] = tt; }   /* the units just moved */
+        else until[pick] = tt;
         freq[pick] += 1;
         if (trace && done < trace_cap) {
             trace[4 * done] = r; trace[4 * done + 1] = s;
@@ -407,6 +424,6 @@ ORC_EXPORT int orc_tabu_freq(int n, const int32_t *F, const int32_t *D, const in
     }
     *best_cost = best;
     if (iters_done) *iters_done = done;
-    free(tab); free(until); free(p);
+    free(tab); free(until); free(mark); free(p);
     return 0;
 }

@@ -287,23 +287,27 @@ def test_contraction_form_equals_eq2_and_cost_differences(n, sym, diag):
                     k += 1
 
 
-def py_tabu_freq(F, D, p0, iters, lo, hi, seed, start, div):
+def py_tabu_freq(F, D, p0, iters, lo, hi, seed, start, div, attr=0):
     """Independent numpy re-simulation of the tabu rules with the frequency memory and the
     frequency-based diversification move (the least exchanged non-tabu pair, lowest index
     on ties, when the best cost has not improved for more than div iterations; div = 0
     never), on tiny inputs: every neighbourhood by full recomputation of Eq. (1), tenure
-    from numpy's Philox."""
+    from numpy's Philox.  attr 1: a move is tabu while either unit it would move was
+    moved within its tenure (unit marking) instead of the pair of locations."""
     n = len(p0)
     m = n * (n - 1) // 2
     p = np.array(p0).copy()
     cur = np_cost(F, D, p)
     best, bestp, last = cur, p.copy(), 0
     until = [0] * m
+    marked = {}          # unit -> iteration until which it is marked
     freq = [0] * m
     moves = []
     pairs = [(r, s) for r in range(n) for s in range(r + 1, n)]
     for it in range(1, iters + 1):
         deltas = np_all_swap_deltas(F, D, p)
+        if attr == 1:
+            until = [max(marked.get(int(p[r]), 0), marked.get(int(p[s]), 0)) for r, s in pairs]
         pick = None
         diversify = div > 0 and it - last > div
         if diversify:
@@ -327,7 +331,12 @@ def py_tabu_freq(F, D, p0, iters, lo, hi, seed, start, div):
         if diversify:
             last = it
         x = int(np.random.Philox(key=seed, counter=it + (start << 64) - 1).random_raw(1)[0])
-        until[pick] = it + lo + (((x >> 32) * (hi - lo + 1)) >> 32)
+        t_until = it + lo + (((x >> 32) * (hi - lo + 1)) >> 32)
+        if attr == 1:
+            marked[int(p[r])] = t_until
+            marked[int(p[s])] = t_until
+        else:
+            until[pick] = t_until
         freq[pick] += 1
         moves.append((r, s, d, cur))
     return bestp, best, len(moves), np.array(freq), moves
@@ -364,3 +373,21 @@ def test_diversification_changes_the_trajectory():
     assert not np.array_equal(a[4], b[4])
     ep, ec, ed, ef, em = py_tabu_freq(F, D, p0, 120, 1, 3, 5, 0, 2)
     assert (b[3] == ef).all() and b[1] == ec
+
+
+@pytest.mark.parametrize("seed,n,lo,hi,iters,div", [(0, 5, 1, 2, 60, 0), (1, 6, 1, 3, 80, 0), (2, 7, 2, 3, 70, 4),
+                                                     (3, 8, 1, 2, 60, 3), (4, 6, 3, 4, 40, 0)])
+def test_tabu_unit_marking_matches_resimulation(seed, n, lo, hi, iters, div):
+    """The unit-marking tabu attribute (either unit moved within its tenure makes a move
+    tabu), alone and with diversification, pinned to the independent re-simulation; it
+    differs from the pair attribute on these inputs."""
+    rng = np.random.default_rng(500 + seed)
+    F, D = W.random_instance(rng, n, 0, 20, symmetric=bool(seed % 2))
+    p0 = rng.permutation(n).astype(np.int32)
+    bp, bc, done, freq, tr = oracle.tabu_freq(F, D, p0, iters, lo, hi, seed + 3, start=seed, div=div,
+                                              trace_cap=iters, attr=1)
+    ep, ec, ed, ef, em = py_tabu_freq(F, D, p0, iters, lo, hi, seed + 3, seed, div, attr=1)
+    assert bc == ec and done == ed and (bp == ep).all() and (freq == ef).all()
+    assert [tuple(int(x) for x in row) for row in tr] == em
+    pair = oracle.tabu_freq(F, D, p0, iters, lo, hi, seed + 3, start=seed, div=div, trace_cap=iters)
+    assert not np.array_equal(pair[4], tr)
