@@ -153,16 +153,20 @@ int qap_tabu_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int
  *           move), the next move is the non-tabu pair exchanged least often so far, ties
  *           to the lowest packed index, whatever its delta and without aspiration; if
  *           every move is tabu, the ordinary move is made.
+ *   attr    what is tabu.  0: the pair of locations exchanged (Tabuarr, Sec. 4.3), as
+ *           qap_tabu_async.  1: the units, after Zhu et al.'s marking of moved units
+ *           (Sec. 3.1): the two units moved at iteration it are marked until it + t, and
+ *           a move is tabu while either unit it would move is marked.
  *   d_freq  device int32[k][n(n-1)/2], overwritten: row j holds start j's counts at packed
  *           pair index r*n - r*(r+1)/2 + (s - r - 1) for r < s (the order of
  *           qap_delta_table); the counts sum to the moves made.
- * QAP_E_INVALID if d_freq is NULL with k > 0 or div < 0; QAP_E_UNSUPPORTED if div > 0
- * and the launch would use the streamed kernel (n above the register tiles' reach);
- * otherwise as qap_tabu_async.
+ * QAP_E_INVALID if d_freq is NULL with k > 0, div < 0 or attr not 0 or 1;
+ * QAP_E_UNSUPPORTED if div > 0 and the launch would use the streamed kernel (n above the
+ * register tiles' reach); otherwise as qap_tabu_async.
  */
 int qap_tabu_freq_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo,
-                        int32_t hi, uint64_t seed, int64_t start_base, int32_t div, int64_t *d_best,
-                        int32_t *d_done, int32_t *d_freq, void *stream);
+                        int32_t hi, uint64_t seed, int64_t start_base, int32_t div, int32_t attr,
+                        int64_t *d_best, int32_t *d_done, int32_t *d_freq, void *stream);
 
 /*
  * The plain delivery of qap_tabu_async: the same arithmetic and results, but one kernel

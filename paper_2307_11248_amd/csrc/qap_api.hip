@@ -209,7 +209,7 @@ int make_tables(qap_ctx *h, const int32_t *d_perms, int k, int32_t **d_table, hi
 
 hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t *d_table, int k, int iters,
                            int lo, int hi, uint64_t seed, int64_t start_base, int64_t *d_cost, int32_t *d_steps,
-                           hipStream_t st, bool plain, int32_t *d_freq = nullptr, int div = 0) {
+                           hipStream_t st, bool plain, int32_t *d_freq = nullptr, int div = 0, int attr = 0) {
     // one shape for the whole launch: its kernel and its tile list
     const int ri = launch_shape(h, algo, k);
     if (ri < 0) return hipErrorInvalidValue;
@@ -226,6 +226,7 @@ hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t
     a.start_base = start_base;
     a.freq = d_freq;
     a.div = div;
+    a.attr = attr;
     hipError_t e = hipSuccess;
     if (ri == kStream) {
         // tile state in stream-ordered scratch, one slice per search of a launch
@@ -262,14 +263,14 @@ hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t
 
 int run_search(qap_ctx *h, int algo, int32_t *d_perms, int k, int iters, int lo, int hi, uint64_t seed,
                int64_t start_base, int64_t *d_cost, int32_t *d_steps, hipStream_t st, bool plain,
-               int32_t *d_freq = nullptr, int div = 0) {
+               int32_t *d_freq = nullptr, int div = 0, int attr = 0) {
     if (h->rows_choice[algo] < 0) return QAP_E_UNSUPPORTED;
     if (k == 0) return QAP_OK;
     int32_t *d_table = nullptr;
     int rc = make_tables(h, d_perms, k, &d_table, st);
     if (rc != QAP_OK) return rc;
     hipError_t e = launch_searches(h, algo, d_perms, d_table, k, iters, lo, hi, seed, start_base, d_cost,
-                                   d_steps, st, plain, d_freq, div);
+                                   d_steps, st, plain, d_freq, div, attr);
     hipError_t e2 = hipFreeAsync(d_table, st);
     if (e == hipSuccess) e = e2;
     return dev_err(e);
@@ -563,12 +564,14 @@ int qap_tabu_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int
 }
 
 int qap_tabu_freq_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo, int32_t hi,
-                        uint64_t seed, int64_t start_base, int32_t div, int64_t *d_best, int32_t *d_done,
-                        int32_t *d_freq, void *stream) {
-    if (!tabu_args_ok(h, d_perms, k, iters, lo, hi, d_best) || (k > 0 && !d_freq) || div < 0) return QAP_E_INVALID;
+                        uint64_t seed, int64_t start_base, int32_t div, int32_t attr, int64_t *d_best,
+                        int32_t *d_done, int32_t *d_freq, void *stream) {
+    if (!tabu_args_ok(h, d_perms, k, iters, lo, hi, d_best) || (k > 0 && !d_freq) || div < 0 || attr < 0 ||
+        attr > 1)
+        return QAP_E_INVALID;
     if (div > 0 && k > 0 && launch_shape(h, 0, k) == kStream) return QAP_E_UNSUPPORTED;
     return run_search(h, 0, d_perms, k, iters, lo, hi, seed, start_base, d_best, d_done, (hipStream_t)stream,
-                      false, d_freq, div);
+                      false, d_freq, div, attr);
 }
 
 int qap_tabu_plain_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo, int32_t hi,

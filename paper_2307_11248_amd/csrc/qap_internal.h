@@ -112,6 +112,7 @@ struct SearchArgs {
     long long tile_stride;
     int32_t *freq;           // tabu: [k][m] exchange counts per search, or null
     int div;                 // with freq: diversification patience (0: none)
+    int attr;                // with freq: tabu attribute, 0 pairs of locations, 1 units
 };
 
 // With QAP_VERBOSE set in the environment, report a failed HIP call on stderr.
@@ -176,6 +177,9 @@ struct Item {
     // with freq (register-tile kernels): after more than div iterations without a new
     // best, the next move is the least exchanged non-tabu pair; 0: never
     int div;
+    // with freq: what is tabu, 0 the pair of locations exchanged, 1 the two units moved
+    // (a move is tabu while either unit it would move is marked)
+    int attr;
 };
 
 // The batched launch: one block per item of `items`; per-start buffers are shared by

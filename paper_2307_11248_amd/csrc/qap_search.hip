@@ -279,6 +279,8 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     __shared__ int s_chunk_end;   // chunked runs: set by thread 0 once the clock budget is spent
     __shared__ long long s_red2[FREQ ? 16 : 1];   // diversification: wave minima of (count, key)
     __shared__ int s_dd;                          // diversification: delta of the chosen move
+    // unit marking: the iteration until which the unit at each location is marked
+    __shared__ int s_mark[FREQ ? 264 : 1];
     const int n = a.n, rs = row_stride(n), L = blockDim.x, t = threadIdx.x;
     const int nb16 = (n + 15) & ~15;   // bytes of a row the dot products read (zero past n)
     const int nb32 = (n + 31) & ~31;   // the same, for the 32-byte steps of the row recomputation
@@ -550,8 +552,10 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         }
     }
     if (t >= W && t < 16) red[t] = NO_MOVE;   // unused wave-minimum slots
-    if constexpr (FREQ)
+    if constexpr (FREQ) {
         if (t >= W && t < 16) s_red2[t] = NO_MOVE;
+        for (int u = t; u < np; u += L) s_mark[u] = 0;
+    }
     int last_imp = 0;   // diversification: the iteration of the last new best
     bool stopped = false;
     __syncthreads();
@@ -819,6 +823,14 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         if (improved)
             for (int u = t; u < n; u += L) bestp[u] = perm[u == r ? s : (u == s ? r : u)];
         if (TABU && tpos == 0) ten[t] = draw_tenure(a.seed, (long long)it + t, start_id, a.lo, a.hi);
+        // unit marking: the two units moved are marked until it + t; they now sit at s
+        // and r (thread 0 drew ten[0] itself when tpos is 0; read after B2)
+        if constexpr (FREQ)
+            if (a.attr == 1 && t == 0) {
+                const int tt = it + ten[tpos];
+                s_mark[r] = tt;
+                s_mark[s] = tt;
+            }
         __syncthreads();  // B2
 
         // ---- C: G, G^T and p follow the move
@@ -944,7 +956,26 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                     }
             }
             bool tabu_set = false;
-            if (TABU) {
+            if (FREQ && TABU && a.attr == 1) {
+                // unit marking: a slot is tabu while either of its units is marked; only the
+                // slots in the rows and columns of r and s changed units or marks
+                if (g == r / ROWS || g == s / ROWS || b == (r >> 2) || b == (s >> 2)) {
+                    int mu[ROWS], mv[4];
+#pragma unroll
+                    for (int j = 0; j < ROWS; ++j) mu[j] = s_mark[u0 + j];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) mv[e] = s_mark[v0 + e];
+#pragma unroll
+                    for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int u = u0 + j, v = v0 + e;
+                            if ((u == r || u == s || v == r || v == s) && u < n && v < n && u != v)
+                                ut[j][e] = max(mu[j], mv[e]);
+                        }
+                    tabu_set = true;
+                }
+            } else if (TABU) {
                 // the move and its mirror become tabu until iteration it + t
                 tabu_set = (g == r / ROWS && b == (s >> 2)) || (g == s / ROWS && b == (r >> 2));
                 if (g == r / ROWS && b == (s >> 2)) {
@@ -1081,6 +1112,7 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
     it.steps_out = a.steps_out ? a.steps_out + job : nullptr;
     it.freq = FREQ ? a.freq + (size_t)job * a.m : nullptr;
     it.div = FREQ ? a.div : 0;
+    it.attr = FREQ ? a.attr : 0;
     it.st = nullptr;
     it.n = a.n;
     it.m = a.m;
@@ -1150,6 +1182,7 @@ __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     it.steps_out = a.steps_out ? a.steps_out + job : nullptr;
     it.freq = FREQ ? a.freq + (size_t)job * a.m : nullptr;
     it.div = FREQ ? a.div : 0;
+    it.attr = FREQ ? a.attr : 0;
     it.n = a.n;
     it.m = a.m;
     it.sym = a.sym;

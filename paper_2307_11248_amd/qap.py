@@ -75,8 +75,8 @@ def lib():
                 "qap_2opt_async": (ctypes.c_int, [_vp, _vp, i32, i32, _vp, _vp, _vp]),
                 "qap_tabu": (ctypes.c_int, [_vp, _i32p, i32, i32, i32, i32, u64, _i64p, _i32p]),
                 "qap_tabu_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, _vp, _vp, _vp]),
-                "qap_tabu_freq_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, i32, _vp, _vp,
-                                                        _vp, _vp]),
+                "qap_tabu_freq_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, i32, i32, _vp,
+                                                        _vp, _vp, _vp]),
                 "qap_tabu_plain_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, _vp, _vp,
                                                         _vp]),
                 "qap_2opt_with_table_async": (ctypes.c_int, [_vp, _vp, _vp, i32, i32, _vp, _vp, _vp]),
@@ -271,12 +271,14 @@ class Handle:
                "qap_tabu_async")
 
     def tabu_freq_async(self, d_perms, iters, lo, hi, seed, d_best, d_freq, d_done=None, start_base: int = 0,
-                        div: int = 0, stream=None):
+                        div: int = 0, attr: int = 0, stream=None):
         """tabu_async that also fills d_freq (int32[k][n(n-1)/2]) with the number of
         exchanges of each pair of locations, and with div > 0 makes the frequency-based
-        diversification move (``qap_tabu_freq_async``)."""
+        diversification move; attr 1 makes the units moved tabu instead of the pair of
+        locations (``qap_tabu_freq_async``)."""
         _check(lib().qap_tabu_freq_async(self.ptr, _dptr(d_perms, "int32"), d_perms.shape[0], int(iters), int(lo),
-                                         int(hi), int(seed), int(start_base), int(div), _dptr(d_best, "int64"),
+                                         int(hi), int(seed), int(start_base), int(div), int(attr),
+                                         _dptr(d_best, "int64"),
                                          _dptr(d_done, "int32"), _dptr(d_freq, "int32"), _stream_ptr(stream)),
                "qap_tabu_freq_async")
 
