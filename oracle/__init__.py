@@ -195,8 +195,9 @@ def tabu(F, D, perm, iters, lo, hi, seed, start=0, mode=1, trace_cap=0):
 def tabu_freq(F, D, perm, iters, lo, hi, seed, start=0, div=0, trace_cap=0, attr=0):
     """Tabu search keeping the frequency memory, with the frequency-based diversification
     move every time the best cost has not improved for more than div iterations (div = 0:
-    none); attr 0 makes pairs of locations tabu, 1 the units just moved.  Returns
-    (best_perm, best_cost, iters_done, freq, trace)."""
+    none); attr 0 makes pairs of locations tabu, 1 the units just moved, 2 the return of
+    both units to locations they just left.  Returns (best_perm, best_cost, iters_done,
+    freq, trace)."""
     n = len(perm)
     F, D, p0 = _mat(F, n), _mat(D, n), _vec(perm, n)
     m = n * (n - 1) // 2

@@ -358,6 +358,10 @@ ORC_EXPORT int orc_tabu(int n, const int32_t *F, const int32_t *D, const int32_t
  *   1: the units, in the manner of Zhu et al.'s unit marking (cited in Sec. 3): after the
  *      move of iteration it the two units it moved are marked until it + t, and a move
  *      is tabu while either of the units it would move is marked (mark > it).
+ *   2: unit-location pairs, in the manner of Taillard's robust tabu search (cited in
+ *      Sec. 4.3): after the move of iteration it each of the two units may not return
+ *      to the location it left until it + t, and a move is tabu when both units it
+ *      would move would return to such a location.
  * Everything else (tenure, aspiration, best update, early stop, results, trace) is as in
  * orc_tabu, mode 1.  freq (int32[n(n-1)/2]) receives the counts.  Returns 0, or -1 if
  * memory ran out.
@@ -370,8 +374,12 @@ ORC_EXPORT int orc_tabu_freq(int n, const int32_t *F, const int32_t *D, const in
     int64_t *tab = malloc(sizeof(int64_t) * (m > 0 ? m : 1));
     int64_t *until = calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
     int64_t *mark = calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));   /* per unit */
+    int64_t *uloc = calloc((size_t)(n > 0 ? n * n : 1), sizeof(int64_t)); /* per unit, location */
     int32_t *p = malloc(sizeof(int32_t) * n);
-    if (!tab || !until || !mark || !p) { free(tab); free(until); free(mark); free(p); return -1; }
+    if (!tab || !until || !mark || !uloc || !p) {
+        free(tab); free(until); free(mark); free(uloc); free(p);
+        return -1;
+    }
     for (int64_t i = 0; i < m; i++) freq[i] = 0;
     memcpy(p, p0, sizeof(int32_t) * n);
     memcpy(best_perm, p0, sizeof(int32_t) * n);
@@ -387,6 +395,14 @@ ORC_EXPORT int orc_tabu_freq(int n, const int32_t *F, const int32_t *D, const in
                 pair_of(n, i, &a, &b);
                 int64_t ma = mark[p[a]], mb = mark[p[b]];
                 until[i] = ma > mb ? ma : mb;
+            }
+        } else if (attr == 2) {
+            for (int64_t i = 0; i < m; i++) {
+                int a, b;
+                pair_of(n, i, &a, &b);
+                /* the unit at a would go to b, the one at b to a */
+                int64_t xa = uloc[(int64_t)p[a] * n + b], xb = uloc[(int64_t)p[b] * n + a];
+                until[i] = xa < xb ? xa : xb;
             }
         }
         int diversify = div > 0 && it - last > div;
@@ -414,7 +430,10 @@ ORC_EXPORT int orc_tabu_freq(int n, const int32_t *F, const int32_t *D, const in
         if (diversify) last = it;
         int64_t tt = (int64_t)it + orc_tenure(seed, (uint64_t)it, start, lo, hi);
         if (attr == 1) { mark[p[r]] = tt; mark[p[s]] = tt; }   /* the units just moved */
-        else until[pick] = tt;
+        else if (attr == 2) {                                   /* p[s] left r, p[r] left s */
+            uloc[(int64_t)p[s] * n + r] = tt;
+            uloc[(int64_t)p[r] * n + s] = tt;
+        } else until[pick] = tt;
         freq[pick] += 1;
         if (trace && done < trace_cap) {
             trace[4 * done] = r; trace[4 * done + 1] = s;
@@ -424,6 +443,6 @@ ORC_EXPORT int orc_tabu_freq(int n, const int32_t *F, const int32_t *D, const in
     }
     *best_cost = best;
     if (iters_done) *iters_done = done;
-    free(tab); free(until); free(mark); free(p);
+    free(tab); free(until); free(mark); free(uloc); free(p);
     return 0;
 }

@@ -293,7 +293,9 @@ def py_tabu_freq(F, D, p0, iters, lo, hi, seed, start, div, attr=0):
     on ties, when the best cost has not improved for more than div iterations; div = 0
     never), on tiny inputs: every neighbourhood by full recomputation of Eq. (1), tenure
     from numpy's Philox.  attr 1: a move is tabu while either unit it would move was
-    moved within its tenure (unit marking) instead of the pair of locations."""
+    moved within its tenure (unit marking) instead of the pair of locations; attr 2: a
+    move is tabu when both units would return to locations they left within their
+    tenure (unit-location pairs)."""
     n = len(p0)
     m = n * (n - 1) // 2
     p = np.array(p0).copy()
@@ -301,6 +303,7 @@ def py_tabu_freq(F, D, p0, iters, lo, hi, seed, start, div, attr=0):
     best, bestp, last = cur, p.copy(), 0
     until = [0] * m
     marked = {}          # unit -> iteration until which it is marked
+    left = {}            # (unit, location) -> iteration until which the unit may not return
     freq = [0] * m
     moves = []
     pairs = [(r, s) for r in range(n) for s in range(r + 1, n)]
@@ -308,6 +311,8 @@ def py_tabu_freq(F, D, p0, iters, lo, hi, seed, start, div, attr=0):
         deltas = np_all_swap_deltas(F, D, p)
         if attr == 1:
             until = [max(marked.get(int(p[r]), 0), marked.get(int(p[s]), 0)) for r, s in pairs]
+        elif attr == 2:
+            until = [min(left.get((int(p[r]), s), 0), left.get((int(p[s]), r), 0)) for r, s in pairs]
         pick = None
         diversify = div > 0 and it - last > div
         if diversify:
@@ -335,6 +340,9 @@ def py_tabu_freq(F, D, p0, iters, lo, hi, seed, start, div, attr=0):
         if attr == 1:
             marked[int(p[r])] = t_until
             marked[int(p[s])] = t_until
+        elif attr == 2:          # after the exchange p[s] came from r, p[r] from s
+            left[(int(p[s]), r)] = t_until
+            left[(int(p[r]), s)] = t_until
         else:
             until[pick] = t_until
         freq[pick] += 1
@@ -390,4 +398,22 @@ def test_tabu_unit_marking_matches_resimulation(seed, n, lo, hi, iters, div):
     assert bc == ec and done == ed and (bp == ep).all() and (freq == ef).all()
     assert [tuple(int(x) for x in row) for row in tr] == em
     pair = oracle.tabu_freq(F, D, p0, iters, lo, hi, seed + 3, start=seed, div=div, trace_cap=iters)
+    assert not np.array_equal(pair[4], tr)
+
+
+@pytest.mark.parametrize("seed,n,lo,hi,iters,div", [(0, 5, 2, 4, 60, 0), (1, 6, 3, 6, 80, 0), (2, 7, 4, 8, 70, 5),
+                                                     (3, 8, 5, 9, 60, 4), (4, 6, 8, 9, 40, 0)])
+def test_tabu_unit_location_matches_resimulation(seed, n, lo, hi, iters, div):
+    """The unit-location tabu attribute (a move is tabu when both units would return to
+    locations they left within their tenure), alone and with diversification, pinned to
+    the independent re-simulation; it differs from the pair attribute on these inputs."""
+    rng = np.random.default_rng(700 + seed)
+    F, D = W.random_instance(rng, n, 0, 20, symmetric=bool(seed % 2))
+    p0 = rng.permutation(n).astype(np.int32)
+    bp, bc, done, freq, tr = oracle.tabu_freq(F, D, p0, iters, lo, hi, seed + 5, start=seed, div=div,
+                                              trace_cap=iters, attr=2)
+    ep, ec, ed, ef, em = py_tabu_freq(F, D, p0, iters, lo, hi, seed + 5, seed, div, attr=2)
+    assert bc == ec and done == ed and (bp == ep).all() and (freq == ef).all()
+    assert [tuple(int(x) for x in row) for row in tr] == em
+    pair = oracle.tabu_freq(F, D, p0, iters, lo, hi, seed + 5, start=seed, div=div, trace_cap=iters)
     assert not np.array_equal(pair[4], tr)
