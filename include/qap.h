@@ -156,11 +156,15 @@ int qap_tabu_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int
  *   attr    what is tabu.  0: the pair of locations exchanged (Tabuarr, Sec. 4.3), as
  *           qap_tabu_async.  1: the units, after Zhu et al.'s marking of moved units
  *           (Sec. 3.1): the two units moved at iteration it are marked until it + t, and
- *           a move is tabu while either unit it would move is marked.
+ *           a move is tabu while either unit it would move is marked.  2: unit-location
+ *           pairs, after Taillard's robust tabu search (cited in Sec. 4.3): after the move
+ *           of iteration it neither of the two units may return to the location it left
+ *           until it + t, and a move is tabu when both units it would move would return to
+ *           such a location (needs k * n * n int32 of stream-ordered device scratch).
  *   d_freq  device int32[k][n(n-1)/2], overwritten: row j holds start j's counts at packed
  *           pair index r*n - r*(r+1)/2 + (s - r - 1) for r < s (the order of
  *           qap_delta_table); the counts sum to the moves made.
- * QAP_E_INVALID if d_freq is NULL with k > 0, div < 0 or attr not 0 or 1;
+ * QAP_E_INVALID if d_freq is NULL with k > 0, div < 0 or attr not 0, 1 or 2;
  * QAP_E_UNSUPPORTED if div > 0 and the launch would use the streamed kernel (n above the
  * register tiles' reach); otherwise as qap_tabu_async.
  */

@@ -207,6 +207,8 @@ int make_tables(qap_ctx *h, const int32_t *d_perms, int k, int32_t **d_table, hi
     return QAP_OK;
 }
 
+hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipStream_t st, bool plain);
+
 hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t *d_table, int k, int iters,
                            int lo, int hi, uint64_t seed, int64_t start_base, int64_t *d_cost, int32_t *d_steps,
                            hipStream_t st, bool plain, int32_t *d_freq = nullptr, int div = 0, int attr = 0) {
@@ -227,6 +229,22 @@ hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t
     a.freq = d_freq;
     a.div = div;
     a.attr = attr;
+    hipError_t e = hipSuccess;
+    if (d_freq && attr == 2) {
+        // the unit-location table of every search, in stream-ordered scratch
+        e = report(hipMallocAsync((void **)&a.uloc, (size_t)k * h->n * h->n * sizeof(int32_t) + 16, st),
+                   "hipMallocAsync");
+        if (e != hipSuccess) return e;
+        e = launch_shaped(h, algo, ri, a, k, st, plain);
+        const hipError_t e2 = hipFreeAsync(a.uloc, st);
+        return e != hipSuccess ? e : e2;
+    }
+    return launch_shaped(h, algo, ri, a, k, st, plain);
+}
+
+// The launches of one search call with tile shape ri (the streamed kernel takes its tile
+// state from stream-ordered scratch).
+hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipStream_t st, bool plain) {
     hipError_t e = hipSuccess;
     if (ri == kStream) {
         // tile state in stream-ordered scratch, one slice per search of a launch
@@ -567,7 +585,7 @@ int qap_tabu_freq_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters
                         uint64_t seed, int64_t start_base, int32_t div, int32_t attr, int64_t *d_best,
                         int32_t *d_done, int32_t *d_freq, void *stream) {
     if (!tabu_args_ok(h, d_perms, k, iters, lo, hi, d_best) || (k > 0 && !d_freq) || div < 0 || attr < 0 ||
-        attr > 1)
+        attr > 2)
         return QAP_E_INVALID;
     if (div > 0 && k > 0 && launch_shape(h, 0, k) == kStream) return QAP_E_UNSUPPORTED;
     return run_search(h, 0, d_perms, k, iters, lo, hi, seed, start_base, d_best, d_done, (hipStream_t)stream,

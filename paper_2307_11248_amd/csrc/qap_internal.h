@@ -112,7 +112,8 @@ struct SearchArgs {
     long long tile_stride;
     int32_t *freq;           // tabu: [k][m] exchange counts per search, or null
     int div;                 // with freq: diversification patience (0: none)
-    int attr;                // with freq: tabu attribute, 0 pairs of locations, 1 units
+    int attr;                // with freq: tabu attribute, 0 pairs of locations, 1 units, 2 unit-locations
+    int32_t *uloc;           // attr 2: [k][n][n] per search, until when a unit may not return to a location
 };
 
 // With QAP_VERBOSE set in the environment, report a failed HIP call on stderr.
@@ -178,8 +179,10 @@ struct Item {
     // best, the next move is the least exchanged non-tabu pair; 0: never
     int div;
     // with freq: what is tabu, 0 the pair of locations exchanged, 1 the two units moved
-    // (a move is tabu while either unit it would move is marked)
+    // (a move is tabu while either unit it would move is marked), 2 the return of a unit
+    // to a location it left (a move is tabu when both units would return)
     int attr;
+    int32_t *uloc;            // attr 2: [n][n], unit x location -> until when it may not return
 };
 
 // The batched launch: one block per item of `items`; per-start buffers are shared by

@@ -319,6 +319,8 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     for (int u = t; u < np; u += L) pinv[u] = -1;
     if (FREQ && a.freq)
         for (int i = t; i < a.m; i += L) a.freq[i] = 0;
+    if (FREQ && a.attr == 2)
+        for (int i = t; i < n * n; i += L) a.uloc[i] = 0;
     __syncthreads();
     const int32_t *pin = resume ? a.st_perm : a.perm_in;
     for (int u = t; u < n; u += L) {
@@ -831,6 +833,19 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 s_mark[r] = tt;
                 s_mark[s] = tt;
             }
+        // unit-location pairs: the unit at r may not return to r, nor the one at s to s,
+        // until it + t (device-scope stores, complete at B2; read after it at device scope)
+        int pr_old = 0, ps_old = 0;   // the units at r and s before the move
+        if constexpr (FREQ)
+            if (a.attr == 2) {
+                pr_old = __builtin_amdgcn_readfirstlane(perm[r]);
+                ps_old = __builtin_amdgcn_readfirstlane(perm[s]);
+                if (t == 0) {
+                    const int tt = it + ten[tpos];
+                    __hip_atomic_store(a.uloc + (size_t)pr_old * n + r, tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(a.uloc + (size_t)ps_old * n + s, tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
         __syncthreads();  // B2
 
         // ---- C: G, G^T and p follow the move
@@ -975,6 +990,38 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                         }
                     tabu_set = true;
                 }
+            } else if (FREQ && TABU && a.attr == 2) {
+                // unit-location pairs: a slot is tabu when both of its units would return to
+                // a location they left; only the slots in the rows and columns of r and s
+                // changed units or table entries.  The units at other rows and columns are
+                // read from p (only p[r] and p[s] change in this phase).
+                if (g == r / ROWS || g == s / ROWS || b == (r >> 2) || b == (s >> 2)) {
+                    int pu[ROWS], pv[4];
+#pragma unroll
+                    for (int j = 0; j < ROWS; ++j) {
+                        const int x = u0 + j;
+                        pu[j] = x == r ? ps_old : (x == s ? pr_old : (x < n ? perm[x] : 0));
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int x = v0 + e;
+                        pv[e] = x == r ? ps_old : (x == s ? pr_old : (x < n ? perm[x] : 0));
+                    }
+#pragma unroll
+                    for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int u = u0 + j, v = v0 + e;
+                            if ((u == r || u == s || v == r || v == s) && u < n && v < n && u != v) {
+                                const int xa = __hip_atomic_load(a.uloc + (size_t)pu[j] * n + v, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                                const int xb = __hip_atomic_load(a.uloc + (size_t)pv[e] * n + u, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                                ut[j][e] = min(xa, xb);
+                            }
+                        }
+                    tabu_set = true;
+                }
             } else if (TABU) {
                 // the move and its mirror become tabu until iteration it + t
                 tabu_set = (g == r / ROWS && b == (s >> 2)) || (g == s / ROWS && b == (r >> 2));
@@ -1113,6 +1160,7 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
     it.freq = FREQ ? a.freq + (size_t)job * a.m : nullptr;
     it.div = FREQ ? a.div : 0;
     it.attr = FREQ ? a.attr : 0;
+    it.uloc = FREQ && a.uloc ? a.uloc + (size_t)job * a.n * a.n : nullptr;
     it.st = nullptr;
     it.n = a.n;
     it.m = a.m;
@@ -1183,6 +1231,7 @@ __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     it.freq = FREQ ? a.freq + (size_t)job * a.m : nullptr;
     it.div = FREQ ? a.div : 0;
     it.attr = FREQ ? a.attr : 0;
+    it.uloc = FREQ && a.uloc ? a.uloc + (size_t)job * a.n * a.n : nullptr;
     it.n = a.n;
     it.m = a.m;
     it.sym = a.sym;

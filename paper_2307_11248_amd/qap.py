@@ -275,7 +275,8 @@ class Handle:
         """tabu_async that also fills d_freq (int32[k][n(n-1)/2]) with the number of
         exchanges of each pair of locations, and with div > 0 makes the frequency-based
         diversification move; attr 1 makes the units moved tabu instead of the pair of
-        locations (``qap_tabu_freq_async``)."""
+        locations, attr 2 the return of both units to locations they left
+        (``qap_tabu_freq_async``)."""
         _check(lib().qap_tabu_freq_async(self.ptr, _dptr(d_perms, "int32"), d_perms.shape[0], int(iters), int(lo),
                                          int(hi), int(seed), int(start_base), int(div), int(attr),
                                          _dptr(d_best, "int64"),

@@ -421,3 +421,38 @@ def test_tabu_unit_marking_equals_oracle(n, sym, rows, div):
         pair = oracle.tabu_freq(F, D, perms[j], iters, lo, hi, seed, start=j, div=div)
         changed |= not (pair[3] == freq).all()
     assert changed
+
+
+@pytest.mark.parametrize("n,sym,rows,div", [(12, False, 0, 0), (40, True, 1, 0), (64, False, 2, 7),
+                                            (101, True, 4, 0), (130, False, 8, 10), (150, False, 16, 0),
+                                            (200, False, -8, 0)])
+def test_tabu_unit_location_equals_oracle(n, sym, rows, div):
+    """The unit-location tabu attribute (a move is tabu when both units would return to a
+    location they left within their tenure), alone and with the diversification move,
+    equals the oracle on every tile shape, the streamed kernel included; it changes the
+    search for at least one start."""
+    import torch
+    F, D, rng = rand_inst(8000 + n + div, n, sym)
+    k, iters, seed = 3, 250, 123
+    perms = W.starts(rng, n, k)
+    lo, hi = W.tabu_tenure_range(n)
+    m = n * (n - 1) // 2
+    note("tabu unit-location n=%d rows=%d div=%d" % (n, rows, div))
+    with qap.Handle(F, D) as h:
+        if rows:
+            h.set_tile_rows("tabu", rows)
+        dp = torch.from_numpy(perms).cuda()
+        db = torch.zeros(k, dtype=torch.int64, device="cuda")
+        dd = torch.zeros(k, dtype=torch.int32, device="cuda")
+        df = torch.full((k, m), -1, dtype=torch.int32, device="cuda")
+        h.tabu_freq_async(dp, iters, lo, hi, seed, db, df, dd, div=div, attr=2)
+        torch.cuda.synchronize()
+        got_p, got_c, got_d, got_f = dp.cpu().numpy(), db.cpu().numpy(), dd.cpu().numpy(), df.cpu().numpy()
+    changed = False
+    for j in range(k):
+        bp, bc, done, freq, _ = oracle.tabu_freq(F, D, perms[j], iters, lo, hi, seed, start=j, div=div, attr=2)
+        assert (got_p[j] == bp).all() and got_c[j] == bc and got_d[j] == done, j
+        assert (got_f[j] == freq).all(), j
+        pair = oracle.tabu_freq(F, D, perms[j], iters, lo, hi, seed, start=j, div=div)
+        changed |= not (pair[3] == freq).all()
+    assert changed
