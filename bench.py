@@ -39,12 +39,12 @@ BYTES_PER_EVAL = 8   # an int32 delta read and written per entry per step if kep
 # valid only for the kernel sources they were taken with.
 KERNEL_SOURCES = ["paper_2307_11248_amd/csrc/qap_search.hip", "paper_2307_11248_amd/csrc/qap_internal.h"]
 TRAFFIC = {
-    "c2_n64_dense_tabu": {"bytes": 2 * 728 * 1024 + 40 * 1024, "sources": "679214ddfaaa3ae0"},
+    "c2_n64_dense_tabu": {"bytes": 2 * 728 * 1024 + 40 * 1024, "sources": "67d2d772d861139c"},
     # sum over the six kernels of one launch (tiles of 2 rows on 128, 256 and 512 lanes, of
     # 4 rows on 256, 512 and 768)
-    "c4_batched_uneven_tabu": {"bytes": int((2 * (1799.2 + 9562.4 + 16618.4 + 1910.6 + 48989.6 + 43361.6)
-                                             + (84.5 + 247.7 + 265.4 + 45.2 + 600.6 + 408.1)) * 1024),
-                               "sources": "679214ddfaaa3ae0"},
+    "c4_batched_uneven_tabu": {"bytes": int((2 * (1412.1 + 9547.7 + 16594.5 + 2286.7 + 48974.7 + 43354.9)
+                                             + (67.3 + 247.7 + 265.4 + 62.4 + 600.8 + 407.7)) * 1024),
+                               "sources": "67d2d772d861139c"},
 }
 
 
