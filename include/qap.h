@@ -164,9 +164,8 @@ int qap_tabu_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int
  *   d_freq  device int32[k][n(n-1)/2], overwritten: row j holds start j's counts at packed
  *           pair index r*n - r*(r+1)/2 + (s - r - 1) for r < s (the order of
  *           qap_delta_table); the counts sum to the moves made.
- * QAP_E_INVALID if d_freq is NULL with k > 0, div < 0 or attr not 0, 1 or 2;
- * QAP_E_UNSUPPORTED if div > 0 and the launch would use the streamed kernel (n above the
- * register tiles' reach); otherwise as qap_tabu_async.
+ * QAP_E_INVALID if d_freq is NULL with k > 0, div < 0 or attr not 0, 1 or 2; otherwise as
+ * qap_tabu_async.  Every tile shape serves it, the streamed kernel included.
  */
 int qap_tabu_freq_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo,
                         int32_t hi, uint64_t seed, int64_t start_base, int32_t div, int32_t attr,

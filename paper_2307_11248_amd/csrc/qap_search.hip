@@ -587,14 +587,37 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         int dstar = __builtin_amdgcn_readfirstlane((int)(mk >> 32));
         int kstar = __builtin_amdgcn_readfirstlane((int)(mk & 0xffffffffLL));
         bool diversified = false;
-        if constexpr (FREQ && !STREAM) {
+        if constexpr (FREQ) {
             if (a.div > 0 && it - last_imp > a.div) {
                 // diversification move: the non-tabu pair exchanged least often so far,
                 // lowest key on ties (a pair's own slot has a lower key than its mirror
                 // slot, so the winner is never a mirror).  The counts are read at device
                 // scope: the adds of earlier moves were made in L2.
                 long long dsel = NO_MOVE;
-                if (active) {
+                auto consider = [&](int u, int v, int until) {
+                    if (u < n && v < n && u != v && until <= it) {
+                        const int cnt = __hip_atomic_load(a.freq + pidx(n, min(u, v), max(u, v)),
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const long long c = ((long long)cnt << 32) | (unsigned)((u << 9) | v);
+                        dsel = c < dsel ? c : dsel;
+                    }
+                };
+                if constexpr (STREAM) {
+                    // the lane's tiles, their tabu state as the last pass stored it
+                    for (int q = 0; q < npass; ++q) {
+                        const int tix = t + q * L;
+                        if (tix >= a.ntiles) break;
+                        int tg, tb;
+                        tile_of(tix, tg, tb);
+                        for (int j = 0; j < ROWS; ++j) {
+                            const int4 y = a.tile_u[tile_addr(q, j)];
+                            consider(tg * ROWS + j, tb * TILE_COLS, y.x);
+                            consider(tg * ROWS + j, tb * TILE_COLS + 1, y.y);
+                            consider(tg * ROWS + j, tb * TILE_COLS + 2, y.z);
+                            consider(tg * ROWS + j, tb * TILE_COLS + 3, y.w);
+                        }
+                    }
+                } else if (active) {
                     // opaque copies of the tile origin: the count addresses are made here,
                     // not kept through the whole loop as invariants
                     int pu = u0, pv = v0;
@@ -603,13 +626,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                     for (int j = 0; j < ROWS; ++j)
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
-                            const int u = pu + j, v = pv + e;
-                            if (u < n && v < n && u != v && ut[j][e] <= it) {
-                                const int cnt = __hip_atomic_load(a.freq + pidx(n, min(u, v), max(u, v)),
-                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                const long long c = ((long long)cnt << 32) | (unsigned)((u << 9) | v);
-                                dsel = c < dsel ? c : dsel;
-                            }
+                            consider(pu + j, pv + e, ut[j][e]);
                             // one load in flight at a time: this rare path must not add to the
                             // registers the loop holds
                             asm volatile("" ::: "memory");
@@ -625,7 +642,19 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                     const int kd = __builtin_amdgcn_readfirstlane((int)(mk2 & 0xffffffffLL));
                     const int ud = kd >> 9, vd = kd & 511;
                     // the lane holding the pair's own slot publishes its delta
-                    if (active && ud >= u0 && ud < u0 + ROWS && vd >= v0 && vd < v0 + TILE_COLS) {
+                    if constexpr (STREAM) {
+                        for (int q = 0; q < npass; ++q) {
+                            const int tix = t + q * L;
+                            if (tix >= a.ntiles) break;
+                            int tg, tb;
+                            tile_of(tix, tg, tb);
+                            const int j = ud - tg * ROWS, e = vd - tb * TILE_COLS;
+                            if (j >= 0 && j < ROWS && e >= 0 && e < TILE_COLS) {
+                                const int4 x = a.tile_d[tile_addr(q, j)];
+                                s_dd = e == 0 ? x.x : (e == 1 ? x.y : (e == 2 ? x.z : x.w));
+                            }
+                        }
+                    } else if (active && ud >= u0 && ud < u0 + ROWS && vd >= v0 && vd < v0 + TILE_COLS) {
                         int x = 0;
 #pragma unroll
                         for (int j = 0; j < ROWS; ++j)

@@ -341,12 +341,12 @@ def test_tabu_frequency_memory_counts_the_oracle_moves(n, sym, rows):
 
 @pytest.mark.parametrize("n,sym,rows,div", [(12, False, 0, 3), (40, True, 1, 6), (64, False, 2, 10),
                                             (64, False, 1, 4), (101, True, 4, 8), (130, False, 8, 12),
-                                            (150, False, 16, 9)])
+                                            (150, False, 16, 9), (200, False, -8, 7), (230, True, -8, 11)])
 def test_tabu_frequency_diversification_equals_oracle(n, sym, rows, div):
     """With div > 0 the frequency memory drives a diversification move (the least
     exchanged non-tabu pair after more than div iterations without a new best): best
-    permutations, costs, moves made and counts equal the oracle's, on every register tile
-    shape; the rule changes the search for at least one start."""
+    permutations, costs, moves made and counts equal the oracle's, on every tile shape,
+    the streamed kernel included; the rule changes the search for at least one start."""
     import torch
     F, D, rng = rand_inst(6000 + n + div, n, sym)
     k, iters, seed = 4, 300, 4242
@@ -374,23 +374,9 @@ def test_tabu_frequency_diversification_equals_oracle(n, sym, rows, div):
     assert changed
 
 
-def test_tabu_diversification_rejected_on_the_streamed_kernel():
-    import torch
-    F, D, rng = rand_inst(6200, 200, False)
-    perms = W.starts(rng, 200, 1)
-    note("tabu diversification streamed n=200")
-    with qap.Handle(F, D) as h:
-        dp = torch.from_numpy(perms).cuda()
-        db = torch.zeros(1, dtype=torch.int64, device="cuda")
-        df = torch.zeros((1, 200 * 199 // 2), dtype=torch.int32, device="cuda")
-        with pytest.raises(qap.QapError) as ei:
-            h.tabu_freq_async(dp, 10, 180, 220, 1, db, df, div=5)
-        assert ei.value.code == qap.QAP_E_UNSUPPORTED
-
-
 @pytest.mark.parametrize("n,sym,rows,div", [(12, False, 0, 0), (40, True, 1, 0), (64, False, 2, 6),
                                             (101, True, 4, 0), (130, False, 8, 9), (150, False, 16, 0),
-                                            (200, False, -8, 0)])
+                                            (200, False, -8, 0), (210, True, -8, 8)])
 def test_tabu_unit_marking_equals_oracle(n, sym, rows, div):
     """The unit-marking tabu attribute (the two units moved are marked for the tenure; a
     move is tabu while either of its units is marked), alone and with the diversification
@@ -425,7 +411,7 @@ def test_tabu_unit_marking_equals_oracle(n, sym, rows, div):
 
 @pytest.mark.parametrize("n,sym,rows,div", [(12, False, 0, 0), (40, True, 1, 0), (64, False, 2, 7),
                                             (101, True, 4, 0), (130, False, 8, 10), (150, False, 16, 0),
-                                            (200, False, -8, 0)])
+                                            (200, False, -8, 0), (190, False, -8, 9)])
 def test_tabu_unit_location_equals_oracle(n, sym, rows, div):
     """The unit-location tabu attribute (a move is tabu when both units would return to a
     location they left within their tenure), alone and with the diversification move,
