@@ -23,7 +23,7 @@
  * without waiting, and neither read nor write their buffers from the host.
  *
  * Exactness: all flows and distances must lie in [0, 255].  Then every delta fits in
- * int32 with a wide margin (|delta| <= (2n-2) * 255 * 255 < 2^26 for n <= 256) and every
+ * int32 with a wide margin (|delta| <= (2n-2) * 255 * 255 < 2^26 for n <= 512) and every
  * cost in int64, and all results are exact integers, identical to a plain CPU
  * evaluation of the paper's formulas.
  *
@@ -40,7 +40,10 @@
 extern "C" {
 #endif
 
-#define QAP_NMAX 256
+#define QAP_NMAX 512
+/* Largest n of the batched (qap_batch_*) and served (qap_server_*) searches, and of the
+ * frequency memory (qap_tabu_freq_async); above it those return QAP_E_UNSUPPORTED. */
+#define QAP_NMAX_BATCH 256
 
 enum {
     QAP_OK = 0,
@@ -61,11 +64,16 @@ const char *qap_strerror(int code);
  * Create a handle for one instance (F, D) of size n (Sec. 2.1) on the current HIP
  * device.  F and D are host pointers, read once and copied; the handle owns its device
  * copies until qap_destroy.  Returns QAP_E_RANGE if an entry lies outside [0, 255].
- * Every entry point serves every n <= QAP_NMAX: the searches hold the neighbourhood in
- * registers and F, F^T, D, D^T in LDS while that fits one workgroup (n <= 176 in the
- * batched kernels), and above that run the streamed kernel (neighbourhood in global
- * memory, only G = F[p][p] in LDS).  QAP_E_UNSUPPORTED is left for a device whose LDS
- * is smaller than the streamed kernel needs.
+ * Every entry point serves every n <= QAP_NMAX_BATCH: the searches hold the
+ * neighbourhood in registers and F, F^T, D, D^T in LDS while that fits one workgroup
+ * (n <= 176 in the batched kernels), and above that run the streamed kernel
+ * (neighbourhood in global memory, only G = F[p][p] in LDS).  For QAP_NMAX_BATCH < n <=
+ * QAP_NMAX the single-instance entry points (cost, neighbourhood table, qap_2opt*,
+ * qap_tabu*, except qap_tabu_freq_async) run the wide streamed kernel, which keeps G and
+ * G^T in global memory too (2 n RS bytes of stream-ordered scratch per search, RS = n
+ * rounded up to 32, plus 16), and the neighbourhood table is evaluated entry by entry
+ * from Eq. (2).  QAP_E_UNSUPPORTED is left for a device whose LDS is smaller than the
+ * streamed kernel needs.
  */
 int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out);
 

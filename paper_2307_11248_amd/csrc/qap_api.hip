@@ -126,7 +126,7 @@ const TileSet &shape_tiles(const qap_ctx *h, int ri) { return h->tiles[ri == kSt
 
 bool shape_fits(const qap_ctx *h, int ri) {
     if (ri == kStream) return h->stream_ok != 0;
-    if (ri < 0 || ri >= kShapes) return false;
+    if (ri < 0 || ri >= kShapes || h->n > WIDE_N) return false;
     const TileSet &ts = h->tiles[ri];
     if (ts.lanes < 64 || ts.lanes > search_max_lanes(kRowsChoices[ri])) return false;
     if (ts.ntiles > ts.lanes) return false;
@@ -253,6 +253,14 @@ hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipS
         e = report(hipMallocAsync((void **)&a.tile_work, (size_t)per_launch * a.tile_stride * sizeof(int4), st),
                    "hipMallocAsync");
         if (e != hipSuccess) return e;
+        if (h->n > WIDE_N) {   // G and G^T of every search of a launch
+            a.gstride = wide_g_bytes(h->n, h->sym);
+            e = report(hipMallocAsync((void **)&a.gwork, (size_t)per_launch * a.gstride, st), "hipMallocAsync");
+            if (e != hipSuccess) {
+                (void)hipFreeAsync(a.tile_work, st);
+                return e;
+            }
+        }
         if (plain) {
             for (int j = 0; j < k && e == hipSuccess; ++j) {
                 a.job0 = j;
@@ -262,7 +270,11 @@ hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipS
             a.job0 = 0;
             e = launch_stream(algo == 0, a, k, st);
         }
-        const hipError_t e2 = hipFreeAsync(a.tile_work, st);
+        hipError_t e2 = hipFreeAsync(a.tile_work, st);
+        if (a.gwork) {
+            const hipError_t e3 = hipFreeAsync(a.gwork, st);
+            if (e2 == hipSuccess) e2 = e3;
+        }
         return e != hipSuccess ? e : e2;
     }
     const int rows = kRowsChoices[ri];
@@ -297,6 +309,7 @@ int run_search(qap_ctx *h, int algo, int32_t *d_perms, int k, int iters, int lo,
 // Whether tile shape ri serves this instance in the batched kernel (fixed workgroup of
 // BATCH_LANES lanes, rows 2, 4 or 8).
 bool batch_fits(const qap_ctx *h, int ri) {
+    if (h->n > WIDE_N) return false;   // the wide streamed kernel runs single-instance searches only
     if (ri == kStream) return h->stream_ok != 0;
     if (ri < kBatchFirst || ri > kBatchFirst + 2) return false;
     const TileSet &ts = h->tiles[ri];
@@ -310,7 +323,7 @@ bool batch_fits(const qap_ctx *h, int ri) {
 int batch_default(const qap_ctx *h) {
     for (int i = kBatchFirst; i < kBatchFirst + 3; ++i)
         if (batch_fits(h, i)) return i;
-    return h->stream_ok ? kStream : -1;
+    return h->stream_ok && h->n <= WIDE_N ? kStream : -1;
 }
 
 bool algo_fits(const qap_ctx *h, int algo, int ri) { return algo == 2 ? batch_fits(h, ri) : shape_fits(h, ri); }
@@ -587,6 +600,7 @@ int qap_tabu_freq_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters
     if (!tabu_args_ok(h, d_perms, k, iters, lo, hi, d_best) || (k > 0 && !d_freq) || div < 0 || attr < 0 ||
         attr > 2)
         return QAP_E_INVALID;
+    if (h->n > WIDE_N) return QAP_E_UNSUPPORTED;   // the wide kernel keeps no frequency memory
     return run_search(h, 0, d_perms, k, iters, lo, hi, seed, start_base, d_best, d_done, (hipStream_t)stream,
                       false, d_freq, div, attr);
 }

@@ -10,12 +10,15 @@
 namespace qapk {
 
 // Delta held by slots that are not moves (the diagonal u == v of a tile and padding
-// beyond n).  Larger than any real delta (|delta| < 2^26 for entries in [0, 255] and
-// n <= 256), so such a slot is never the best candidate, and the incremental update
-// adds exactly 0 to a diagonal slot.
+// beyond n).  Larger than any real delta (|delta| <= (2n - 2) * 255^2 < 2^26 for entries
+// in [0, 255] and n <= 512), so such a slot is never the best candidate, and the
+// incremental update adds exactly 0 to a diagonal slot.
 constexpr int BIG = 0x3FFFFFFF;
 constexpr int KEY_NONE = 0x7FFFFFFF;
 constexpr int TILE_COLS = 4;   // columns of the register tile held by one lane
+// Above this n, G = F[p][p] and G^T no longer fit in LDS beside the search's other
+// arrays: the wide streamed kernel keeps them, like D and D^T, in global memory.
+constexpr int WIDE_N = 256;
 // Bound on the moves of one 2opt search run to a local optimum (the cost strictly
 // decreases, so this only bounds a run on inconsistent data).
 constexpr int TWO_OPT_MAX_MOVES = 1 << 20;
@@ -47,8 +50,10 @@ struct Smem {
     int d, dt, g, gt, acbe, rpr, rps, kc, perm, bestp, pinv, ten, red, total;
 };
 
-// dglobal: D and D^T are read from global memory (the streamed kernels), not staged.
-__host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym, bool dglobal = false) {
+// dglobal: D and D^T are read from global memory (the streamed kernels), not staged;
+// gglobal: so are G and G^T (the wide streamed kernel, n above WIDE_N).
+__host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym, bool dglobal = false,
+                                          bool gglobal = false) {
     const int rs = row_stride(n);
     Smem s;
     int o = 0;
@@ -63,8 +68,12 @@ __host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym, boo
         s.d = take_mat(128); o += n * rs;
         s.dt = sym ? s.d : take_mat(192); if (!sym) o += n * rs;
     }
-    s.g = take_mat(0); o += n * rs;
-    s.gt = sym ? s.g : take_mat(64); if (!sym) o += n * rs;
+    if (gglobal) {
+        s.g = s.gt = -1;
+    } else {
+        s.g = take_mat(0); o += n * rs;
+        s.gt = sym ? s.g : take_mat(64); if (!sym) o += n * rs;
+    }
     s.acbe = take(np * 8);
     s.rpr = take(np * 4);
     s.rps = take(np * 4);
@@ -114,6 +123,8 @@ struct SearchArgs {
     int div;                 // with freq: diversification patience (0: none)
     int attr;                // with freq: tabu attribute, 0 pairs of locations, 1 units, 2 unit-locations
     int32_t *uloc;           // attr 2: [k][n][n] per search, until when a unit may not return to a location
+    uint8_t *gwork;          // wide streamed kernel: per search, gstride bytes holding G and G^T
+    long long gstride;
 };
 
 // With QAP_VERBOSE set in the environment, report a failed HIP call on stderr.
@@ -175,7 +186,7 @@ struct Item {
     // tabu: the frequency memory, m counts of how often each pair of locations was
     // exchanged (packed pair index), zeroed when the search starts; null: not kept
     int32_t *freq;
-    // with freq (register-tile kernels): after more than div iterations without a new
+    // with freq: after more than div iterations without a new
     // best, the next move is the least exchanged non-tabu pair; 0: never
     int div;
     // with freq: what is tabu, 0 the pair of locations exchanged, 1 the two units moved
@@ -183,6 +194,7 @@ struct Item {
     // to a location it left (a move is tabu when both units would return)
     int attr;
     int32_t *uloc;            // attr 2: [n][n], unit x location -> until when it may not return
+    uint8_t *gmat;            // wide streamed kernel: G, then G^T (unless symmetric), rows of RS bytes
 };
 
 // The batched launch: one block per item of `items`; per-start buffers are shared by
@@ -229,9 +241,17 @@ int search_max_lanes(int rows);
 // unit at once (HIP's occupancy query; 0 if it fails).
 int search_blocks_per_cu(int n, int rows, bool tabu, int lanes, int sym);
 // Streamed kernels (any n up to 256): tiles of STREAM_ROWS x 4 slots kept in global memory
-// between passes, D read from global memory, BATCH_LANES lanes per search.
+// between passes, D read from global memory, BATCH_LANES lanes per search.  The wide form
+// (n above WIDE_N, up to 512, single-instance searches only) also keeps G and G^T in
+// global memory (Item::gmat, wide_g_bytes(n, sym) per search) and runs up to four
+// (index, family) tasks per lane.
 constexpr int STREAM_ROWS = 8;
+constexpr int WIDE_MAXN = 512;
+constexpr int WIDE_MAXT = 4 * WIDE_MAXN / BATCH_LANES;   // tasks a lane, n = 512 not symmetric
 int stream_shape_ok(int n, int sym, size_t max_smem);
+__host__ __device__ inline long long wide_g_bytes(int n, int sym) {
+    return (((long long)(sym ? 1 : 2) * n * row_stride(n)) + 255) & ~255LL;
+}
 // int4 of tile state one streamed search needs (deltas, then tabu-until values)
 __host__ __device__ inline long long stream_tile_int4(int ntiles) {
     const long long passes = (ntiles + BATCH_LANES - 1) / BATCH_LANES;

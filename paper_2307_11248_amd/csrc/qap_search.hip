@@ -273,7 +273,8 @@ __device__ inline void dot_rows2_64(const uint8_t *a, const uint8_t *b1, const u
 // >= families * n).  NARROW: the row recomputation reads 16 bytes a step instead of 32
 // (for kernels held to 128 VGPRs, where the wider steps spill).  FREQ: tabu keeps the
 // frequency memory in a.freq (compiled only into the kernels that need it).
-template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool SYM, bool NARROW, bool FREQ = false>
+template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool SYM, bool NARROW, bool FREQ = false,
+          bool GGLOB = false>
 __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsigned char *sm) {
     __shared__ int s_bad;
     __shared__ int s_chunk_end;   // chunked runs: set by thread 0 once the clock budget is spent
@@ -288,14 +289,26 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     constexpr int sym = SYM ? 1 : 0;   // F and D both symmetric (the caller checked a.sym)
     constexpr int nq = SYM ? 2 : 4, lq = SYM ? 1 : 2;
     const int np = padded_n(n, ROWS);
-    const Smem S = smem_plan(n, np, L, sym, STREAM);
+    const Smem S = smem_plan(n, np, L, sym, STREAM, GGLOB);
     SearchState *const st = RESUME ? a.st : nullptr;   // saved state, chunked runs only
     const bool resume = RESUME && st != nullptr && st->it > 1;
 
     // D and D^T: staged in LDS, or (streamed kernels) read in place from global memory
     const uint8_t *Dm = STREAM ? a.mats + 2 * n * rs : sm + S.d;
     const uint8_t *DmT = STREAM ? a.mats + 3 * n * rs : sm + S.dt;
-    uint8_t *Gm = sm + S.g, *GmT = sm + S.gt;
+    // G and G^T: in LDS, or (wide kernel) in the search's global scratch, where a byte's
+    // offset is counted from a.gmat instead of from the LDS base
+    uint8_t *const gbase = GGLOB ? a.gmat : sm;
+    const int g_off = GGLOB ? 0 : S.g, gt_off = GGLOB ? (sym ? 0 : n * rs) : S.gt;
+    uint8_t *Gm = gbase + g_off, *GmT = gbase + gt_off;
+    // wide kernel: G is written by some lanes and read by others through the vector
+    // caches, so the barriers that order those accesses also make the writes visible
+    // at device scope and drop stale lines before the reads
+    auto gsync = [&]() {
+        if constexpr (GGLOB) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if constexpr (GGLOB) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    };
     int *rpr = reinterpret_cast<int *>(sm + S.rpr);
     int *rps = reinterpret_cast<int *>(sm + S.rps);
     int *kc = reinterpret_cast<int *>(sm + S.kc);
@@ -363,7 +376,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             if (!sym) reinterpret_cast<unsigned *>(GmT)[i] = wgt;
         }
     }
-    __syncthreads();
+    gsync();
 
     // ---- RD_u = sum_k D[u][k] G[u][k], CD_u = sum_k D[k][u] G[k][u]; cost (Eq. 1) = sum RD_u
     long long part = 0;
@@ -576,7 +589,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         if (!STREAM) sel = active ? tile_min(dl, ut, u0, v0, it, aspiration()) : NO_MOVE;
         const long long kw = wave_min_pair<64>((int)(sel >> 32), (int)(sel & 0xffffffffLL));
         if (lane == 0) red[wid] = kw;
-        __syncthreads();  // B1
+        gsync();  // B1
         if (RESUME && s_chunk_end) break;   // uniform: every lane reads the same word
         // workgroup minimum of the 16 wave-minimum slots (slots past W hold the largest
         // key): lane i of every wave reads slot i, then the same two-pass DPP minimum
@@ -686,15 +699,17 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             __hip_atomic_fetch_add(a.freq + pidx(n, r, s), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         // words of rows r and s of G and G^T for the exchange in C (read now, G is not
-        // written before B2); lanes 0 .. RS/4-1 of wave 0, which all hold task 0
-        const bool swap_lane = wid == 0 && lane < rs / 4;
+        // written before B2); lanes 0 .. 63 of wave 0 (the bytes of n <= 256), or in the
+        // wide kernel lanes 0 .. RS/4-1, all of which hold task 0
+        const int swl = GGLOB ? t : lane;
+        const bool swap_lane = GGLOB ? t < rs / 4 : (wid == 0 && lane < rs / 4);
         unsigned sw_r = 0, sw_s = 0, swt_r = 0, swt_s = 0;
         int sw_grr = 0, sw_grs = 0, sw_gsr = 0, sw_gss = 0;
         if (swap_lane) {
-            sw_r = reinterpret_cast<const unsigned *>(Gm + r * rs)[lane];
-            sw_s = reinterpret_cast<const unsigned *>(Gm + s * rs)[lane];
-            swt_r = reinterpret_cast<const unsigned *>(GmT + r * rs)[lane];
-            swt_s = reinterpret_cast<const unsigned *>(GmT + s * rs)[lane];
+            sw_r = reinterpret_cast<const unsigned *>(Gm + r * rs)[swl];
+            sw_s = reinterpret_cast<const unsigned *>(Gm + s * rs)[swl];
+            swt_r = reinterpret_cast<const unsigned *>(GmT + r * rs)[swl];
+            swt_s = reinterpret_cast<const unsigned *>(GmT + s * rs)[swl];
         }
         // ---- X: one (u, family) task per lane: the update vectors of u, and the deltas
         //      of (u, r) and (u, s) under p'
@@ -841,10 +856,10 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             // this lane's share of exchanging columns r and s of G (and G^T) in row u
             if (u != r && u != s) {
                 if (sym) {
-                    colw_addr[i] = S.g + u * rs + (q == 0 ? r : s);
+                    colw_addr[i] = g_off + u * rs + (q == 0 ? r : s);
                     colw_val[i] = q == 0 ? g_us : g_ur;
                 } else {
-                    colw_addr[i] = ((q & 2) ? S.gt : S.g) + u * rs + ((q & 1) ? s : r);
+                    colw_addr[i] = ((q & 2) ? gt_off : g_off) + u * rs + ((q & 1) ? s : r);
                     colw_val[i] = q == 0 ? g_us : (q == 1 ? g_ur : (q == 2 ? g_su : g_ru));
                 }
             }
@@ -875,12 +890,12 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                     __hip_atomic_store(a.uloc + (size_t)ps_old * n + s, tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
-        __syncthreads();  // B2
+        gsync();  // B2
 
         // ---- C: G, G^T and p follow the move
         if (swap_lane) {
             // rows r and s exchange, with their entries at columns r and s exchanged
-            const int wr = lane;
+            const int wr = swl;
             unsigned nr = sw_s, ns = sw_r, nrt = swt_s, nst = swt_r;
             if ((r >> 2) == wr) {
                 const int sh = 8 * (r & 3);
@@ -907,7 +922,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         }
 #pragma unroll
         for (int i = 0; i < MAXT; ++i)
-            if (colw_addr[i] >= 0) sm[colw_addr[i]] = (uint8_t)colw_val[i];
+            if (colw_addr[i] >= 0) gbase[colw_addr[i]] = (uint8_t)colw_val[i];
         if (t == 0) {
             const int pr = perm[r], ps = perm[s];
             perm[r] = ps;
@@ -1164,12 +1179,13 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
 }
 
 // The search body for both symmetric and general instances (one uniform branch).
-template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool NARROW, bool FREQ = false>
+template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool NARROW, bool FREQ = false,
+          bool GGLOB = false>
 __device__ __attribute__((always_inline)) void search_body(const Item &a, unsigned char *sm) {
     if (a.sym)
-        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, true, NARROW, FREQ>(a, sm);
+        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, true, NARROW, FREQ, GGLOB>(a, sm);
     else
-        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, false, NARROW, FREQ>(a, sm);
+        search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, false, NARROW, FREQ, GGLOB>(a, sm);
 }
 
 // One search per workgroup: block b runs search job0 + b of the launch.
@@ -1244,8 +1260,9 @@ __global__ void __launch_bounds__(BATCH_LANES) resume_kernel(const Item *items) 
     }
 }
 
-// Streamed search, one per workgroup: block b runs search job0 + b of the launch.
-template <bool TABU, bool FREQ = false>
+// Streamed search, one per workgroup: block b runs search job0 + b of the launch.  WIDE
+// (n above WIDE_N): G and G^T in global scratch, up to four (index, family) tasks a lane.
+template <bool TABU, bool FREQ = false, bool WIDE = false>
 __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const int job = a.job0 + blockIdx.x;
@@ -1275,7 +1292,12 @@ __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     it.stream = 1;
     it.tile_d = a.tile_work + (size_t)blockIdx.x * a.tile_stride;
     it.tile_u = it.tile_d + a.tile_stride / 2;
-    search_body<STREAM_ROWS, TABU, 1024 / BATCH_LANES, false, true, false, FREQ>(it, sm);
+    if constexpr (WIDE) {
+        it.gmat = a.gwork + (size_t)blockIdx.x * a.gstride;
+        search_body<STREAM_ROWS, TABU, WIDE_MAXT, false, true, false, false, true>(it, sm);
+    } else {
+        search_body<STREAM_ROWS, TABU, 1024 / BATCH_LANES, false, true, false, FREQ>(it, sm);
+    }
 }
 
 template <int ROWS, bool TABU, bool FREQ = false>
@@ -1391,18 +1413,25 @@ hipError_t launch_resume(const Item *d_items, int count, size_t smem, hipStream_
 }
 
 size_t stream_smem_bytes(int n, int sym) {
-    return (size_t)smem_plan(n, padded_n(n, STREAM_ROWS), BATCH_LANES, sym, true).total;
+    return (size_t)smem_plan(n, padded_n(n, STREAM_ROWS), BATCH_LANES, sym, true, n > WIDE_N).total;
 }
 
 int stream_shape_ok(int n, int sym, size_t max_smem) {
-    return families(sym) * n <= 1024 && stream_smem_bytes(n, sym) <= max_smem ? 1 : 0;
+    const int tasks = n <= WIDE_N ? 1024 : (n <= WIDE_MAXN ? BATCH_LANES * WIDE_MAXT : 0);
+    return families(sym) * n <= tasks && stream_smem_bytes(n, sym) <= max_smem ? 1 : 0;
 }
 
 // grid = searches in this launch; a.tile_work holds grid * a.tile_stride int4.
 hipError_t launch_stream(bool tabu, const SearchArgs &a, int grid, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
     const size_t smem = stream_smem_bytes(a.n, a.sym);
-    if (tabu && a.freq)
+    if (a.n > WIDE_N) {   // G in a.gwork; no frequency memory
+        if (a.freq || !a.gwork) return hipErrorInvalidValue;
+        if (tabu)
+            hipLaunchKernelGGL((stream_kernel<true, false, true>), dim3(grid), dim3(BATCH_LANES), smem, st, a);
+        else
+            hipLaunchKernelGGL((stream_kernel<false, false, true>), dim3(grid), dim3(BATCH_LANES), smem, st, a);
+    } else if (tabu && a.freq)
         hipLaunchKernelGGL((stream_kernel<true, true>), dim3(grid), dim3(BATCH_LANES), smem, st, a);
     else if (tabu)
         hipLaunchKernelGGL(stream_kernel<true>, dim3(grid), dim3(BATCH_LANES), smem, st, a);

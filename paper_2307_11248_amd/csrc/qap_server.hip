@@ -183,6 +183,10 @@ const Tiles *tiles_for(qap_server *s, int n, int rows, int *rc) {
 // register-tile kernel, else the streamed kernel (rows = -STREAM_ROWS); -1 if none.
 int server_rows(qap_server *s, int n, int sym, int *rc) {
     *rc = QAP_OK;
+    if (n > WIDE_N) {   // the wide streamed kernel serves single-instance searches only
+        *rc = QAP_E_UNSUPPORTED;
+        return -1;
+    }
     for (int rows : {2, 4, 8}) {
         int ninner = 0;
         const int nt = (int)enumerate_tiles(n, rows, &ninner).size();

@@ -127,6 +127,82 @@ __device__ bool tb_stage_perm(const int32_t *p, int n, int *perm, int *pinv, int
     return *bad == 0;
 }
 
+// n above WIDE_N (F and D do not fit in LDS): the matrices are read in place from global
+// memory, only the start and its inverse are staged.
+
+// Cost (Eq. 1) of one start per workgroup.
+__global__ void __launch_bounds__(256) cost_wide_kernel(TableArgs a) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    __shared__ int bad;
+    __shared__ long long red[4];
+    const int n = a.n, rs = row_stride(n), job = blockIdx.x, t = threadIdx.x;
+    int *perm = reinterpret_cast<int *>(sm), *pinv = perm + n;
+    if (!tb_stage_perm(a.perms + (size_t)job * n, n, perm, pinv, &bad)) {
+        if (t == 0) a.costs[job] = INT64_MIN;
+        return;
+    }
+    const uint8_t *F = a.mats, *D = a.mats + (size_t)2 * n * rs;
+    long long part = 0;
+    for (int i = t; i < n; i += blockDim.x) {
+        const uint8_t *frow = F + (size_t)perm[i] * rs, *drow = D + (size_t)i * rs;
+        int acc = 0;   // at most n * 255^2 < 2^31
+        for (int k = 0; k < n; ++k) acc += (int)frow[perm[k]] * (int)drow[k];
+        part += acc;
+    }
+    part = wave_sum64(part);
+    if ((t & 63) == 0) red[t >> 6] = part;
+    __syncthreads();
+    if (t == 0) {
+        long long z = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) z += red[w];
+        a.costs[job] = z;
+    }
+}
+
+// Neighbourhood row r of start `job` (block (r, job)): lane t evaluates the exchange of
+// locations r and s = r + 1 + t by Eq. (2), with G = F[p][p]:
+//   delta(r, s) = sum_{k != r, s} (G_sk - G_rk)(D_rk - D_sk) + (G_ks - G_kr)(D_kr - D_ks)
+//               + (G_ss - G_rr)(D_rr - D_ss) + (G_sr - G_rs)(D_rs - D_sr).
+// Row r's bytes (G_rk, G_kr, D_rk, D_kr) are staged in LDS; row s's are read from F, F^T,
+// D and D^T in global memory.
+__global__ void __launch_bounds__(TB_LANES) table_wide_kernel(TableArgs a) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    __shared__ int bad;
+    const int n = a.n, rs = row_stride(n), r = blockIdx.x, job = blockIdx.y, t = threadIdx.x;
+    int32_t *out = a.table + (size_t)job * a.m;
+    int *perm = reinterpret_cast<int *>(sm), *pinv = perm + n;
+    uint8_t *gr = reinterpret_cast<uint8_t *>(pinv + n), *gtr = gr + n, *dr = gtr + n, *dtr = dr + n;
+    const int s = r + 1 + t;
+    if (!tb_stage_perm(a.perms + (size_t)job * n, n, perm, pinv, &bad)) {
+        if (s < n) out[pidx(n, r, s)] = 0;
+        return;
+    }
+    const uint8_t *F = a.mats, *FT = F + (size_t)n * rs, *D = F + (size_t)2 * n * rs, *DT = F + (size_t)3 * n * rs;
+    const int pr = perm[r];
+    for (int k = t; k < n; k += blockDim.x) {
+        const int pk = perm[k];
+        gr[k] = F[(size_t)pr * rs + pk];
+        gtr[k] = FT[(size_t)pr * rs + pk];
+        dr[k] = D[(size_t)r * rs + k];
+        dtr[k] = DT[(size_t)r * rs + k];
+    }
+    __syncthreads();
+    if (s >= n) return;
+    const int ps = perm[s];
+    const uint8_t *Fs = F + (size_t)ps * rs, *FTs = FT + (size_t)ps * rs, *Ds = D + (size_t)s * rs,
+                  *DTs = DT + (size_t)s * rs;
+    int acc = 0;
+    for (int k = 0; k < n; ++k) {
+        const int pk = perm[k];
+        const int term = ((int)Fs[pk] - (int)gr[k]) * ((int)dr[k] - (int)Ds[k]) +
+                         ((int)FTs[pk] - (int)gtr[k]) * ((int)dtr[k] - (int)DTs[k]);
+        acc += (k == r || k == s) ? 0 : term;
+    }
+    acc += ((int)Fs[ps] - (int)gr[r]) * ((int)dr[r] - (int)Ds[s]) +
+           ((int)Fs[pr] - (int)gr[s]) * ((int)dr[s] - (int)Ds[r]);
+    out[pidx(n, r, s)] = acc;
+}
+
 // (I, J), I <= J, of tile pair q in row-major order over nt x nt tiles
 __device__ inline void tb_pair(int q, int nt, int &I, int &J) {
     I = 0;
@@ -326,6 +402,10 @@ hipError_t launch_table_items(const Item *d_items, int count, size_t smem, hipSt
 
 hipError_t launch_cost(const TableArgs &a, hipStream_t st) {
     if (a.k == 0) return hipSuccess;
+    if (a.n > WIDE_N) {
+        hipLaunchKernelGGL(cost_wide_kernel, dim3(a.k), dim3(256), (size_t)2 * a.n * 4, st, a);
+        return report(hipGetLastError(), "kernel launch");
+    }
     const size_t sm = cost_smem(a.n);
     hipLaunchKernelGGL(cost_kernel, dim3(a.k), dim3(256), sm, st, a);
     return report(hipGetLastError(), "kernel launch");
@@ -333,6 +413,19 @@ hipError_t launch_cost(const TableArgs &a, hipStream_t st) {
 
 hipError_t launch_table(const TableArgs &a, hipStream_t st) {
     if (a.k == 0) return hipSuccess;
+    if (a.n > WIDE_N) {   // starts in groups of at most 65535 (the grid's y extent)
+        for (int j0 = 0; j0 < a.k; j0 += 65535) {
+            TableArgs b = a;
+            b.perms += (size_t)j0 * a.n;
+            b.table += (size_t)j0 * a.m;
+            b.k = a.k - j0 < 65535 ? a.k - j0 : 65535;
+            hipLaunchKernelGGL(table_wide_kernel, dim3(a.n - 1, b.k), dim3(TB_LANES), (size_t)2 * a.n * 4 + 4 * a.n,
+                               st, b);
+            const hipError_t e = report(hipGetLastError(), "kernel launch");
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     const size_t sm = table_smem(a.n);
     hipLaunchKernelGGL(table_kernel, dim3(a.k), dim3(TB_LANES), sm, st, a);
     return report(hipGetLastError(), "kernel launch");

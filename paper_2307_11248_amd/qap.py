@@ -24,7 +24,8 @@ QAP_E_RANGE = -3
 QAP_E_DEVICE = -4
 QAP_E_NOMEM = -5
 QAP_E_UNSUPPORTED = -6
-QAP_NMAX = 256
+QAP_NMAX = 512
+QAP_NMAX_BATCH = 256   # batched and served searches, and the frequency memory
 
 EXPORTS = [
     "qap_strerror", "qap_create", "qap_destroy", "qap_size", "qap_cost", "qap_cost_async", "qap_delta_table",
