@@ -6,7 +6,8 @@ resident in HBM: reset the working permutations from the starts, build every sta
 neighbourhood table, then run every search to completion in one persistent launch.
 The uneven batch (--workload c4: 512 instances, n from 20 to 150) runs every start of
 every instance in one launch of the batched kernel; its step is a captured HIP graph
-(reset, tables, searches) replayed once per step.
+(reset, tables, searches) replayed once per step.  --workload wide runs n = 512 (the
+wide streamed kernel, HBM-bound: its roofline is priced in bytes).
 
 Prints one JSON line (see the keys below).  --gpus N with N > 1 is refused: this build
 runs on one GPU.
@@ -39,12 +40,13 @@ BYTES_PER_EVAL = 8   # an int32 delta read and written per entry per step if kep
 # valid only for the kernel sources they were taken with.
 KERNEL_SOURCES = ["paper_2307_11248_amd/csrc/qap_search.hip", "paper_2307_11248_amd/csrc/qap_internal.h"]
 TRAFFIC = {
-    "c2_n64_dense_tabu": {"bytes": 2 * 728 * 1024 + 40 * 1024, "sources": "67d2d772d861139c"},
+    "c2_n64_dense_tabu": {"bytes": 2 * 728 * 1024 + 40 * 1024, "sources": "2e039f6219c1dec3"},
     # sum over the six kernels of one launch (tiles of 2 rows on 128, 256 and 512 lanes, of
     # 4 rows on 256, 512 and 768)
-    "c4_batched_uneven_tabu": {"bytes": int((2 * (1412.1 + 9547.7 + 16594.5 + 2286.7 + 48974.7 + 43354.9)
-                                             + (67.3 + 247.7 + 265.4 + 62.4 + 600.8 + 407.7)) * 1024),
-                               "sources": "67d2d772d861139c"},
+    "c4_batched_uneven_tabu": {"bytes": int((2 * (1385.5 + 9540.2 + 16608.0 + 2311.1 + 48978.0 + 43356.0)
+                                             + (64.6 + 247.7 + 265.4 + 65.1 + 600.7 + 408.1)) * 1024),
+                               "sources": "2e039f6219c1dec3"},
+    "n512_dense_tabu": {"bytes": int((2 * 457843902.6 + 299529125.3) * 1024), "sources": "2e039f6219c1dec3"},
 }
 
 
@@ -67,7 +69,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3-2opt", "c3-tabu", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3-2opt", "c3-tabu", "c4", "c5", "wide"])
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-start comparison")
@@ -91,6 +93,8 @@ def load_workload(name):
         return W.c3_euclid128_2opt()
     if name == "c4":
         return W.c4_batch()
+    if name == "wide":
+        return W.wide_dense512()
     return W.c3_euclid128_tabu()
 
 
@@ -438,13 +442,24 @@ def main():
     valu = VALU_PER_EVAL[algo] * search_evals / (search_ms / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": round(valu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s",
             "frac": round(valu / PEAK_VALU_TOPS, 4), "traffic": traffic_for(w.name),
-            "kernel": "search_kernel<%d,%s>" % (rows, "true" if algo == "tabu" else "false"),
+            "kernel": ("search_kernel<%d,%s>" % (rows, "true" if algo == "tabu" else "false") if rows > 0 else
+                       "stream_kernel<%s,false,%s>" % ("true" if algo == "tabu" else "false",
+                                                       "true" if n > qap.QAP_NMAX_BATCH else "false")),
             "kernel_ms": round(search_ms, 4),
             "ops_per_eval": VALU_PER_EVAL[algo],
             "hbm_equivalent": {"achieved": round(BYTES_PER_EVAL * search_evals / (search_ms / 1e3) / 1e9, 1),
                                "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                "frac": round(BYTES_PER_EVAL * search_evals / (search_ms / 1e3) / 1e9
                                              / PEAK_HBM_GBS, 4)}}
+    if rows < 0:
+        # streamed kernels keep the neighbourhood in global memory: every entry's delta is
+        # read and written each step, so HBM bounds them
+        hbm = BYTES_PER_EVAL * search_evals / (search_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(hbm / PEAK_HBM_GBS, 4), "traffic": roof["traffic"], "kernel": roof["kernel"],
+                "kernel_ms": roof["kernel_ms"], "bytes_per_eval": BYTES_PER_EVAL,
+                "alu_equivalent": {"achieved": round(valu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s",
+                                   "frac": round(valu / PEAK_VALU_TOPS, 4)}}
 
     out = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",

@@ -301,14 +301,10 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     uint8_t *const gbase = GGLOB ? a.gmat : sm;
     const int g_off = GGLOB ? 0 : S.g, gt_off = GGLOB ? (sym ? 0 : n * rs) : S.gt;
     uint8_t *Gm = gbase + g_off, *GmT = gbase + gt_off;
-    // wide kernel: G is written by some lanes and read by others through the vector
-    // caches, so the barriers that order those accesses also make the writes visible
-    // at device scope and drop stale lines before the reads
-    auto gsync = [&]() {
-        if constexpr (GGLOB) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if constexpr (GGLOB) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    };
+    // (wide kernel: G in global memory is written by some lanes and read by others; the
+    // waves of a workgroup share one compute unit's write-through vector L1, so the
+    // workgroup barriers order those accesses as they do in LDS.  Device-scope fences
+    // would write back and invalidate the whole L2 twice per iteration.)
     int *rpr = reinterpret_cast<int *>(sm + S.rpr);
     int *rps = reinterpret_cast<int *>(sm + S.rps);
     int *kc = reinterpret_cast<int *>(sm + S.kc);
@@ -376,7 +372,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             if (!sym) reinterpret_cast<unsigned *>(GmT)[i] = wgt;
         }
     }
-    gsync();
+    __syncthreads();
 
     // ---- RD_u = sum_k D[u][k] G[u][k], CD_u = sum_k D[k][u] G[k][u]; cost (Eq. 1) = sum RD_u
     long long part = 0;
@@ -589,7 +585,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         if (!STREAM) sel = active ? tile_min(dl, ut, u0, v0, it, aspiration()) : NO_MOVE;
         const long long kw = wave_min_pair<64>((int)(sel >> 32), (int)(sel & 0xffffffffLL));
         if (lane == 0) red[wid] = kw;
-        gsync();  // B1
+        __syncthreads();  // B1
         if (RESUME && s_chunk_end) break;   // uniform: every lane reads the same word
         // workgroup minimum of the 16 wave-minimum slots (slots past W hold the largest
         // key): lane i of every wave reads slot i, then the same two-pass DPP minimum
@@ -890,7 +886,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                     __hip_atomic_store(a.uloc + (size_t)ps_old * n + s, tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
-        gsync();  // B2
+        __syncthreads();  // B2
 
         // ---- C: G, G^T and p follow the move
         if (swap_lane) {

@@ -142,6 +142,16 @@ def c3_euclid128_tabu(k: int = 256, iters: int = 10000) -> Workload:
     return Workload("c3_n128_euclid_tabu", "tabu", [Instance(F, D, starts(rng, 128, k), 3, "c3")], iters)
 
 
+def wide_dense512(k: int = 256, iters: int = 2000) -> Workload:
+    """n=512 asymmetric dense (beyond the largest QAPLIB sizes): F, D uniform [0,99];
+    tabu, k starts x iters, the tenure range of the other tabu workloads."""
+    rng = rng_for(6)
+    n = 512
+    F = uniform_matrix(rng, n, 0, 99)
+    D = uniform_matrix(rng, n, 0, 99)
+    return Workload("n512_dense_tabu", "tabu", [Instance(F, D, starts(rng, n, k), 6, "wide")], iters)
+
+
 def c4_batch(m: int = 512, k: int = 8, iters: int = 5000, nmin: int = 20, nmax: int = 150) -> Workload:
     """m instances, n uniform in [nmin, nmax]; even index dense uniform, odd index sparse
     flow (80% zero) with grid-Manhattan distances; tabu with k starts each."""

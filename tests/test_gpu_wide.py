@@ -2,8 +2,8 @@
 
 Beyond n = 256 the permuted flows G = F[p][p] and G^T no longer fit in LDS beside the
 rest of a search, so the wide kernel keeps them, like D and D^T, in global scratch (the
-move exchanges two of their rows and columns in place, between barriers that also order
-those accesses at device scope), runs up to four (index, family) tasks per lane, and the
+move exchanges two of their rows and columns in place, between the workgroup barriers),
+runs up to four (index, family) tasks per lane, and the
 starting neighbourhood is evaluated entry by entry from Eq. (2).  Every case is compared
 bit for bit with the oracle.  The batched and served paths and the frequency memory stop
 at n = 256 and say so.
