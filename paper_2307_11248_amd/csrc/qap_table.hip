@@ -159,12 +159,13 @@ __global__ void __launch_bounds__(256) cost_wide_kernel(TableArgs a) {
     }
 }
 
-// Neighbourhood row r of start `job` (block (r, job)): lane t evaluates the exchange of
-// locations r and s = r + 1 + t by Eq. (2), with G = F[p][p]:
+// Neighbourhood row r of start `job` (block (r, job)): wave w evaluates the exchanges of
+// locations r and s = r + 1 + w, r + 1 + w + W, ... by Eq. (2), with G = F[p][p]:
 //   delta(r, s) = sum_{k != r, s} (G_sk - G_rk)(D_rk - D_sk) + (G_ks - G_kr)(D_kr - D_ks)
-//               + (G_ss - G_rr)(D_rr - D_ss) + (G_sr - G_rs)(D_rs - D_sr).
-// Row r's bytes (G_rk, G_kr, D_rk, D_kr) are staged in LDS; row s's are read from F, F^T,
-// D and D^T in global memory.
+//               + (G_ss - G_rr)(D_rr - D_ss) + (G_sr - G_rs)(D_rs - D_sr),
+// its 64 lanes splitting k (so each row of F, F^T, D, D^T at s is read by one wave, in
+// one contiguous stretch) and summing their parts at the end.  Row r's bytes (G_rk, G_kr,
+// D_rk, D_kr) are staged in LDS.
 __global__ void __launch_bounds__(TB_LANES) table_wide_kernel(TableArgs a) {
     extern __shared__ __align__(16) unsigned char sm[];
     __shared__ int bad;
@@ -187,20 +188,23 @@ __global__ void __launch_bounds__(TB_LANES) table_wide_kernel(TableArgs a) {
         dtr[k] = DT[(size_t)r * rs + k];
     }
     __syncthreads();
-    if (s >= n) return;
-    const int ps = perm[s];
-    const uint8_t *Fs = F + (size_t)ps * rs, *FTs = FT + (size_t)ps * rs, *Ds = D + (size_t)s * rs,
-                  *DTs = DT + (size_t)s * rs;
-    int acc = 0;
-    for (int k = 0; k < n; ++k) {
-        const int pk = perm[k];
-        const int term = ((int)Fs[pk] - (int)gr[k]) * ((int)dr[k] - (int)Ds[k]) +
-                         ((int)FTs[pk] - (int)gtr[k]) * ((int)dtr[k] - (int)DTs[k]);
-        acc += (k == r || k == s) ? 0 : term;
+    const int lane = t & 63, W = blockDim.x >> 6;
+    for (int sw = r + 1 + (t >> 6); sw < n; sw += W) {
+        const int ps = perm[sw];
+        const uint8_t *Fs = F + (size_t)ps * rs, *FTs = FT + (size_t)ps * rs, *Ds = D + (size_t)sw * rs,
+                      *DTs = DT + (size_t)sw * rs;
+        int acc = 0;
+        for (int k = lane; k < n; k += 64) {
+            const int pk = perm[k];
+            const int term = ((int)Fs[pk] - (int)gr[k]) * ((int)dr[k] - (int)Ds[k]) +
+                             ((int)FTs[pk] - (int)gtr[k]) * ((int)dtr[k] - (int)DTs[k]);
+            acc += (k == r || k == sw) ? 0 : term;
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0)
+            out[pidx(n, r, sw)] = acc + ((int)Fs[ps] - (int)gr[r]) * ((int)dr[r] - (int)Ds[sw]) +
+                                  ((int)Fs[pr] - (int)gr[sw]) * ((int)dr[sw] - (int)Ds[r]);
     }
-    acc += ((int)Fs[ps] - (int)gr[r]) * ((int)dr[r] - (int)Ds[s]) +
-           ((int)Fs[pr] - (int)gr[s]) * ((int)dr[s] - (int)Ds[r]);
-    out[pidx(n, r, s)] = acc;
 }
 
 // (I, J), I <= J, of tile pair q in row-major order over nt x nt tiles
