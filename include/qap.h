@@ -41,8 +41,8 @@ extern "C" {
 #endif
 
 #define QAP_NMAX 512
-/* Largest n of the batched (qap_batch_*) and served (qap_server_*) searches, and of the
- * frequency memory (qap_tabu_freq_async); above it those return QAP_E_UNSUPPORTED. */
+/* Largest n of the batched (qap_batch_*) and served (qap_server_*) searches; above it
+ * those return QAP_E_UNSUPPORTED. */
 #define QAP_NMAX_BATCH 256
 
 enum {
@@ -69,7 +69,7 @@ const char *qap_strerror(int code);
  * (n <= 176 in the batched kernels), and above that run the streamed kernel
  * (neighbourhood in global memory, only G = F[p][p] in LDS).  For QAP_NMAX_BATCH < n <=
  * QAP_NMAX the single-instance entry points (cost, neighbourhood table, qap_2opt*,
- * qap_tabu*, except qap_tabu_freq_async) run the wide streamed kernel, which keeps G and
+ * qap_tabu*) run the wide streamed kernel, which keeps G and
  * G^T in global memory too (2 n RS bytes of stream-ordered scratch per search, RS = n
  * rounded up to 32, plus 16), and the neighbourhood table is evaluated entry by entry
  * from Eq. (2).  QAP_E_UNSUPPORTED is left for a device whose LDS is smaller than the

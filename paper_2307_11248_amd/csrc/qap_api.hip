@@ -600,7 +600,6 @@ int qap_tabu_freq_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters
     if (!tabu_args_ok(h, d_perms, k, iters, lo, hi, d_best) || (k > 0 && !d_freq) || div < 0 || attr < 0 ||
         attr > 2)
         return QAP_E_INVALID;
-    if (h->n > WIDE_N) return QAP_E_UNSUPPORTED;   // the wide kernel keeps no frequency memory
     return run_search(h, 0, d_perms, k, iters, lo, hi, seed, start_base, d_best, d_done, (hipStream_t)stream,
                       false, d_freq, div, attr);
 }

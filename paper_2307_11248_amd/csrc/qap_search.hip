@@ -281,7 +281,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     __shared__ long long s_red2[FREQ ? 16 : 1];   // diversification: wave minima of (count, key)
     __shared__ int s_dd;                          // diversification: delta of the chosen move
     // unit marking: the iteration until which the unit at each location is marked
-    __shared__ int s_mark[FREQ ? 264 : 1];
+    __shared__ int s_mark[FREQ ? (GGLOB ? WIDE_MAXN + 8 : 264) : 1];
     const int n = a.n, rs = row_stride(n), L = blockDim.x, t = threadIdx.x;
     const int nb16 = (n + 15) & ~15;   // bytes of a row the dot products read (zero past n)
     const int nb32 = (n + 31) & ~31;   // the same, for the 32-byte steps of the row recomputation
@@ -1290,7 +1290,7 @@ __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     it.tile_u = it.tile_d + a.tile_stride / 2;
     if constexpr (WIDE) {
         it.gmat = a.gwork + (size_t)blockIdx.x * a.gstride;
-        search_body<STREAM_ROWS, TABU, WIDE_MAXT, false, true, false, false, true>(it, sm);
+        search_body<STREAM_ROWS, TABU, WIDE_MAXT, false, true, false, FREQ, true>(it, sm);
     } else {
         search_body<STREAM_ROWS, TABU, 1024 / BATCH_LANES, false, true, false, FREQ>(it, sm);
     }
@@ -1421,9 +1421,11 @@ int stream_shape_ok(int n, int sym, size_t max_smem) {
 hipError_t launch_stream(bool tabu, const SearchArgs &a, int grid, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
     const size_t smem = stream_smem_bytes(a.n, a.sym);
-    if (a.n > WIDE_N) {   // G in a.gwork; no frequency memory
-        if (a.freq || !a.gwork) return hipErrorInvalidValue;
-        if (tabu)
+    if (a.n > WIDE_N) {   // G in a.gwork
+        if (!a.gwork) return hipErrorInvalidValue;
+        if (tabu && a.freq)
+            hipLaunchKernelGGL((stream_kernel<true, true, true>), dim3(grid), dim3(BATCH_LANES), smem, st, a);
+        else if (tabu)
             hipLaunchKernelGGL((stream_kernel<true, false, true>), dim3(grid), dim3(BATCH_LANES), smem, st, a);
         else
             hipLaunchKernelGGL((stream_kernel<false, false, true>), dim3(grid), dim3(BATCH_LANES), smem, st, a);

@@ -25,7 +25,7 @@ QAP_E_DEVICE = -4
 QAP_E_NOMEM = -5
 QAP_E_UNSUPPORTED = -6
 QAP_NMAX = 512
-QAP_NMAX_BATCH = 256   # batched and served searches, and the frequency memory
+QAP_NMAX_BATCH = 256   # batched and served searches
 
 EXPORTS = [
     "qap_strerror", "qap_create", "qap_destroy", "qap_size", "qap_cost", "qap_cost_async", "qap_delta_table",

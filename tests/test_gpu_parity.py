@@ -307,7 +307,7 @@ def test_tabu_config3_full_size_sampled():
 
 
 @pytest.mark.parametrize("n,sym,rows", [(12, False, 0), (40, True, 1), (64, False, 2), (130, False, 4),
-                                        (200, False, -8)])
+                                        (200, False, -8), (300, False, -8)])
 def test_tabu_frequency_memory_counts_the_oracle_moves(n, sym, rows):
     """The frequency memory (Sec. 4.3, lower triangle of Tabuarr) counts, per pair of
     locations, the exchanges the search made: it must equal the count of the oracle's
@@ -341,7 +341,8 @@ def test_tabu_frequency_memory_counts_the_oracle_moves(n, sym, rows):
 
 @pytest.mark.parametrize("n,sym,rows,div", [(12, False, 0, 3), (40, True, 1, 6), (64, False, 2, 10),
                                             (64, False, 1, 4), (101, True, 4, 8), (130, False, 8, 12),
-                                            (150, False, 16, 9), (200, False, -8, 7), (230, True, -8, 11)])
+                                            (150, False, 16, 9), (200, False, -8, 7), (230, True, -8, 11),
+                                            (300, False, -8, 7), (420, True, -8, 3)])
 def test_tabu_frequency_diversification_equals_oracle(n, sym, rows, div):
     """With div > 0 the frequency memory drives a diversification move (the least
     exchanged non-tabu pair after more than div iterations without a new best): best
@@ -376,7 +377,7 @@ def test_tabu_frequency_diversification_equals_oracle(n, sym, rows, div):
 
 @pytest.mark.parametrize("n,sym,rows,div", [(12, False, 0, 0), (40, True, 1, 0), (64, False, 2, 6),
                                             (101, True, 4, 0), (130, False, 8, 9), (150, False, 16, 0),
-                                            (200, False, -8, 0), (210, True, -8, 8)])
+                                            (200, False, -8, 0), (210, True, -8, 8), (333, False, -8, 6)])
 def test_tabu_unit_marking_equals_oracle(n, sym, rows, div):
     """The unit-marking tabu attribute (the two units moved are marked for the tenure; a
     move is tabu while either of its units is marked), alone and with the diversification
@@ -411,7 +412,7 @@ def test_tabu_unit_marking_equals_oracle(n, sym, rows, div):
 
 @pytest.mark.parametrize("n,sym,rows,div", [(12, False, 0, 0), (40, True, 1, 0), (64, False, 2, 7),
                                             (101, True, 4, 0), (130, False, 8, 10), (150, False, 16, 0),
-                                            (200, False, -8, 0), (190, False, -8, 9)])
+                                            (200, False, -8, 0), (190, False, -8, 9), (300, False, -8, 3)])
 def test_tabu_unit_location_equals_oracle(n, sym, rows, div):
     """The unit-location tabu attribute (a move is tabu when both units would return to a
     location they left within their tenure), alone and with the diversification move,
