@@ -40,13 +40,13 @@ BYTES_PER_EVAL = 8   # an int32 delta read and written per entry per step if kep
 # valid only for the kernel sources they were taken with.
 KERNEL_SOURCES = ["paper_2307_11248_amd/csrc/qap_search.hip", "paper_2307_11248_amd/csrc/qap_internal.h"]
 TRAFFIC = {
-    "c2_n64_dense_tabu": {"bytes": 2 * 728 * 1024 + 40 * 1024, "sources": "2e039f6219c1dec3"},
+    "c2_n64_dense_tabu": {"bytes": 2 * 726 * 1024 + 40 * 1024, "sources": "53a1c7390546758b"},
     # sum over the six kernels of one launch (tiles of 2 rows on 128, 256 and 512 lanes, of
     # 4 rows on 256, 512 and 768)
-    "c4_batched_uneven_tabu": {"bytes": int((2 * (1385.5 + 9540.2 + 16608.0 + 2311.1 + 48978.0 + 43356.0)
-                                             + (64.6 + 247.7 + 265.4 + 65.1 + 600.7 + 408.1)) * 1024),
-                               "sources": "2e039f6219c1dec3"},
-    "n512_dense_tabu": {"bytes": int((2 * 457843902.6 + 299529125.3) * 1024), "sources": "2e039f6219c1dec3"},
+    "c4_batched_uneven_tabu": {"bytes": int((2 * (1062.9 + 9547.4 + 16606.0 + 2637.2 + 48965.1 + 43353.5)
+                                             + (50.0 + 247.7 + 265.4 + 79.7 + 600.4 + 408.0)) * 1024),
+                               "sources": "53a1c7390546758b"},
+    "n512_dense_tabu": {"bytes": int((2 * 457807363.4 + 299529572.0) * 1024), "sources": "53a1c7390546758b"},
 }
 
 
