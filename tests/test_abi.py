@@ -64,3 +64,10 @@ def test_null_handle_calls():
     assert L.qap_destroy(None) == 0
     assert L.qap_size(None) == qap.QAP_E_INVALID
     assert L.qap_set_tile_rows(None, 0, 4) == qap.QAP_E_INVALID
+
+
+def test_binding_size_limits_match_the_header():
+    txt = open(os.path.join(ROOT, "include", "qap.h")).read()
+    defs = dict(re.findall(r"#define (QAP_NMAX\w*) (\d+)", txt))
+    assert int(defs["QAP_NMAX"]) == qap.QAP_NMAX == 512
+    assert int(defs["QAP_NMAX_BATCH"]) == qap.QAP_NMAX_BATCH == 256

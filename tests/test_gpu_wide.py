@@ -122,3 +122,37 @@ def test_wide_paths_that_stop_at_256_say_so():
         with pytest.raises(qap.QapError) as ei:
             s.footprint(n)
         assert ei.value.code == qap.QAP_E_UNSUPPORTED
+
+
+def test_wide_table_taking_entry_points_and_full_descent():
+    """The search kernels alone on a table built by qap_delta_table_async (the bench's
+    step), against the entry points that build their own; and 2opt run to the local
+    optimum (no move cap) against the oracle."""
+    import torch
+    n = 300
+    rng = np.random.default_rng(9500)
+    F, D = W.random_instance(rng, n, 0, 99, symmetric=True)
+    perms = W.starts(rng, n, 2)
+    lo, hi = W.tabu_tenure_range(n)
+    iters = 150
+    note("wide table-taking entry points n=300")
+    with qap.Handle(F, D) as h:
+        p, c, d = h.tabu(perms, iters, lo, hi, 17)
+        q, qc, qs = h.two_opt(perms)
+        m = n * (n - 1) // 2
+        dp = torch.from_numpy(perms).cuda()
+        dt = torch.empty((2, m), dtype=torch.int32, device="cuda")
+        db = torch.zeros(2, dtype=torch.int64, device="cuda")
+        dd = torch.zeros(2, dtype=torch.int32, device="cuda")
+        h.delta_table_async(dp, dt)
+        h.tabu_with_table_async(dp, dt, iters, lo, hi, 17, db, dd)
+        torch.cuda.synchronize()
+        assert (dp.cpu().numpy() == p).all() and (db.cpu().numpy() == c).all() and (dd.cpu().numpy() == d).all()
+        dp2 = torch.from_numpy(perms).cuda()
+        h.delta_table_async(dp2, dt)
+        h.two_opt_with_table_async(dp2, dt, db, dd)
+        torch.cuda.synchronize()
+        assert (dp2.cpu().numpy() == q).all() and (db.cpu().numpy() == qc).all() and (dd.cpu().numpy() == qs).all()
+    res = pmap(lambda j: oracle.two_opt(F, D, perms[j]), range(2))
+    for j, r in enumerate(res):
+        assert (q[j] == r[0]).all() and qc[j] == r[1] and qs[j] == r[2], j
