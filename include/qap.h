@@ -47,7 +47,8 @@ extern "C" {
 
 enum {
     QAP_OK = 0,
-    QAP_E_INVALID = -1,   /* null pointer, n < 2, n > QAP_NMAX, k < 0, iters < 0, lo < 0, lo > hi */
+    QAP_E_INVALID = -1,   /* null pointer, n < 2, n > QAP_NMAX, k < 0, iters < 0, lo < 0, lo > hi,
+                             iters + hi >= 2^31 - 1 (the tabu-until iteration must fit int32) */
     QAP_E_NOT_PERM = -2,  /* a row of perms is not a permutation of 0..n-1 */
     QAP_E_RANGE = -3,     /* a flow or distance lies outside [0, 255] */
     QAP_E_DEVICE = -4,    /* a HIP call failed */
@@ -111,7 +112,8 @@ int qap_delta_table_async(qap_handle h, const int32_t *d_perms, int32_t k, int32
  * 2opt (Secs. 4.1-4.2), read as best improvement: from each start, repeatedly take the
  * move with the lowest delta (lowest idx among equal deltas) while that delta is
  * negative.  The search stops at a local optimum, or after max_iters moves when
- * max_iters > 0 (2^20 moves when max_iters <= 0).
+ * max_iters > 0 (max_iters <= 0: no cap; the integer cost strictly decreases, so the
+ * search always ends).
  *   perms     host int32[k][n]: the starts on entry, the final permutations on return.
  *   costs_out host int64[k]: their costs.
  *   steps_out host int32[k] or NULL: moves made by each start.

@@ -51,8 +51,12 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            build(force=False)
-            lib = ctypes.CDLL(_LIB_PATH)
+            # QAP_ORACLE_LIB names another build of qap_oracle.c (the sanitizer-instrumented
+            # one of tests/test_oracle_sanitized.py); by default the library is built here.
+            path = os.environ.get("QAP_ORACLE_LIB")
+            if not path:
+                path = build(force=False)
+            lib = ctypes.CDLL(path)
             lib.orc_cost.restype = ctypes.c_int64
             lib.orc_cost.argtypes = [ctypes.c_int, _i32p, _i32p, _i32p]
             lib.orc_delta.restype = ctypes.c_int64

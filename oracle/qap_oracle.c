@@ -203,7 +203,7 @@ ORC_EXPORT void orc_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_i
 ORC_EXPORT int32_t orc_tenure(uint64_t seed, uint64_t it, uint64_t start, int32_t lo, int32_t hi) {
     uint64_t ctr[4] = {it, start, 0, 0}, key[2] = {seed, 0}, x[4];
     orc_philox4x64_10(ctr, key, x);
-    uint64_t span = (uint64_t)(int64_t)(hi - lo + 1);
+    uint64_t span = (uint64_t)((int64_t)hi - lo + 1);
     return lo + (int32_t)(((x[0] >> 32) * span) >> 32);
 }
 

@@ -584,7 +584,7 @@ int qap_2opt_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t max_iters,
 
 static int tabu_args_ok(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo, int32_t hi,
                         int64_t *d_best) {
-    return h && k >= 0 && iters >= 0 && lo >= 0 && lo <= hi && (k == 0 || (d_perms && d_best));
+    return h && k >= 0 && tenure_args_ok(iters, lo, hi) && (k == 0 || (d_perms && d_best));
 }
 
 int qap_tabu_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo, int32_t hi,
@@ -701,7 +701,7 @@ int qap_2opt(qap_handle h, int32_t *perms, int32_t k, int32_t max_iters, int64_t
 
 int qap_tabu(qap_handle h, int32_t *perms, int32_t k, int32_t iters, int32_t lo, int32_t hi, uint64_t seed,
              int64_t *best_costs_out, int32_t *iters_done_out) {
-    if (!h || k < 0 || iters < 0 || lo < 0 || lo > hi || (k > 0 && (!perms || !best_costs_out)))
+    if (!h || k < 0 || !tenure_args_ok(iters, lo, hi) || (k > 0 && (!perms || !best_costs_out)))
         return QAP_E_INVALID;
     return host_search(h, 0, perms, k, iters, lo, hi, seed, best_costs_out, iters_done_out);
 }
@@ -720,7 +720,7 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
     size_t gsmem[BV_COUNT] = {}, tsmem = 0;
     for (int i = 0; i < m; ++i) {
         qap_ctx *h = hs[i];
-        if (!h || k_per[i] < 0 || lo_per[i] < 0 || lo_per[i] > hi_per[i]) return QAP_E_INVALID;
+        if (!h || k_per[i] < 0 || !tenure_args_ok(iters, lo_per[i], hi_per[i])) return QAP_E_INVALID;
         const int ri = rows_per && rows_per[i] != 0 ? rows_index(rows_per[i]) : batch_shape(h);
         if (ri < 0 || !batch_fits(h, ri)) return QAP_E_UNSUPPORTED;
         const bool streamed = ri == kStream;

@@ -27,4 +27,10 @@ int dev_err_at(hipError_t e, const char *where);
 // Whether each of the k rows of perms is a permutation of 0..n-1.
 bool check_perms(const int32_t *perms, int k, int n);
 
+// Whether a tabu run of `iters` iterations with tenures in [lo, hi] is valid: the
+// iteration until which a move stays tabu, it + t <= iters + hi, must fit in int32.
+inline bool tenure_args_ok(int32_t iters, int32_t lo, int32_t hi) {
+    return iters >= 0 && lo >= 0 && lo <= hi && (int64_t)iters + hi < INT32_MAX;
+}
+
 }  // namespace qaph

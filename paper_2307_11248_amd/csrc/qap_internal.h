@@ -19,9 +19,10 @@ constexpr int TILE_COLS = 4;   // columns of the register tile held by one lane
 // Above this n, G = F[p][p] and G^T no longer fit in LDS beside the search's other
 // arrays: the wide streamed kernel keeps them, like D and D^T, in global memory.
 constexpr int WIDE_N = 256;
-// Bound on the moves of one 2opt search run to a local optimum (the cost strictly
-// decreases, so this only bounds a run on inconsistent data).
-constexpr int TWO_OPT_MAX_MOVES = 1 << 20;
+// Moves of one 2opt search run to a local optimum (max_iters <= 0): unbounded in effect.
+// The integer cost strictly decreases with every move, so the search always ends at a
+// local optimum; the bound only keeps the move counter inside int32.
+constexpr int TWO_OPT_MAX_MOVES = INT32_MAX;
 
 // Rows are padded to RS bytes, an odd multiple of 16 (16 more than n rounded up to 32):
 // every row starts 16-byte aligned, 16 consecutive rows start in 16 different groups of

@@ -153,7 +153,7 @@ __device__ inline unsigned long long philox4x64_10_w0(unsigned long long c0, uns
 __device__ inline int draw_tenure(unsigned long long seed, long long it, long long start, int lo, int hi) {
     const unsigned long long x = philox4x64_10_w0((unsigned long long)it, (unsigned long long)start, 0, 0,
                                                   seed, 0);
-    const unsigned long long span = (unsigned long long)(long long)(hi - lo + 1);
+    const unsigned long long span = (unsigned long long)((long long)hi - lo + 1);
     return lo + (int)(((x >> 32) * span) >> 32);
 }
 

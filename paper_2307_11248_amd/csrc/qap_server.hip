@@ -291,7 +291,8 @@ int64_t qap_server_footprint(qap_server_handle s, int32_t n, int32_t sym) {
 
 int qap_server_submit(qap_server_handle s, const int32_t *F, const int32_t *D, int32_t n, const int32_t *start,
                       int32_t iters, int32_t lo, int32_t hi, uint64_t seed, int64_t *ticket_out) {
-    if (!s || !F || !D || !start || !ticket_out || n < 2 || n > QAP_NMAX || iters < 0 || lo < 0 || lo > hi)
+    if (!s || !F || !D || !start || !ticket_out || n < 2 || n > QAP_NMAX ||
+        !tenure_args_ok(iters, lo, hi))
         return QAP_E_INVALID;
     if (!check_perms(start, 1, n)) return QAP_E_NOT_PERM;
     Request *r = new (std::nothrow) Request;

@@ -417,3 +417,101 @@ def test_tabu_unit_location_matches_resimulation(seed, n, lo, hi, iters, div):
     assert [tuple(int(x) for x in row) for row in tr] == em
     pair = oracle.tabu_freq(F, D, p0, iters, lo, hi, seed + 5, start=seed, div=div, trace_cap=iters)
     assert not np.array_equal(pair[4], tr)
+
+
+def py_two_opt(F, D, p0, rule="best"):
+    """Independent numpy re-simulation of 2opt on tiny inputs: every neighbourhood by full
+    recomputation of Eq. (1).  rule "best": the move of lowest (delta, packed index), stop
+    when that delta is >= 0 (the reading of Sec. 4.1 the oracle follows).  "last_tie" and
+    "first" are two plausible misreadings (ties to the highest index; the first improving
+    move in packed order), kept only to show that the inputs below tell them apart."""
+    n = len(p0)
+    p = np.array(p0).copy()
+    cur = np_cost(F, D, p)
+    moves = []
+    while True:
+        deltas = np_all_swap_deltas(F, D, p)
+        if rule == "best":
+            k = int(np.argmin(deltas))                       # numpy: first occurrence
+        elif rule == "last_tie":
+            k = len(deltas) - 1 - int(np.argmin(deltas[::-1]))
+        else:
+            neg = np.flatnonzero(deltas < 0)
+            k = int(neg[0]) if len(neg) else int(np.argmin(deltas))
+        d = int(deltas[k])
+        if d >= 0:
+            break
+        r = next(r for r in range(n) if r * n - r * (r + 1) // 2 + (n - r - 1) > k)
+        s = k - (r * n - r * (r + 1) // 2) + r + 1
+        p[r], p[s] = p[s], p[r]
+        cur += d
+        moves.append((r, s, d, cur))
+    return p, cur, moves
+
+
+def test_two_opt_tie_fixtures_by_hand():
+    """Hand-worked n = 3 cases: a tie at the minimum (lowest packed index wins) and a first
+    improving move that is not the best one."""
+    g = json.load(open(os.path.join(GOLD, "two_opt_ties_n3.json")))
+    D = np.array(g["D"])
+    for case in g["cases"]:
+        F, p = np.array(case["F"]), np.array(case["perm"])
+        assert oracle.cost(F, D, p) == case["cost"]
+        assert list(oracle.delta_table(F, D, p)) == case["deltas_packed"]
+        for mode in (0, 1):
+            q, c, steps, tr = oracle.two_opt(F, D, p, mode=mode, trace_cap=8)
+            assert list(q) == case["two_opt_perm"] and c == case["two_opt_cost"]
+            assert steps == len(case["moves"])
+            assert [list(map(int, row)) for row in tr] == case["moves"]
+    # the misreadings give what the fixture says they give, which the oracle does not
+    tie, first = g["cases"]
+    q, _, _ = py_two_opt(np.array(tie["F"]), D, tie["perm"], rule="last_tie")
+    assert list(q) == tie["ties_to_highest_index_perm"] != tie["two_opt_perm"]
+    q, _, mv = py_two_opt(np.array(first["F"]), D, first["perm"], rule="first")
+    assert [list(x) for x in mv] == first["first_improvement_moves"]
+    assert list(q) == first["first_improvement_perm"] != first["two_opt_perm"]
+
+
+def _tie_heavy_instances():
+    """Inputs full of equal deltas: 0/1 flows and distances, and grid instances like the
+    n = 12 workload (flows in [0, 9], Manhattan distances)."""
+    rng = np.random.default_rng(2023)
+    out = []
+    for n in (5, 6, 7, 8):
+        F = rng.integers(0, 2, size=(n, n)).astype(np.int32)
+        Dm = rng.integers(0, 2, size=(n, n)).astype(np.int32)
+        np.fill_diagonal(F, 0)
+        np.fill_diagonal(Dm, 0)
+        out.append((F, Dm))
+    for n in (6, 9, 12):
+        F = W.symmetrise_upper(W.uniform_matrix(rng, n, 0, 9))
+        out.append((F, W.grid_manhattan(n)))
+    return out, rng
+
+
+def test_two_opt_move_choice_matches_resimulation():
+    """Every move of orc_2opt (both modes) is the lowest (delta, packed index) of the
+    current neighbourhood, recomputed from Eq. (1), on tie-heavy inputs; and on the same
+    inputs the two misreadings above give different trajectories, so this pin would fail
+    for either of them."""
+    insts, rng = _tie_heavy_instances()
+    differs = {"last_tie": 0, "first": 0}
+    ties_seen = 0
+    for F, Dm in insts:
+        n = F.shape[0]
+        for _ in range(6):
+            p0 = rng.permutation(n).astype(np.int32)
+            ep, ec, emoves = py_two_opt(F, Dm, p0)
+            for mode in (0, 1):
+                q, c, steps, tr = oracle.two_opt(F, Dm, p0, mode=mode, trace_cap=4096)
+                assert [tuple(map(int, row)) for row in tr] == emoves
+                assert list(q) == list(ep) and c == ec and steps == len(emoves)
+            p = p0.copy()
+            for r, s, d, _ in emoves:
+                deltas = np_all_swap_deltas(F, Dm, p)
+                ties_seen += int((deltas == d).sum() > 1)
+                p[r], p[s] = p[s], p[r]
+            for rule in differs:
+                differs[rule] += int(py_two_opt(F, Dm, p0, rule=rule)[2] != emoves)
+    assert ties_seen > 0
+    assert differs["last_tie"] > 0 and differs["first"] > 0
