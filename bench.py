@@ -4,10 +4,15 @@
 A step is one pass of the whole hot path over one batch of starts that are already
 resident in HBM: reset the working permutations from the starts, build every start's
 neighbourhood table, then run every search to completion in one persistent launch.
-The uneven batch (--workload c4: 512 instances, n from 20 to 150) runs every start of
-every instance in one launch of the batched kernel; its step is a captured HIP graph
-(reset, tables, searches) replayed once per step.  --workload wide runs n = 512 (the
-wide streamed kernel, HBM-bound: its roofline is priced in bytes).
+The default workload is the uneven batch (--workload c4: 512 instances, n from 20 to
+150, 8 starts each, 5000 tabu iterations): every start of every instance runs in one
+launch of the batched kernels, and the step is a captured HIP graph (reset, tables,
+searches) replayed once per step.  Other workloads: c1, c2, c3-2opt, c3-tabu (single
+instances), c5 (the serving stream), wide (n = 512, the wide streamed kernel).
+
+The roofline is priced in HBM bytes: a swap-delta eval (one neighbourhood entry made
+current for one step of one search) is an int32 read and write, 8 bytes, against the
+8 TB/s of MI355X's HBM3E; the VALU rate of the same evals is reported beside it.
 
 Prints one JSON line (see the keys below).  --gpus N with N > 1 is refused: this build
 runs on one GPU.
@@ -50,6 +55,18 @@ TRAFFIC = {
 }
 
 
+def roofline(search_evals, kernel_ms, kernel, traffic, ops_per_eval):
+    """HBM roofline of the search phase at 8 B per eval, with the VALU rate beside it."""
+    sec = kernel_ms / 1e3
+    hbm = BYTES_PER_EVAL * search_evals / sec / 1e9
+    valu = ops_per_eval * search_evals / sec / 1e12
+    return {"bound": "hbm", "achieved": round(hbm, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(hbm / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": kernel,
+            "kernel_ms": round(kernel_ms, 4), "bytes_per_eval": BYTES_PER_EVAL, "evals_per_launch": search_evals,
+            "alu_equivalent": {"achieved": round(valu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s",
+                               "frac": round(valu / PEAK_VALU_TOPS, 4), "ops_per_eval": ops_per_eval}}
+
+
 def kernel_digest():
     import hashlib
     h = hashlib.sha1()
@@ -69,11 +86,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3-2opt", "c3-tabu", "c4", "c5", "wide"])
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3-2opt", "c3-tabu", "c4", "c5", "wide"])
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-start comparison")
-    ap.add_argument("--cpu-starts", type=int, default=32)
+    ap.add_argument("--cpu-starts", type=int, default=32,
+                    help="single instances: oracle starts; uneven batch: at most this many instances "
+                         "per oracle leg x 16 (one start each)")
+    ap.add_argument("--plain-instances", type=int, default=32,
+                    help="uneven batch: instances whose starts are also run one launch per start")
     ap.add_argument("--no-tune", action="store_true", help="uneven batch: the default tile shape for every n")
     ap.add_argument("--chunk-ms", type=float, default=2.0, help="serving: device time per chunk of a search")
     ap.add_argument("--requests", type=int, default=2000, help="serving: requests in the arrival stream")
@@ -224,25 +245,47 @@ def run_batch(args, w):
     evals_step = int((ms * (moves + 1)).sum())
     search_evals = int((ms * moves).sum())
     value = evals_step / (ms_step / 1e3)
-    valu = VALU_PER_EVAL["tabu"] * search_evals / (search_ms / 1e3) / 1e12
-    roof = {"bound": "alu", "achieved": round(valu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s",
-            "frac": round(valu / PEAK_VALU_TOPS, 4), "traffic": traffic_for(w.name), "kernel": "batch_kernel",
-            "kernel_ms": round(search_ms, 4), "ops_per_eval": VALU_PER_EVAL["tabu"],
-            "hbm_equivalent": {"achieved": round(BYTES_PER_EVAL * search_evals / (search_ms / 1e3) / 1e9, 1),
-                               "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                               "frac": round(BYTES_PER_EVAL * search_evals / (search_ms / 1e3) / 1e9
-                                             / PEAK_HBM_GBS, 4)}}
+    # the search phase: one batch_group_kernel dispatch per tile-shape variant, forked onto
+    # side streams and joined back; the events bracket the fork and the join
+    roof = roofline(search_evals, search_ms, "batch_group_kernel (search phase: %d concurrent variant dispatches)"
+                    % b.groups(), traffic_for(w.name), VALU_PER_EVAL["tabu"])
     ns = [I.n for I in insts]
     out = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int32", "data": "synthetic",
            "config": {"workload": w.name, "instances": m, "n_range": [min(ns), max(ns)], "starts_per_instance": k,
                       "iters": w.iters, "tenure": "[0.9n, 1.1n]", "graph": True,
-                      "tile_rows_per_instance": rows_hist, "tuning_s": tune_s},
+                      "tile_rows_per_instance": rows_hist, "tuning_s": tune_s,
+                      "searches_per_variant": dict(zip(["r2_512", "r4_512", "r8_512", "stream_512", "r2_128",
+                                                        "r2_256", "r4_256", "r4_768"],
+                                                       map(int, b.groups(counts=True)[1])))},
            "solves_per_s": m * k / (ms_step / 1e3), "table_kernel_ms": table_ms, "roofline": roof}
 
     if not args.no_plain:
-        # the same searches launched per instance (one launch of k blocks each)
+        batched_solves = m * k / (ms_step / 1e3)
+        # (1) the plain path: one launch per start, back to back on one stream, on the
+        #     starts of a sample of instances spread over the batch (the whole batch
+        #     would take about a minute this way)
+        pi = list(range(0, m, max(1, m // args.plain_instances)))[:args.plain_instances]
+        pw = starts.clone()
+        pb = torch.empty(m * k, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for t in pi:
+                I = insts[t]
+                hs[t].tabu_async(pw[off[t]:off[t + 1]].view(k, I.n), w.iters, lo[t], hi[t], I.seed,
+                                 pb[t * k:(t + 1) * k], None, plain=True, stream=stream)
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t0
+        pw_h, pb_h = pw.cpu().numpy(), pb.cpu().numpy()
+        same = all((pb_h[t * k:(t + 1) * k] == gpu_best[t * k:(t + 1) * k]).all()
+                   and (pw_h[off[t]:off[t + 1]] == gpu_perm[off[t]:off[t + 1]]).all() for t in pi)
+        out["plain"] = {"solves_per_s": len(pi) * k / pdt, "speedup_batched_vs_plain": batched_solves / (len(pi) * k / pdt),
+                        "identical_costs": bool(same),
+                        "sample": "one launch per start for the %d starts of %d instances spread over the batch"
+                                  % (len(pi) * k, len(pi))}
+        # (2) one launch per instance (k blocks each), the whole batch
         pw = starts.clone()
         pb = torch.empty(m * k, dtype=torch.int64, device="cuda")
         torch.cuda.synchronize()
@@ -254,12 +297,15 @@ def run_batch(args, w):
         torch.cuda.synchronize()
         pdt = time.perf_counter() - t0
         out["per_instance_launches"] = {
-            "solves_per_s": m * k / pdt, "speedup_batched": (m * k / (ms_step / 1e3)) / (m * k / pdt),
+            "solves_per_s": m * k / pdt, "speedup_batched": batched_solves / (m * k / pdt),
             "identical_costs": bool((pb.cpu().numpy() == gpu_best).all() and (pw.cpu().numpy() == gpu_perm).all())}
 
     if not args.no_cpu:
-        step = max(1, m // args.cpu_starts)
-        sample = [(t, t % k) for t in range(0, m, step)][:args.cpu_starts]
+        # one start of every instance, up to 16 x --cpu-starts of them (the default covers all
+        # 512 instances, every tile-shape variant, about a tenth of the batch's evals)
+        cap = 16 * args.cpu_starts
+        step = max(1, -(-m // cap))
+        sample = [(t, t % k) for t in range(0, m, step)][:cap]
         cb, exact = cpu_baseline_batch(w, gpu_best, gpu_perm, sample)
         out["cpu_baseline"] = cb
         out["bit_exact_sample"] = exact
@@ -439,27 +485,10 @@ def main():
     assert (h.cost(gpu_perm) == gpu_best).all(), "returned costs are not Eq. (1) of the returned permutations"
 
     search_evals = int(moves.sum()) * m
-    valu = VALU_PER_EVAL[algo] * search_evals / (search_ms / 1e3) / 1e12
-    roof = {"bound": "alu", "achieved": round(valu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s",
-            "frac": round(valu / PEAK_VALU_TOPS, 4), "traffic": traffic_for(w.name),
-            "kernel": ("search_kernel<%d,%s>" % (rows, "true" if algo == "tabu" else "false") if rows > 0 else
-                       "stream_kernel<%s,false,%s>" % ("true" if algo == "tabu" else "false",
-                                                       "true" if n > qap.QAP_NMAX_BATCH else "false")),
-            "kernel_ms": round(search_ms, 4),
-            "ops_per_eval": VALU_PER_EVAL[algo],
-            "hbm_equivalent": {"achieved": round(BYTES_PER_EVAL * search_evals / (search_ms / 1e3) / 1e9, 1),
-                               "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                               "frac": round(BYTES_PER_EVAL * search_evals / (search_ms / 1e3) / 1e9
-                                             / PEAK_HBM_GBS, 4)}}
-    if rows < 0:
-        # streamed kernels keep the neighbourhood in global memory: every entry's delta is
-        # read and written each step, so HBM bounds them
-        hbm = BYTES_PER_EVAL * search_evals / (search_ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(hbm / PEAK_HBM_GBS, 4), "traffic": roof["traffic"], "kernel": roof["kernel"],
-                "kernel_ms": roof["kernel_ms"], "bytes_per_eval": BYTES_PER_EVAL,
-                "alu_equivalent": {"achieved": round(valu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s",
-                                   "frac": round(valu / PEAK_VALU_TOPS, 4)}}
+    kname = ("search_kernel<%d,%s>" % (rows, "true" if algo == "tabu" else "false") if rows > 0 else
+             "stream_kernel<%s,false,%s>" % ("true" if algo == "tabu" else "false",
+                                             "true" if n > qap.QAP_NMAX_BATCH else "false"))
+    roof = roofline(search_evals, search_ms, kname, traffic_for(w.name), VALU_PER_EVAL[algo])
 
     out = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",

@@ -53,7 +53,8 @@ enum {
     QAP_E_RANGE = -3,     /* a flow or distance lies outside [0, 255] */
     QAP_E_DEVICE = -4,    /* a HIP call failed */
     QAP_E_NOMEM = -5,     /* host or device allocation failed */
-    QAP_E_UNSUPPORTED = -6 /* valid request this build cannot serve (see the entry point) */
+    QAP_E_BUSY = -6,      /* the server's queue is full (qap_server_submit*); nothing was queued */
+    QAP_E_UNSUPPORTED = -7 /* valid request this build cannot serve (see the entry point) */
 };
 
 typedef struct qap_ctx *qap_handle;
@@ -220,24 +221,38 @@ int qap_tabu_with_table_async(qap_handle h, int32_t *d_perms, const int32_t *d_t
  * start's neighbourhood table, Eq. (2), into the plan's scratch) followed by
  * qap_batch_search_async (every search, from those tables); the two halves may be
  * enqueued separately, in that order, on one stream.  qap_batch_size reports the number
- * of starts and of permutation entries.  qap_tabu_batch is the blocking host form (rows
- * of perms are checked; QAP_E_NOT_PERM otherwise).  A device-side row that is not a
- * permutation is left as it is, with best cost INT64_MIN and moves QAP_E_NOT_PERM.
+ * of starts and of permutation entries.  A device-side row that is not a permutation is
+ * left as it is, with best cost INT64_MIN and moves QAP_E_NOT_PERM.
+ * Blocking host forms (rows of perms are checked; QAP_E_NOT_PERM otherwise):
+ *   qap_tabu_batch         per-instance host arrays: perms[i] int32[k_per[i]][n_i] (the
+ *                          starts on entry, the best permutations on return) and
+ *                          best_out[i] int64[k_per[i]].
+ *   qap_tabu_batch_concat  the concatenated layout above, with the moves made in
+ *                          done_out (int32[sum k_i], may be NULL).
  */
 typedef struct qap_batch *qap_batch_handle;
 int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *k_per, int32_t iters,
                      const int32_t *lo_per, const int32_t *hi_per, const uint64_t *seed_per,
                      const int32_t *rows_per, qap_batch_handle *out);
 int qap_batch_size(qap_batch_handle b, int64_t *starts_out, int64_t *perm_ints_out);
+/* Kernel dispatches of one qap_batch_search_async: returns the number of tile-shape
+ * variants the plan uses (one dispatch each, forked onto side streams of `stream` and
+ * joined back), and, when count_out (int32[8]) is not NULL, the searches per variant in
+ * the order: tiles of 2, 4, 8 rows on 512 lanes, streamed, 2 rows on 128 and on 256
+ * lanes, 4 rows on 256 and on 768 lanes. */
+int qap_batch_groups(qap_batch_handle b, int32_t *count_out);
 int qap_batch_run_async(qap_batch_handle b, int32_t *d_perms, int64_t *d_best, int32_t *d_done,
                         void *stream);
 int qap_batch_tables_async(qap_batch_handle b, const int32_t *d_perms, void *stream);
 int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int64_t *d_best, int32_t *d_done,
                            void *stream);
 int qap_batch_destroy(qap_batch_handle b);
-int qap_tabu_batch(const qap_handle *hs, int32_t m, int32_t *perms, const int32_t *k_per,
-                   int32_t iters, const int32_t *lo_per, const int32_t *hi_per,
-                   const uint64_t *seed_per, int64_t *best_out, int32_t *done_out);
+int qap_tabu_batch(const qap_handle *hs, int32_t m, int32_t *const *perms, const int32_t *k_per,
+                   int32_t iters, const int32_t *lo_per, const int32_t *hi_per, const uint64_t *seed_per,
+                   int64_t *const *best_out);
+int qap_tabu_batch_concat(const qap_handle *hs, int32_t m, int32_t *perms, const int32_t *k_per,
+                          int32_t iters, const int32_t *lo_per, const int32_t *hi_per,
+                          const uint64_t *seed_per, int64_t *best_out, int32_t *done_out);
 
 /*
  * Serving: tabu solves of uneven n submitted one at a time, run with continuous
@@ -245,36 +260,75 @@ int qap_tabu_batch(const qap_handle *hs, int32_t m, int32_t *perms, const int32_
  * applied to a stream of requests).
  *
  * qap_server_create reserves a device memory pool of pool_bytes and slots for up to
- * max_active concurrent searches.  qap_server_submit copies a request (its own F, D, n,
- * one start permutation, iteration count and tenure range [lo, hi], Philox seed; start id
- * 0) and queues it; it returns QAP_E_NOMEM at once if the request's footprint
- * (qap_server_footprint(s, n, sym) bytes, sym = 1 when F and D are both symmetric)
- * exceeds the whole pool, QAP_E_UNSUPPORTED if no tile
- * shape of the batched kernel serves n, QAP_E_RANGE / QAP_E_NOT_PERM as qap_create and
- * qap_tabu do.  qap_server_step admits queued requests in arrival order while a slot is
- * free and their footprint fits the pool, then runs one chunk of every admitted search
- * in one launch: each search runs until about chunk_ms of device time has passed (0: to
- * its end), stopping at an iteration boundary, with its permutation, neighbourhood,
- * tabu list and best solution kept in the pool in between.  It blocks until the chunk
- * ends, then copies back the results of searches that finished and frees their memory;
- * it returns how many finished, and the numbers still running and still queued.  Every
+ * max_active concurrent searches, on the current HIP device; chunk_ms is the device time
+ * each search runs per step (0: every search runs to its end in one step).
+ *
+ * Submitting (never blocks; the request is queued and its ticket returned):
+ *   qap_server_submit          a request on an existing handle h (its device copies of F
+ *                              and D are used in place; the handle must stay alive until
+ *                              the request has finished or been cancelled), one start
+ *                              permutation (host int32[n], copied), iteration count,
+ *                              tenure range [lo, hi] and Philox seed (start id 0).
+ *   qap_server_submit_matrices the same with its own F and D (host int32[n][n], copied
+ *                              into the pool on admission), which need no handle.
+ * Both check as qap_create and qap_tabu do (QAP_E_INVALID, QAP_E_RANGE, QAP_E_NOT_PERM),
+ * return QAP_E_NOMEM at once if the request's footprint (qap_server_footprint(s, n, sym)
+ * bytes with its own matrices, sym = 1 when F and D are both symmetric, 4 n RS bytes
+ * less on a handle) exceeds the whole pool, QAP_E_UNSUPPORTED if no tile shape of the
+ * batched kernel serves n (n > QAP_NMAX_BATCH), and QAP_E_BUSY if the queue already holds
+ * qap_server_set_queue_limit requests (default 65536).
+ *
+ * Stepping: each step admits queued requests in arrival order while a slot is free and
+ * their footprint fits the pool (a request that does not fit is passed over by later
+ * ones that do, for at most 8 steps, after which nothing behind it is admitted first),
+ * then runs one chunk of every admitted search in one launch: each search runs until
+ * about chunk_ms of device time has passed, stopping at an iteration boundary, with its
+ * permutation, neighbourhood, tabu list and best solution kept in the pool in between.
+ * Searches that finished are then collected and their slot and memory freed.  Every
  * result equals that of qap_tabu on the same instance, start, iterations, tenure range
  * and seed (start id 0), whatever else was admitted alongside and however it was
- * chunked.  qap_server_result returns 1 and the result (best permutation int32[n], best
- * cost, moves made, and in latency_ms_out[2] (may be NULL) the time from submission to
- * the step that finished it and the time spent queued, in ms) once the request has
- * finished, after which its ticket is forgotten; 0 while it is queued or running.
- * qap_server_stats fills int64[6]: running, queued, pool bytes in use, pool bytes,
- * steps, chunks run.  One thread at a time may call a server's functions.
+ * chunked.  Steps are driven by the caller, qap_server_step (blocks for one step and
+ * returns how many searches finished, and the numbers still running and queued), or by
+ * the server's own host thread between qap_server_start and qap_server_stop (while it
+ * runs qap_server_step returns QAP_E_INVALID; qap_server_stop returns the error that
+ * stopped the thread, if any, and is implied by qap_server_destroy).
+ *
+ * Collecting: qap_server_poll returns 1 and the best permutation (host int32[n], may be
+ * NULL) and best cost (may be NULL) once the request has finished, after which its ticket
+ * is forgotten; 0 while it is queued or running.  qap_server_result is the same with the
+ * moves made and, in latency_ms_out[2] (may be NULL), the time from submission to the
+ * step that finished it and the time spent queued, in ms.  A search that failed on the
+ * device (its saved state found corrupt) returns QAP_E_DEVICE once, then is forgotten;
+ * the other searches are unaffected.  An unknown ticket gives QAP_E_INVALID.
+ *
+ * qap_server_cancel drops a queued or running request (1; a running search leaves at
+ * the next step boundary and its ticket is forgotten at once), or returns 0 if it has
+ * already finished (its result stays to be collected).  qap_server_inject_failure is a
+ * test hook: the running request's saved permutation is overwritten with an invalid one
+ * before the next chunk, so that its search fails there as a corrupted search would
+ * (QAP_E_INVALID unless the request is running).
+ *
+ * qap_server_stats fills int64[9]: running, queued, pool bytes in use, pool bytes,
+ * steps, chunks run, searches finished, failed, cancelled.  Every server function may be
+ * called from any host thread.
  */
 typedef struct qap_server *qap_server_handle;
 int qap_server_create(int64_t pool_bytes, int32_t max_active, double chunk_ms, qap_server_handle *out);
 int64_t qap_server_footprint(qap_server_handle s, int32_t n, int32_t sym);
-int qap_server_submit(qap_server_handle s, const int32_t *F, const int32_t *D, int32_t n, const int32_t *start,
-                      int32_t iters, int32_t lo, int32_t hi, uint64_t seed, int64_t *ticket_out);
+int qap_server_submit(qap_server_handle s, qap_handle h, const int32_t *start, int32_t iters, int32_t lo,
+                      int32_t hi, uint64_t seed, int64_t *ticket_out);
+int qap_server_submit_matrices(qap_server_handle s, const int32_t *F, const int32_t *D, int32_t n,
+                               const int32_t *start, int32_t iters, int32_t lo, int32_t hi, uint64_t seed,
+                               int64_t *ticket_out);
+int qap_server_set_queue_limit(qap_server_handle s, int32_t max_queued);
 int qap_server_step(qap_server_handle s, int32_t *active_out, int32_t *pending_out);
+int qap_server_start(qap_server_handle s);
+int qap_server_stop(qap_server_handle s);
+int qap_server_poll(qap_server_handle s, int64_t ticket, int32_t *best_perm, int64_t *best_cost);
 int qap_server_result(qap_server_handle s, int64_t ticket, int32_t *perm_out, int64_t *best_out,
                       int32_t *moves_out, double *latency_ms_out);
+int qap_server_cancel(qap_server_handle s, int64_t ticket);
+int qap_server_inject_failure(qap_server_handle s, int64_t ticket);
 int qap_server_stats(qap_server_handle s, int64_t *out);
 int qap_server_destroy(qap_server_handle s);
 

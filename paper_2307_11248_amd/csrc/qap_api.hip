@@ -102,6 +102,17 @@ struct qap_ctx {
     int stream_ok = 0;               // the streamed kernel serves this n
 };
 
+namespace qaph {
+bool handle_view(const qap_ctx *h, const uint8_t **mats, int *n, int *sym, int *device) {
+    if (!h) return false;
+    *mats = h->d_mats;
+    *n = h->n;
+    *sym = h->sym;
+    *device = h->device;
+    return true;
+}
+}  // namespace qaph
+
 namespace {
 
 // Shape index of the streamed kernel (tiles of STREAM_ROWS rows in global memory); the
@@ -388,6 +399,7 @@ const char *qap_strerror(int code) {
         case QAP_E_RANGE: return "a flow or distance lies outside [0, 255]";
         case QAP_E_DEVICE: return "HIP device error";
         case QAP_E_NOMEM: return "out of memory";
+        case QAP_E_BUSY: return "server queue full";
         case QAP_E_UNSUPPORTED: return "unsupported by this build";
         default: return "unknown error";
     }
@@ -819,6 +831,16 @@ extern "C" int qap_batch_size(qap_batch_handle b, int64_t *starts_out, int64_t *
     return QAP_OK;
 }
 
+extern "C" int qap_batch_groups(qap_batch_handle b, int32_t *count_out) {
+    if (!b) return QAP_E_INVALID;
+    int groups = 0;
+    for (int v = 0; v < BV_COUNT; ++v) {
+        if (count_out) count_out[v] = b->group_count[v];
+        groups += b->group_count[v] > 0;
+    }
+    return groups;
+}
+
 extern "C" int qap_batch_tables_async(qap_batch_handle b, const int32_t *d_perms, void *stream) {
     if (!b || (b->count > 0 && !d_perms)) return QAP_E_INVALID;
     if (b->count == 0) return QAP_OK;
@@ -872,9 +894,9 @@ extern "C" int qap_batch_destroy(qap_batch_handle b) {
     return QAP_OK;
 }
 
-extern "C" int qap_tabu_batch(const qap_handle *hs, int32_t m, int32_t *perms, const int32_t *k_per, int32_t iters,
-                              const int32_t *lo_per, const int32_t *hi_per, const uint64_t *seed_per,
-                              int64_t *best_out, int32_t *done_out) {
+extern "C" int qap_tabu_batch_concat(const qap_handle *hs, int32_t m, int32_t *perms, const int32_t *k_per,
+                                     int32_t iters, const int32_t *lo_per, const int32_t *hi_per,
+                                     const uint64_t *seed_per, int64_t *best_out, int32_t *done_out) {
     if (!hs || !k_per || (m > 0 && (!perms || !best_out))) return QAP_E_INVALID;
     long long off = 0;
     for (int i = 0; i < m; ++i) {
@@ -906,4 +928,43 @@ extern "C" int qap_tabu_batch(const qap_handle *hs, int32_t m, int32_t *perms, c
     qap_batch_destroy(b);
     if (rc != QAP_OK) return rc;
     return dev_err(e);
+}
+
+extern "C" int qap_tabu_batch(const qap_handle *hs, int32_t m, int32_t *const *perms, const int32_t *k_per,
+                              int32_t iters, const int32_t *lo_per, const int32_t *hi_per, const uint64_t *seed_per,
+                              int64_t *const *best_out) {
+    if (!hs || !k_per || m < 0 || (m > 0 && (!perms || !best_out))) return QAP_E_INVALID;
+    long long ints = 0, starts = 0;
+    for (int i = 0; i < m; ++i) {
+        if (!hs[i] || k_per[i] < 0 || (k_per[i] > 0 && (!perms[i] || !best_out[i]))) return QAP_E_INVALID;
+        ints += (long long)k_per[i] * hs[i]->n;
+        starts += k_per[i];
+    }
+    // gathered into one concatenated batch, run, and scattered back
+    std::vector<int32_t> cat;
+    std::vector<int64_t> best;
+    try {
+        cat.resize((size_t)ints);
+        best.resize((size_t)starts);
+    } catch (...) {
+        return QAP_E_NOMEM;
+    }
+    long long o = 0;
+    for (int i = 0; i < m; ++i) {
+        const size_t c = (size_t)k_per[i] * hs[i]->n;
+        if (c) std::memcpy(cat.data() + o, perms[i], c * sizeof(int32_t));
+        o += (long long)c;
+    }
+    const int rc = qap_tabu_batch_concat(hs, m, cat.data(), k_per, iters, lo_per, hi_per, seed_per, best.data(),
+                                         nullptr);
+    if (rc != QAP_OK) return rc;
+    long long po = 0, bo = 0;
+    for (int i = 0; i < m; ++i) {
+        const size_t c = (size_t)k_per[i] * hs[i]->n;
+        if (c) std::memcpy(perms[i], cat.data() + po, c * sizeof(int32_t));
+        if (k_per[i]) std::memcpy(best_out[i], best.data() + bo, (size_t)k_per[i] * sizeof(int64_t));
+        po += (long long)c;
+        bo += k_per[i];
+    }
+    return QAP_OK;
 }

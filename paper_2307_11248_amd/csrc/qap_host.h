@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <vector>
 
+struct qap_ctx;
+
 namespace qaph {
 
 // Tile heights of the search kernels.
@@ -26,6 +28,10 @@ int dev_err_at(hipError_t e, const char *where);
 
 // Whether each of the k rows of perms is a permutation of 0..n-1.
 bool check_perms(const int32_t *perms, int k, int n);
+
+// A handle's device copy of [F | F^T | D | D^T], its n, symmetry and device (for the
+// server's requests on existing handles).  False for a null handle.
+bool handle_view(const struct ::qap_ctx *h, const uint8_t **mats, int *n, int *sym, int *device);
 
 // Whether a tabu run of `iters` iterations with tenures in [lo, hi] is valid: the
 // iteration until which a move stays tabu, it + t <= iters + hi, must fit in int32.

@@ -1,20 +1,28 @@
 // qap_server.hip -- serving loop for tabu solves of uneven n: continuous batching of
 // resumable searches over device-resident state.
 //
-// Requests are admitted in arrival order while their device footprint fits the
-// server's memory pool and a slot is free.  Each step runs one chunk of every admitted
-// search in a single launch (one workgroup per search, each stopping at an iteration
-// boundary once a clock budget is spent) and keeps the search's permutation, tabu list
-// and neighbourhood on the device between chunks, so a search gives exactly the result
-// it gives when run alone in one go.  Requests that arrive while a chunk runs join at
-// the next step; finished searches free their slot and memory at once.
+// Requests are admitted in arrival order while a slot is free and their device
+// footprint fits the server's memory pool; a request that does not fit is passed over
+// by later ones that do, until it has been passed over kMaxPassOvers times, after which
+// nothing behind it is admitted before it (so a large request cannot starve).  Each step
+// runs one chunk of every admitted search in a single launch (one workgroup per search,
+// each stopping at an iteration boundary once a clock budget is spent) and keeps the
+// search's permutation, tabu list and neighbourhood on the device between chunks, so a
+// search gives exactly the result it gives when run alone in one go.  Requests that
+// arrive while a chunk runs join at the next step; finished searches free their slot and
+// memory at once.  Steps are driven either by the caller (qap_server_step) or by the
+// server's own host thread (qap_server_start); submissions, polls and cancellations are
+// safe from any thread meanwhile.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -28,6 +36,8 @@ using namespace qaph;
 namespace {
 
 constexpr size_t kAlign = 256;
+// Steps a queued request may be passed over by later ones before admission waits for it.
+constexpr int kMaxPassOvers = 8;
 
 size_t up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -82,11 +92,13 @@ struct Layout {
     size_t mats, perm, st_perm, st_bestp, table, st_du, tile_work, total;
 };
 
-Layout layout_for(int n, bool streamed, int ntiles) {
+// own_mats: the request brought its own F and D (a copy lives in the pool); otherwise it
+// runs on an existing handle's device matrices.
+Layout layout_for(int n, bool streamed, int ntiles, bool own_mats = true) {
     const size_t m = (size_t)n * (n - 1) / 2;
     Layout L{};
     size_t o = 0;
-    L.mats = o;     o += up((size_t)4 * n * row_stride(n));
+    L.mats = o;     if (own_mats) o += up((size_t)4 * n * row_stride(n));
     L.perm = o;     o += up((size_t)n * 4);
     L.st_perm = o;  o += up((size_t)n * 4);
     L.st_bestp = o; o += up((size_t)n * 4);
@@ -102,12 +114,16 @@ struct Request {
     int n = 0, m = 0, sym = 0, rows = 0, iters = 0, lo = 0, hi = 0;
     bool streamed = false;
     uint64_t seed = 0;
-    std::vector<uint8_t> mats;
+    std::vector<uint8_t> mats;          // own copy of [F | F^T | D | D^T], or empty
+    const uint8_t *ext_mats = nullptr;  // else the device matrices of a handle
     std::vector<int32_t> start;
     Layout lay{};
     long long off = -1;
     int slot = -1;
-    bool fresh = false;    // admitted, table not built yet
+    bool fresh = false;      // admitted, table not built yet
+    bool cancelled = false;  // dropped at the next step
+    bool inject = false;     // test hook: its device state is corrupted before the next chunk
+    int passed_over = 0;     // steps in which a later request was admitted before it
     double t_submit = 0, t_admit = 0;
 };
 
@@ -115,6 +131,7 @@ struct Result {
     std::vector<int32_t> perm;
     int64_t best = 0;
     int32_t moves = 0;
+    int status = QAP_OK;     // QAP_E_DEVICE when the search failed on the device
     double latency_ms = 0, queued_ms = 0;
 };
 
@@ -154,8 +171,17 @@ struct qap_server {
     std::vector<Request *> active;
     std::unordered_map<int64_t, Result> done;
     std::unordered_map<int64_t, int> state;   // 0 pending, 1 active, 2 done
+    std::unordered_map<int64_t, Request *> live;   // pending and active requests by ticket
     int64_t next_ticket = 1;
-    long long chunks = 0, steps = 0;
+    long long chunks = 0, steps = 0, finished = 0, failed = 0, cancelled = 0;
+    int max_queued = 1 << 16;
+    // mu guards everything above that submit, poll, cancel and step share (queues,
+    // result maps, arena, slots, tile lists); step_mu makes steps one at a time
+    std::mutex mu, step_mu;
+    std::condition_variable cv;
+    std::thread driver;
+    bool driver_on = false, driver_stop = false;
+    int driver_error = QAP_OK;
 };
 
 namespace {
@@ -202,7 +228,7 @@ Item make_item(qap_server *s, const Request *r) {
     const Tiles &ts = s->tiles[r->n * 16 + (r->streamed ? STREAM_ROWS : r->rows)];
     uint8_t *base = s->pool + r->off;
     Item it{};
-    it.mats = base + r->lay.mats;
+    it.mats = r->ext_mats ? r->ext_mats : base + r->lay.mats;
     it.tiles = ts.d;
     it.table = reinterpret_cast<const int32_t *>(base + r->lay.table);
     it.perm_in = reinterpret_cast<const int32_t *>(base + r->lay.perm);
@@ -238,6 +264,205 @@ void release(qap_server *s, Request *r) {
     if (r->slot >= 0) s->free_slots.push_back(r->slot);
     r->off = -1;
     r->slot = -1;
+}
+
+// Queue a request whose matrices and tile shape are settled (s->mu held by the caller).
+int enqueue(qap_server *s, Request *r, int32_t n, const int32_t *start, int32_t iters, int32_t lo, int32_t hi,
+            uint64_t seed, int64_t *ticket_out) {
+    if ((int64_t)s->pending.size() >= s->max_queued) return QAP_E_BUSY;
+    r->n = n;
+    r->m = n * (n - 1) / 2;
+    r->iters = iters;
+    r->lo = lo;
+    r->hi = hi;
+    r->seed = seed;
+    r->start.assign(start, start + n);
+    r->ticket = s->next_ticket++;
+    r->t_submit = now_ms();
+    s->pending.push_back(r);
+    s->state[r->ticket] = 0;
+    s->live[r->ticket] = r;
+    *ticket_out = r->ticket;
+    s->cv.notify_all();
+    return QAP_OK;
+}
+
+// Tile shape and layout of a request (s->mu held); QAP_OK or an error code.
+int plan_request(qap_server *s, Request *r, int n) {
+    int rc = QAP_OK;
+    r->rows = server_rows(s, n, r->sym, &rc);
+    if (rc != QAP_OK) return rc;
+    r->streamed = r->rows < 0;
+    const Tiles &ts = s->tiles[n * 16 + (r->streamed ? STREAM_ROWS : r->rows)];
+    r->lay = layout_for(n, r->streamed, ts.ntiles, r->ext_mats == nullptr);
+    if (up(r->lay.total) > s->pool_bytes) return QAP_E_NOMEM;   // could never be admitted
+    return QAP_OK;
+}
+
+// One step: admit, run one chunk of every admitted search, collect the finished ones.
+// Called with s->step_mu held; takes s->mu only around the shared state.
+int step_locked(qap_server *s, int32_t *active_out, int32_t *pending_out) {
+    hipError_t e = hipSuccess;
+    int nnew = 0, count = 0;
+    size_t smem = 0, tsmem = 0;
+    std::vector<Request *> admitted, injected;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        // cancelled searches leave now
+        std::vector<Request *> keep;
+        for (Request *r : s->active) {
+            if (!r->cancelled) { keep.push_back(r); continue; }
+            release(s, r);
+            delete r;
+        }
+        s->active.swap(keep);
+        // admission in arrival order; a request that does not fit is passed over by later
+        // ones that do, until it has waited kMaxPassOvers steps
+        std::deque<Request *> still;
+        bool blocked = false;
+        while (!s->pending.empty()) {
+            Request *r = s->pending.front();
+            s->pending.pop_front();
+            long long off = -1;
+            if (!blocked && !s->free_slots.empty()) off = s->arena.alloc(r->lay.total);
+            if (off < 0) {
+                if (!blocked && ++r->passed_over > kMaxPassOvers) blocked = true;
+                still.push_back(r);
+                continue;
+            }
+            r->off = off;
+            r->slot = s->free_slots.back();
+            s->free_slots.pop_back();
+            r->fresh = true;
+            r->t_admit = now_ms();
+            s->active.push_back(r);
+            s->state[r->ticket] = 1;
+            admitted.push_back(r);
+        }
+        s->pending.swap(still);
+        count = (int)s->active.size();
+        for (int i = 0; i < count; ++i) {
+            Request *r = s->active[i];
+            s->h_items[i] = make_item(s, r);
+            smem = std::max(smem, r->streamed ? stream_smem_bytes(r->n, r->sym)
+                                              : search_smem_bytes(r->n, r->rows, BATCH_LANES, r->sym));
+            if (r->fresh) {
+                s->h_new[nnew++] = s->h_items[i];
+                tsmem = std::max(tsmem, table_smem_bytes(r->n));
+                r->fresh = false;
+            }
+            if (r->inject) {
+                injected.push_back(r);
+                r->inject = false;
+            }
+        }
+    }
+    // device work, outside the lock (only this step touches active requests' buffers)
+    for (Request *r : admitted) {
+        if (e != hipSuccess) break;
+        uint8_t *base = s->pool + r->off;
+        if (!r->ext_mats)
+            e = hipMemcpyAsync(base + r->lay.mats, r->mats.data(), r->mats.size(), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(base + r->lay.perm, r->start.data(), (size_t)r->n * 4, hipMemcpyHostToDevice, s->st);
+        SearchState &hs = s->h_state[r->slot];
+        hs = SearchState{};
+        hs.it = 1;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->d_state + r->slot, &hs, sizeof(SearchState), hipMemcpyHostToDevice, s->st);
+    }
+    if (count > 0 && e == hipSuccess) {
+        if (nnew) e = hipMemcpyAsync(s->d_new, s->h_new, (size_t)nnew * sizeof(Item), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->d_items, s->h_items, (size_t)count * sizeof(Item), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess && nnew) e = launch_table_items(s->d_new, nnew, tsmem, s->st);
+        // test hook: a corrupted saved permutation (every entry 0), which the search
+        // detects when it resumes; it then stops with its failure code
+        for (Request *r : injected) {
+            if (e != hipSuccess) break;
+            uint8_t *base = s->pool + r->off;
+            e = hipMemsetAsync(base + r->lay.perm, 0, (size_t)r->n * 4, s->st);
+            if (e == hipSuccess) e = hipMemsetAsync(base + r->lay.st_perm, 0, (size_t)r->n * 4, s->st);
+        }
+        if (e == hipSuccess) e = launch_resume(s->d_items, count, smem, s->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->h_state, s->d_state, (size_t)s->max_active * sizeof(SearchState),
+                               hipMemcpyDeviceToHost, s->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->h_cost, s->d_cost, (size_t)s->max_active * 8, hipMemcpyDeviceToHost, s->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->h_moves, s->d_moves, (size_t)s->max_active * 4, hipMemcpyDeviceToHost, s->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    }
+    if (e != hipSuccess) return dev_err(e);
+    // finished searches: their best permutations come back before they are published
+    std::vector<Request *> fin;
+    std::vector<std::vector<int32_t>> perms;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (count > 0) {
+            ++s->steps;
+            s->chunks += count;
+        }
+        for (Request *r : s->active)
+            if (s->h_state[r->slot].done) fin.push_back(r);
+    }
+    perms.resize(fin.size());
+    for (size_t i = 0; i < fin.size() && e == hipSuccess; ++i) {
+        perms[i].resize(fin[i]->n);
+        e = hipMemcpyAsync(perms[i].data(), s->pool + fin[i]->off + fin[i]->lay.perm, (size_t)fin[i]->n * 4,
+                           hipMemcpyDeviceToHost, s->st);
+    }
+    if (e == hipSuccess && !fin.empty()) e = hipStreamSynchronize(s->st);
+    if (e != hipSuccess) return dev_err(e);
+    const double t = now_ms();
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::vector<Request *> keep;
+    for (Request *r : s->active)
+        if (std::find(fin.begin(), fin.end(), r) == fin.end()) keep.push_back(r);
+    for (size_t i = 0; i < fin.size(); ++i) {
+        Request *r = fin[i];
+        s->live.erase(r->ticket);
+        if (r->cancelled) {
+            s->state.erase(r->ticket);
+        } else {
+            Result &res = s->done[r->ticket];
+            res.perm.swap(perms[i]);
+            res.best = s->h_cost[r->slot];
+            res.moves = s->h_moves[r->slot];
+            // a search that found its state corrupted stops with moves = -2 (it never
+            // starts from an unchecked permutation: submissions are checked on the host)
+            res.status = res.moves < 0 ? QAP_E_DEVICE : QAP_OK;
+            res.latency_ms = t - r->t_submit;
+            res.queued_ms = r->t_admit - r->t_submit;
+            s->state[r->ticket] = 2;
+            ++(res.status == QAP_OK ? s->finished : s->failed);
+        }
+        release(s, r);
+        delete r;
+    }
+    s->active.swap(keep);
+    if (active_out) *active_out = (int32_t)s->active.size();
+    if (pending_out) *pending_out = (int32_t)s->pending.size();
+    return (int)fin.size();
+}
+
+void driver_loop(qap_server *s) {
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait(lk, [s] { return s->driver_stop || !s->pending.empty() || !s->active.empty(); });
+            if (s->driver_stop) return;
+        }
+        std::lock_guard<std::mutex> sl(s->step_mu);
+        const int rc = step_locked(s, nullptr, nullptr);
+        if (rc < 0) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->driver_error = rc;
+            return;
+        }
+    }
 }
 
 }  // namespace
@@ -281,6 +506,7 @@ int qap_server_create(int64_t pool_bytes, int32_t max_active, double chunk_ms, q
 
 int64_t qap_server_footprint(qap_server_handle s, int32_t n, int32_t sym) {
     if (!s || n < 2 || n > QAP_NMAX) return QAP_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
     int rc = QAP_OK;
     const int rows = server_rows(s, n, sym ? 1 : 0, &rc);
     if (rc != QAP_OK) return rc;
@@ -289,162 +515,183 @@ int64_t qap_server_footprint(qap_server_handle s, int32_t n, int32_t sym) {
     return (int64_t)layout_for(n, rows < 0, nt).total;
 }
 
-int qap_server_submit(qap_server_handle s, const int32_t *F, const int32_t *D, int32_t n, const int32_t *start,
-                      int32_t iters, int32_t lo, int32_t hi, uint64_t seed, int64_t *ticket_out) {
-    if (!s || !F || !D || !start || !ticket_out || n < 2 || n > QAP_NMAX ||
-        !tenure_args_ok(iters, lo, hi))
+int qap_server_submit_matrices(qap_server_handle s, const int32_t *F, const int32_t *D, int32_t n,
+                               const int32_t *start, int32_t iters, int32_t lo, int32_t hi, uint64_t seed,
+                               int64_t *ticket_out) {
+    if (!s || !F || !D || !start || !ticket_out || n < 2 || n > QAP_NMAX || !tenure_args_ok(iters, lo, hi))
         return QAP_E_INVALID;
     if (!check_perms(start, 1, n)) return QAP_E_NOT_PERM;
     Request *r = new (std::nothrow) Request;
     if (!r) return QAP_E_NOMEM;
     int rc = pack_instance(F, D, n, r->mats, &r->sym);
-    if (rc == QAP_OK) r->rows = server_rows(s, n, r->sym, &rc);
-    if (rc == QAP_OK) {
-        r->streamed = r->rows < 0;
-        const Tiles &ts = s->tiles[n * 16 + (r->streamed ? STREAM_ROWS : r->rows)];
-        r->lay = layout_for(n, r->streamed, ts.ntiles);
-    }
-    if (rc == QAP_OK && up(r->lay.total) > s->pool_bytes) rc = QAP_E_NOMEM;   // could never be admitted
-    if (rc != QAP_OK) {
-        delete r;
-        return rc;
-    }
-    r->n = n;
-    r->m = n * (n - 1) / 2;
-    r->iters = iters;
-    r->lo = lo;
-    r->hi = hi;
-    r->seed = seed;
-    r->start.assign(start, start + n);
-    r->ticket = s->next_ticket++;
-    r->t_submit = now_ms();
-    s->pending.push_back(r);
-    s->state[r->ticket] = 0;
-    *ticket_out = r->ticket;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (rc == QAP_OK) rc = plan_request(s, r, n);
+    if (rc == QAP_OK) rc = enqueue(s, r, n, start, iters, lo, hi, seed, ticket_out);
+    if (rc != QAP_OK) delete r;
+    return rc;
+}
+
+int qap_server_submit(qap_server_handle s, qap_handle h, const int32_t *start, int32_t iters, int32_t lo,
+                      int32_t hi, uint64_t seed, int64_t *ticket_out) {
+    const uint8_t *mats = nullptr;
+    int n = 0, sym = 0, dev = 0;
+    if (!s || !start || !ticket_out || !handle_view(h, &mats, &n, &sym, &dev) || !tenure_args_ok(iters, lo, hi))
+        return QAP_E_INVALID;
+    if (dev != s->device) return QAP_E_INVALID;
+    if (!check_perms(start, 1, n)) return QAP_E_NOT_PERM;
+    Request *r = new (std::nothrow) Request;
+    if (!r) return QAP_E_NOMEM;
+    r->ext_mats = mats;
+    r->sym = sym;
+    std::lock_guard<std::mutex> lk(s->mu);
+    int rc = plan_request(s, r, n);
+    if (rc == QAP_OK) rc = enqueue(s, r, n, start, iters, lo, hi, seed, ticket_out);
+    if (rc != QAP_OK) delete r;
+    return rc;
+}
+
+int qap_server_set_queue_limit(qap_server_handle s, int32_t max_queued) {
+    if (!s || max_queued < 1) return QAP_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->max_queued = max_queued;
     return QAP_OK;
 }
 
 int qap_server_step(qap_server_handle s, int32_t *active_out, int32_t *pending_out) {
     if (!s) return QAP_E_INVALID;
-    hipError_t e = hipSuccess;
-    // admission, in arrival order, while a slot is free and the footprint fits
-    int nnew = 0;
-    while (!s->pending.empty() && !s->free_slots.empty() && e == hipSuccess) {
-        Request *r = s->pending.front();
-        const long long off = s->arena.alloc(r->lay.total);
-        if (off < 0) break;
-        r->off = off;
-        r->slot = s->free_slots.back();
-        s->free_slots.pop_back();
-        r->fresh = true;
-        r->t_admit = now_ms();
-        uint8_t *base = s->pool + off;
-        e = hipMemcpyAsync(base + r->lay.mats, r->mats.data(), r->mats.size(), hipMemcpyHostToDevice, s->st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(base + r->lay.perm, r->start.data(), (size_t)r->n * 4, hipMemcpyHostToDevice, s->st);
-        SearchState &hs = s->h_state[r->slot];
-        hs = SearchState{};
-        hs.it = 1;
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->d_state + r->slot, &hs, sizeof(SearchState), hipMemcpyHostToDevice, s->st);
-        s->pending.pop_front();
-        s->active.push_back(r);
-        s->state[r->ticket] = 1;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->driver_on) return QAP_E_INVALID;   // the server's own thread steps it
     }
-    // one chunk of every admitted search
-    const int count = (int)s->active.size();
-    size_t smem = 0, tsmem = 0;
-    for (int i = 0; i < count && e == hipSuccess; ++i) {
-        Request *r = s->active[i];
-        s->h_items[i] = make_item(s, r);
-        smem = std::max(smem, r->streamed ? stream_smem_bytes(r->n, r->sym)
-                                          : search_smem_bytes(r->n, r->rows, BATCH_LANES, r->sym));
-        if (r->fresh) {
-            s->h_new[nnew++] = s->h_items[i];
-            tsmem = std::max(tsmem, table_smem_bytes(r->n));
-            r->fresh = false;
-        }
+    std::lock_guard<std::mutex> sl(s->step_mu);
+    return step_locked(s, active_out, pending_out);
+}
+
+int qap_server_start(qap_server_handle s) {
+    if (!s) return QAP_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->driver_on) return QAP_OK;
+    s->driver_stop = false;
+    s->driver_error = QAP_OK;
+    try {
+        s->driver = std::thread(driver_loop, s);
+    } catch (...) {
+        return QAP_E_NOMEM;
     }
-    if (count > 0 && e == hipSuccess) {
-        if (nnew) e = hipMemcpyAsync(s->d_new, s->h_new, (size_t)nnew * sizeof(Item), hipMemcpyHostToDevice, s->st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->d_items, s->h_items, (size_t)count * sizeof(Item), hipMemcpyHostToDevice, s->st);
-        if (e == hipSuccess && nnew) e = launch_table_items(s->d_new, nnew, tsmem, s->st);
-        if (e == hipSuccess) e = launch_resume(s->d_items, count, smem, s->st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->h_state, s->d_state, (size_t)s->max_active * sizeof(SearchState),
-                               hipMemcpyDeviceToHost, s->st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->h_cost, s->d_cost, (size_t)s->max_active * 8, hipMemcpyDeviceToHost, s->st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->h_moves, s->d_moves, (size_t)s->max_active * 4, hipMemcpyDeviceToHost, s->st);
-        if (e == hipSuccess) e = hipStreamSynchronize(s->st);
-        ++s->steps;
-        s->chunks += count;
+    s->driver_on = true;
+    return QAP_OK;
+}
+
+int qap_server_stop(qap_server_handle s) {
+    if (!s) return QAP_E_INVALID;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->driver_on) return QAP_OK;
+        s->driver_stop = true;
+        s->cv.notify_all();
     }
-    if (e != hipSuccess) return dev_err(e);
-    // collect finished searches: copy their best permutations back, free slot and memory
-    std::vector<Request *> fin, keep;
-    for (Request *r : s->active) (s->h_state[r->slot].done ? fin : keep).push_back(r);
-    for (Request *r : fin) {
-        Result &res = s->done[r->ticket];
-        res.perm.resize(r->n);
-        e = hipMemcpyAsync(res.perm.data(), s->pool + r->off + r->lay.perm, (size_t)r->n * 4,
-                           hipMemcpyDeviceToHost, s->st);
-        if (e != hipSuccess) break;
+    s->driver.join();
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->driver_on = false;
+    return s->driver_error;
+}
+
+// Shared lookup of qap_server_poll and qap_server_result (s->mu held): 1 and the result
+// once finished (the ticket is then forgotten), 0 while queued or running, an error code
+// for a search that failed (forgotten too) or an unknown ticket.
+static int take_result(qap_server *s, int64_t ticket, Result *out) {
+    auto st = s->state.find(ticket);
+    if (st == s->state.end()) return QAP_E_INVALID;
+    if (st->second != 2) return s->driver_error != QAP_OK ? s->driver_error : 0;
+    auto it = s->done.find(ticket);
+    *out = std::move(it->second);
+    s->done.erase(it);
+    s->state.erase(st);
+    return out->status == QAP_OK ? 1 : out->status;
+}
+
+int qap_server_poll(qap_server_handle s, int64_t ticket, int32_t *best_perm, int64_t *best_cost) {
+    if (!s) return QAP_E_INVALID;
+    Result r;
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        rc = take_result(s, ticket, &r);
     }
-    if (e == hipSuccess && !fin.empty()) e = hipStreamSynchronize(s->st);
-    if (e != hipSuccess) return dev_err(e);
-    const double t = now_ms();
-    for (Request *r : fin) {
-        Result &res = s->done[r->ticket];
-        res.best = s->h_cost[r->slot];
-        res.moves = s->h_moves[r->slot];
-        res.latency_ms = t - r->t_submit;
-        res.queued_ms = r->t_admit - r->t_submit;
-        s->state[r->ticket] = 2;
-        release(s, r);
-        delete r;
+    if (rc == 1) {
+        if (best_perm) std::copy(r.perm.begin(), r.perm.end(), best_perm);
+        if (best_cost) *best_cost = r.best;
     }
-    s->active.swap(keep);
-    if (active_out) *active_out = (int32_t)s->active.size();
-    if (pending_out) *pending_out = (int32_t)s->pending.size();
-    return (int)fin.size();
+    return rc;
 }
 
 int qap_server_result(qap_server_handle s, int64_t ticket, int32_t *perm_out, int64_t *best_out,
                       int32_t *moves_out, double *latency_ms_out) {
     if (!s) return QAP_E_INVALID;
+    Result r;
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        rc = take_result(s, ticket, &r);
+    }
+    if (rc == 1) {
+        if (perm_out) std::copy(r.perm.begin(), r.perm.end(), perm_out);
+        if (best_out) *best_out = r.best;
+        if (moves_out) *moves_out = r.moves;
+        if (latency_ms_out) {
+            latency_ms_out[0] = r.latency_ms;
+            latency_ms_out[1] = r.queued_ms;
+        }
+    }
+    return rc;
+}
+
+int qap_server_cancel(qap_server_handle s, int64_t ticket) {
+    if (!s) return QAP_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
     auto st = s->state.find(ticket);
     if (st == s->state.end()) return QAP_E_INVALID;
-    if (st->second != 2) return 0;
-    auto it = s->done.find(ticket);
-    const Result &r = it->second;
-    if (perm_out) std::copy(r.perm.begin(), r.perm.end(), perm_out);
-    if (best_out) *best_out = r.best;
-    if (moves_out) *moves_out = r.moves;
-    if (latency_ms_out) {
-        latency_ms_out[0] = r.latency_ms;
-        latency_ms_out[1] = r.queued_ms;
+    if (st->second == 2) return 0;   // finished: the result stays to be collected
+    Request *r = s->live[ticket];
+    if (st->second == 0) {
+        s->pending.erase(std::find(s->pending.begin(), s->pending.end(), r));
+        delete r;
+    } else {
+        r->cancelled = true;   // leaves at the next step boundary
     }
-    s->done.erase(it);
+    s->live.erase(ticket);
     s->state.erase(st);
+    ++s->cancelled;
     return 1;
+}
+
+int qap_server_inject_failure(qap_server_handle s, int64_t ticket) {
+    if (!s) return QAP_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto st = s->state.find(ticket);
+    if (st == s->state.end() || st->second != 1) return QAP_E_INVALID;
+    s->live[ticket]->inject = true;
+    return QAP_OK;
 }
 
 int qap_server_stats(qap_server_handle s, int64_t *out) {
     if (!s || !out) return QAP_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
     out[0] = (int64_t)s->active.size();
     out[1] = (int64_t)s->pending.size();
     out[2] = (int64_t)s->arena.used();
     out[3] = (int64_t)s->pool_bytes;
     out[4] = s->steps;
     out[5] = s->chunks;
+    out[6] = s->finished;
+    out[7] = s->failed;
+    out[8] = s->cancelled;
     return QAP_OK;
 }
 
 int qap_server_destroy(qap_server_handle s) {
     if (!s) return QAP_OK;
+    (void)qap_server_stop(s);
     if (s->st) (void)hipStreamSynchronize(s->st);
     for (Request *r : s->pending) delete r;
     for (Request *r : s->active) delete r;

@@ -23,7 +23,8 @@ QAP_E_NOT_PERM = -2
 QAP_E_RANGE = -3
 QAP_E_DEVICE = -4
 QAP_E_NOMEM = -5
-QAP_E_UNSUPPORTED = -6
+QAP_E_BUSY = -6
+QAP_E_UNSUPPORTED = -7
 QAP_NMAX = 512
 QAP_NMAX_BATCH = 256   # batched and served searches
 
@@ -31,10 +32,14 @@ EXPORTS = [
     "qap_strerror", "qap_create", "qap_destroy", "qap_size", "qap_cost", "qap_cost_async", "qap_delta_table",
     "qap_delta_table_async", "qap_2opt", "qap_2opt_async", "qap_tabu", "qap_tabu_async", "qap_tabu_freq_async",
     "qap_tabu_plain_async", "qap_2opt_with_table_async", "qap_tabu_with_table_async", "qap_set_tile_rows",
-    "qap_get_tile_rows", "qap_launch_tile_rows", "qap_batch_create", "qap_batch_size", "qap_batch_run_async",
+    "qap_get_tile_rows", "qap_launch_tile_rows", "qap_batch_create", "qap_batch_size", "qap_batch_groups",
+    "qap_batch_run_async",
     "qap_batch_tables_async", "qap_batch_search_async", "qap_batch_destroy", "qap_tabu_batch",
-    "qap_tune_tile_rows", "qap_server_create", "qap_server_footprint", "qap_server_submit", "qap_server_step",
-    "qap_server_result", "qap_server_stats", "qap_server_destroy",
+    "qap_tabu_batch_concat",
+    "qap_tune_tile_rows", "qap_server_create", "qap_server_footprint", "qap_server_submit",
+    "qap_server_submit_matrices", "qap_server_set_queue_limit", "qap_server_step", "qap_server_start",
+    "qap_server_stop", "qap_server_poll", "qap_server_result", "qap_server_cancel", "qap_server_inject_failure",
+    "qap_server_stats", "qap_server_destroy",
 ]
 
 ALGOS = {"tabu": 0, "2opt": 1, "batch": 2}
@@ -89,8 +94,16 @@ def lib():
                 "qap_tune_tile_rows": (ctypes.c_int, [_vp, i32, i32, i32, ctypes.POINTER(ctypes.c_float)]),
                 "qap_server_create": (ctypes.c_int, [i64, i32, ctypes.c_double, ctypes.POINTER(_vp)]),
                 "qap_server_footprint": (i64, [_vp, i32, i32]),
-                "qap_server_submit": (ctypes.c_int, [_vp, _i32p, _i32p, i32, _i32p, i32, i32, i32, u64, _i64p]),
+                "qap_server_submit": (ctypes.c_int, [_vp, _vp, _i32p, i32, i32, i32, u64, _i64p]),
+                "qap_server_submit_matrices": (ctypes.c_int, [_vp, _i32p, _i32p, i32, _i32p, i32, i32, i32, u64,
+                                                              _i64p]),
+                "qap_server_set_queue_limit": (ctypes.c_int, [_vp, i32]),
                 "qap_server_step": (ctypes.c_int, [_vp, _i32p, _i32p]),
+                "qap_server_start": (ctypes.c_int, [_vp]),
+                "qap_server_stop": (ctypes.c_int, [_vp]),
+                "qap_server_poll": (ctypes.c_int, [_vp, i64, _i32p, _i64p]),
+                "qap_server_cancel": (ctypes.c_int, [_vp, i64]),
+                "qap_server_inject_failure": (ctypes.c_int, [_vp, i64]),
                 "qap_server_result": (ctypes.c_int, [_vp, i64, _i32p, _i64p, _i32p,
                                                      ctypes.POINTER(ctypes.c_double)]),
                 "qap_server_stats": (ctypes.c_int, [_vp, _i64p]),
@@ -98,12 +111,15 @@ def lib():
                 "qap_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), i32, _i32p, i32, _i32p, _i32p, _u64p,
                                                     _i32p, ctypes.POINTER(_vp)]),
                 "qap_batch_size": (ctypes.c_int, [_vp, _i64p, _i64p]),
+                "qap_batch_groups": (ctypes.c_int, [_vp, _i32p]),
                 "qap_batch_run_async": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
                 "qap_batch_tables_async": (ctypes.c_int, [_vp, _vp, _vp]),
                 "qap_batch_search_async": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
                 "qap_batch_destroy": (ctypes.c_int, [_vp]),
-                "qap_tabu_batch": (ctypes.c_int, [ctypes.POINTER(_vp), i32, _i32p, _i32p, i32, _i32p, _i32p,
-                                                  _u64p, _i64p, _i32p]),
+                "qap_tabu_batch": (ctypes.c_int, [ctypes.POINTER(_vp), i32, ctypes.POINTER(_i32p), _i32p, i32,
+                                                  _i32p, _i32p, _u64p, ctypes.POINTER(_i64p)]),
+                "qap_tabu_batch_concat": (ctypes.c_int, [ctypes.POINTER(_vp), i32, _i32p, _i32p, i32, _i32p,
+                                                         _i32p, _u64p, _i64p, _i32p]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -332,6 +348,13 @@ class Batch:
         _check(lib().qap_batch_run_async(self._b, _dptr(d_perms, "int32"), _dptr(d_best, "int64"),
                                          _dptr(d_done, "int32"), _stream_ptr(stream)), "qap_batch_run_async")
 
+    def groups(self, counts: bool = False):
+        """Kernel dispatches of one search phase (one per tile-shape variant in use); with
+        counts=True also the searches per variant (int32[8], the header's order)."""
+        c = np.zeros(8, dtype=np.int32)
+        g = _check(lib().qap_batch_groups(self._b, _ptr(c, _i32p)), "qap_batch_groups")
+        return (g, c) if counts else g
+
     def tables_async(self, d_perms, stream=None):
         _check(lib().qap_batch_tables_async(self._b, _dptr(d_perms, "int32"), _stream_ptr(stream)),
                "qap_batch_tables_async")
@@ -359,22 +382,37 @@ class Batch:
 
 
 def tabu_batch(handles, perms, ks, iters, lo, hi, seeds):
-    """Blocking batched tabu (``qap_tabu_batch``): perms is the concatenation of every
+    """Blocking batched tabu (``qap_tabu_batch_concat``): perms is the concatenation of every
     instance's starts, flattened; returns (best permutations, best costs, moves made)."""
     m, hs, ks, lo, hi, seeds = _batch_args(handles, ks, lo, hi, seeds)
     p = np.array(perms, dtype=np.int32, copy=True).reshape(-1)
     total = int(sum(int(k) for k in ks))
     best = np.zeros(total, dtype=np.int64)
     done = np.zeros(total, dtype=np.int32)
-    _check(lib().qap_tabu_batch(hs, m, _ptr(p, _i32p), _ptr(ks, _i32p), int(iters), _ptr(lo, _i32p),
-                                _ptr(hi, _i32p), _ptr(seeds, _u64p), _ptr(best, _i64p), _ptr(done, _i32p)),
-           "qap_tabu_batch")
+    _check(lib().qap_tabu_batch_concat(hs, m, _ptr(p, _i32p), _ptr(ks, _i32p), int(iters), _ptr(lo, _i32p),
+                                       _ptr(hi, _i32p), _ptr(seeds, _u64p), _ptr(best, _i64p), _ptr(done, _i32p)),
+           "qap_tabu_batch_concat")
     return p, best, done
 
 
+def tabu_batch_lists(handles, perms_list, iters, lo, hi, seeds):
+    """Blocking batched tabu with per-instance arrays (``qap_tabu_batch``): perms_list[i] is
+    instance i's starts, int32[k_i][n_i]; returns (list of best permutations, list of best
+    costs)."""
+    ks = [len(p) for p in perms_list]
+    m, hs, ks_a, lo, hi, seeds = _batch_args(handles, ks, lo, hi, seeds)
+    ps = [np.array(p, dtype=np.int32, copy=True).reshape(k, h.n) for p, k, h in zip(perms_list, ks, handles)]
+    bs = [np.zeros(k, dtype=np.int64) for k in ks]
+    pp = (_i32p * max(m, 1))(*[_ptr(p, _i32p) for p in ps])
+    bp = (_i64p * max(m, 1))(*[_ptr(b, _i64p) for b in bs])
+    _check(lib().qap_tabu_batch(hs, m, pp, _ptr(ks_a, _i32p), int(iters), _ptr(lo, _i32p), _ptr(hi, _i32p),
+                                _ptr(seeds, _u64p), bp), "qap_tabu_batch")
+    return ps, bs
+
+
 class Server:
-    """Continuous-batching tabu server (``qap_server_*``): submit requests, call step()
-    repeatedly, collect results by ticket."""
+    """Continuous-batching tabu server (``qap_server_*``): submit requests, drive it with
+    step() (or start() its own thread), collect results by ticket with poll() or result()."""
 
     def __init__(self, pool_bytes: int = 1 << 30, max_active: int = 256, chunk_ms: float = 2.0):
         s = _vp()
@@ -384,19 +422,33 @@ class Server:
         self._n = {}
 
     def footprint(self, n: int, sym: bool = False) -> int:
-        """Device bytes a request of size n takes from the pool while admitted."""
+        """Device bytes a request of size n with its own matrices takes from the pool while admitted."""
         return _check(lib().qap_server_footprint(self._s, int(n), int(bool(sym))), "qap_server_footprint")
 
     def submit(self, F, D, start, iters: int, lo: int, hi: int, seed: int) -> int:
+        """A request with its own F and D (qap_server_submit_matrices); returns its ticket."""
         F = _arr(F, np.int32)
         n = F.shape[0]
         D = _arr(D, np.int32, (n, n))
         start = _arr(start, np.int32, (n,))
         t = ctypes.c_int64(0)
-        _check(lib().qap_server_submit(self._s, _ptr(F, _i32p), _ptr(D, _i32p), n, _ptr(start, _i32p), int(iters),
-                                       int(lo), int(hi), int(seed), ctypes.byref(t)), "qap_server_submit")
+        _check(lib().qap_server_submit_matrices(self._s, _ptr(F, _i32p), _ptr(D, _i32p), n, _ptr(start, _i32p),
+                                                int(iters), int(lo), int(hi), int(seed), ctypes.byref(t)),
+               "qap_server_submit_matrices")
         self._n[t.value] = n
         return t.value
+
+    def submit_handle(self, h: "Handle", start, iters: int, lo: int, hi: int, seed: int) -> int:
+        """A request on an existing handle (qap_server_submit); h must outlive the request."""
+        start = _arr(start, np.int32, (h.n,))
+        t = ctypes.c_int64(0)
+        _check(lib().qap_server_submit(self._s, h.ptr, _ptr(start, _i32p), int(iters), int(lo), int(hi), int(seed),
+                                       ctypes.byref(t)), "qap_server_submit")
+        self._n[t.value] = h.n
+        return t.value
+
+    def set_queue_limit(self, max_queued: int):
+        _check(lib().qap_server_set_queue_limit(self._s, int(max_queued)), "qap_server_set_queue_limit")
 
     def step(self):
         """One admission + chunk; returns (finished, running, queued)."""
@@ -404,23 +456,55 @@ class Server:
         f = _check(lib().qap_server_step(self._s, ctypes.byref(a), ctypes.byref(p)), "qap_server_step")
         return f, a.value, p.value
 
+    def start(self):
+        """Run the server's own stepping thread until stop()."""
+        _check(lib().qap_server_start(self._s), "qap_server_start")
+
+    def stop(self):
+        _check(lib().qap_server_stop(self._s), "qap_server_stop")
+
+    def poll(self, ticket: int):
+        """None while queued or running, else (best permutation, best cost)."""
+        n = self._n[ticket]
+        perm = np.zeros(n, dtype=np.int32)
+        best = ctypes.c_int64(0)
+        rc = lib().qap_server_poll(self._s, int(ticket), _ptr(perm, _i32p), ctypes.byref(best))
+        if rc == 0:
+            return None
+        del self._n[ticket]
+        _check(rc, "qap_server_poll")
+        return perm, best.value
+
     def result(self, ticket: int):
         """None while queued or running, else (best permutation, best cost, moves, latency ms, queued ms)."""
         n = self._n[ticket]
         perm = np.zeros(n, dtype=np.int32)
         best, moves = ctypes.c_int64(0), ctypes.c_int32(0)
         lat = (ctypes.c_double * 2)()
-        rc = _check(lib().qap_server_result(self._s, int(ticket), _ptr(perm, _i32p), ctypes.byref(best),
-                                            ctypes.byref(moves), lat), "qap_server_result")
+        rc = lib().qap_server_result(self._s, int(ticket), _ptr(perm, _i32p), ctypes.byref(best),
+                                     ctypes.byref(moves), lat)
         if rc == 0:
             return None
         del self._n[ticket]
+        _check(rc, "qap_server_result")
         return perm, best.value, moves.value, lat[0], lat[1]
 
+    def cancel(self, ticket: int) -> bool:
+        """True if the request was dropped, False if it had already finished."""
+        rc = _check(lib().qap_server_cancel(self._s, int(ticket)), "qap_server_cancel")
+        if rc == 1:
+            del self._n[ticket]
+        return rc == 1
+
+    def inject_failure(self, ticket: int):
+        """Test hook: corrupt a running request's saved state so that its search fails."""
+        _check(lib().qap_server_inject_failure(self._s, int(ticket)), "qap_server_inject_failure")
+
     def stats(self) -> dict:
-        out = np.zeros(6, dtype=np.int64)
+        out = np.zeros(9, dtype=np.int64)
         _check(lib().qap_server_stats(self._s, _ptr(out, _i64p)), "qap_server_stats")
-        return dict(zip(("running", "queued", "pool_used", "pool_bytes", "steps", "chunks"), out.tolist()))
+        return dict(zip(("running", "queued", "pool_used", "pool_bytes", "steps", "chunks", "finished", "failed",
+                         "cancelled"), out.tolist()))
 
     def close(self):
         if getattr(self, "_s", None) is not None:

@@ -30,7 +30,7 @@ def test_library_exports_every_header_symbol():
 
 def test_strerror_codes():
     L = qap.lib()
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.qap_strerror(code)
     assert L.qap_strerror(-99) == b"unknown error"
 
