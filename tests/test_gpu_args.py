@@ -57,8 +57,10 @@ def test_tabu_until_overflow_rejected_everywhere():
         done = np.zeros(k, dtype=np.int32)
         assert L.qap_tabu(h.ptr, _i32(p), k, 0, 0, I32MAX - 1, 1, _i64(best), _i32(done)) == 0
         assert (p == perms).all() and (done == 0).all() and (best == h.cost(perms)).all()
-    with qap.Server(1 << 26, 4, 1.0) as srv:
+    with qap.Server(1 << 26, 4, 1.0) as srv, qap.Handle(F, D) as h:
         t = ctypes.c_int64()
         for iters, lo, hi in bad:
-            assert L.qap_server_submit(srv._s, _i32(F), _i32(D), n, _i32(perms[0]), iters, lo, hi, 1,
+            assert L.qap_server_submit_matrices(srv._s, _i32(F), _i32(D), n, _i32(perms[0]), iters, lo, hi, 1,
+                                                ctypes.byref(t)) == qap.QAP_E_INVALID
+            assert L.qap_server_submit(srv._s, h.ptr, _i32(perms[0]), iters, lo, hi, 1,
                                        ctypes.byref(t)) == qap.QAP_E_INVALID

@@ -208,6 +208,89 @@ def test_batch_full_size_graph_replay_sampled():
         h.close()
 
 
+# Variant order of qap_batch_groups: tiles of 2, 4, 8 rows on 512 lanes, streamed, 2 rows on
+# 128 and 256 lanes, 4 rows on 256 and 768 lanes.
+VARIANTS = ["r2", "r4", "r8", "stream", "r2_128", "r2_256", "r4_256", "r4_768"]
+
+
+def tile_count(n, rows):
+    """Register tiles of rows x 4 that hold some move u < v."""
+    return sum(1 for g in range((n + rows - 1) // rows) for b in range((n + 3) // 4)
+               if g * rows < min(4 * b + 4, n) - 1)
+
+
+def variant_of(n, rows, sym):
+    """The batched kernel a search of this n and tile shape runs on (a lane per tile and per
+    (index, family) task, the smallest workgroup that holds them)."""
+    if rows < 0:
+        return "stream"
+    nt = tile_count(n, rows)
+    need = max(nt, (2 if sym else 4) * n)
+    if rows == 2:
+        return "r2_128" if need <= 128 else ("r2_256" if need <= 256 else "r2")
+    if rows == 4:
+        return "r4_256" if need <= 256 else ("r4" if nt <= 512 else "r4_768")
+    return "r8"
+
+
+def test_batch_full_size_every_variant_sampled():
+    """The full uneven batch with tile shapes spread over every batched kernel variant
+    (rows forced per instance in rotation, the first that fits), run once; 8 (instance,
+    start) pairs of every variant are recomputed by the oracle."""
+    import torch
+    w = W.c4_batch()
+    insts = w.instances
+    m, k = len(insts), len(insts[0].perms)
+    note("batch full size, every variant: %d instances x %d starts x %d iterations" % (m, k, w.iters))
+    hs = [qap.Handle(I.F, I.D) for I in insts]
+    order = [[2, 4, 8, -8], [4, 8, -8], [8, -8], [-8]]
+    rows, kind = [], []
+    for t, (I, h) in enumerate(zip(insts, hs)):
+        for r in order[t % 4]:
+            try:
+                h.set_tile_rows("batch", r)
+            except qap.QapError:
+                continue
+            rows.append(r)
+            break
+        sym = bool((I.F == I.F.T).all() and (I.D == I.D.T).all())
+        kind.append(variant_of(I.n, rows[-1], sym))
+    lo = [w.tenure(I.n)[0] for I in insts]
+    hi = [w.tenure(I.n)[1] for I in insts]
+    seeds = [I.seed for I in insts]
+    work = torch.from_numpy(np.concatenate([I.perms.reshape(-1) for I in insts])).cuda()
+    best = torch.empty(m * k, dtype=torch.int64, device="cuda")
+    done = torch.empty(m * k, dtype=torch.int32, device="cuda")
+    with qap.Batch(hs, [k] * m, w.iters, lo, hi, seeds) as b:
+        _, counts = b.groups(counts=True)
+        expect = [k * kind.count(v) for v in VARIANTS]
+        assert list(counts) == expect, (list(counts), expect)
+        assert all(c > 0 for c in counts), counts
+        b.run_async(work, best, done)
+        torch.cuda.synchronize()
+    ep, ec, ed = work.cpu().numpy(), best.cpu().numpy(), done.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum([k * I.n for I in insts])])
+    rng = np.random.default_rng(4)
+    sample = []
+    for v in VARIANTS:
+        ts = [t for t in range(m) if kind[t] == v]
+        pick = rng.choice(len(ts), size=min(8, len(ts)), replace=False)
+        sample += [(ts[int(i)], int(rng.integers(0, k))) for i in pick]
+    assert len(sample) >= 64
+
+    def one(a):
+        t, j = a
+        I = insts[t]
+        return oracle.tabu(I.F, I.D, I.perms[j], w.iters, lo[t], hi[t], I.seed, j)
+
+    for (t, j), r in zip(sample, pmap(one, sample)):
+        n = insts[t].n
+        got = ep[off[t] + j * n: off[t] + (j + 1) * n]
+        assert (got == r[0]).all() and ec[t * k + j] == r[1] and ed[t * k + j] == r[2], (t, j, kind[t])
+    for h in hs:
+        h.close()
+
+
 @pytest.mark.parametrize("n,sym", [(24, False), (64, False), (100, True), (150, False)])
 def test_tuner_picks_a_fitting_shape_and_results_do_not_change(n, sym):
     rng = np.random.default_rng(n)

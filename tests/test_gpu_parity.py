@@ -281,7 +281,7 @@ def test_tabu_config2_full_size_sampled():
         torch.cuda.synchronize()
         p, c, d = dp.cpu().numpy(), db.cpu().numpy(), dd.cpu().numpy()
         assert (h.cost(p) == c).all()
-    sample = [0, 37, 64, 101, 127]
+    sample = list(range(128))   # every start
     ep, ec, ed = oracle_tabu_many(I.F, I.D, I.perms[sample], w.iters, lo, hi, I.seed, sample)
     assert (p[sample] == ep).all() and (c[sample] == ec).all() and (d[sample] == ed).all()
     assert (d == w.iters).all()
@@ -301,7 +301,7 @@ def test_tabu_config3_full_size_sampled():
         torch.cuda.synchronize()
         p, c, d = dp.cpu().numpy(), db.cpu().numpy(), dd.cpu().numpy()
         assert (h.cost(p) == c).all()
-    sample = [0, 200]
+    sample = list(range(0, 256, 8))   # 32 of the 256 starts
     ep, ec, ed = oracle_tabu_many(I.F, I.D, I.perms[sample], w.iters, lo, hi, I.seed, sample)
     assert (p[sample] == ep).all() and (c[sample] == ec).all() and (d[sample] == ed).all()
 

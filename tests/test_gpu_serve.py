@@ -151,3 +151,28 @@ def test_serve_admission_bounded_by_slots():
     for i, r in enumerate(reqs):
         ep, ec, ed = alone(r)
         assert (got[i][0] == ep).all() and got[i][1] == ec and got[i][2] == ed, i
+
+
+def test_serve_c5_stream_head_equals_oracle():
+    """The first 48 requests of the serving stream (n from 30 to 256, 2000 to 20 000
+    iterations, F sparsity up to 80%), all submitted at once to a server with 2 ms chunks;
+    every result is recomputed by the oracle (start id 0)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    stream = W.c5_stream(count=48)
+    reqs = []
+    for r in stream:
+        lo, hi = W.tabu_tenure_range(r.inst.n)
+        reqs.append((r.inst.F, r.inst.D, r.inst.perms[0], r.iters, lo, hi, r.inst.seed))
+    note("serve the first %d requests of the serving stream, chunk 2 ms" % len(reqs))
+    got, _, _, stats = serve_all(reqs, pool_bytes=1 << 30, max_active=256, chunk_ms=2.0)
+    assert stats["chunks"] >= len(reqs)
+
+    def one(r):
+        F, D, p, it, lo, hi, seed = r
+        return oracle.tabu(F, D, p, it, lo, hi, seed, 0)
+
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+        want = list(ex.map(one, reqs))
+    for i, (g, e) in enumerate(zip(got, want)):
+        assert (g[0] == e[0]).all() and g[1] == e[1] and g[2] == e[2], (i, reqs[i][0].shape[0])
