@@ -54,8 +54,12 @@ enum {
     QAP_E_DEVICE = -4,    /* a HIP call failed */
     QAP_E_NOMEM = -5,     /* host or device allocation failed */
     QAP_E_BUSY = -6,      /* the server's queue is full (qap_server_submit*); nothing was queued */
-    QAP_E_UNSUPPORTED = -7 /* valid request this build cannot serve (see the entry point) */
+    QAP_E_UNSUPPORTED = -7, /* valid request this build cannot serve (see the entry point) */
+    QAP_E_SCRATCH = -8    /* qap_tabu_noalloc_async: the call needs more than its fixed scratch */
 };
+
+/* Bytes of the fixed device array that qap_tabu_noalloc_async takes its scratch from. */
+#define QAP_NOALLOC_SCRATCH_BYTES (64u << 20)
 
 typedef struct qap_ctx *qap_handle;
 
@@ -181,6 +185,22 @@ int qap_tabu_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int
 int qap_tabu_freq_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo,
                         int32_t hi, uint64_t seed, int64_t start_base, int32_t div, int32_t attr,
                         int64_t *d_best, int32_t *d_done, int32_t *d_freq, void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): qap_tabu_async with the same
+ * arguments, semantics and results, which calls no allocating routine.  Its scratch (the
+ * neighbourhood tables, int32[k][n(n-1)/2] rounded up to 256 bytes, and for the streamed
+ * kernels the tile state of every search, plus G and G^T above QAP_NMAX_BATCH) is carved
+ * from one fixed array of QAP_NOALLOC_SCRATCH_BYTES per GPU, which the library holds
+ * from the first qap_create on that GPU until the process ends.  A call that would need
+ * more returns QAP_E_SCRATCH and enqueues nothing.  Every call on one GPU shares that
+ * array: calls whose work overlaps on the device race and give undefined results, so
+ * order them (one stream, or events).  Nothing in the array needs to start at zero.
+ */
+int qap_tabu_noalloc_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo,
+                           int32_t hi, uint64_t seed, int64_t start_base, int64_t *d_best,
+                           int32_t *d_done, void *stream);
 
 /*
  * The plain delivery of qap_tabu_async: the same arithmetic and results, but one kernel

@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -218,13 +219,22 @@ int make_tables(qap_ctx *h, const int32_t *d_perms, int k, int32_t **d_table, hi
     return QAP_OK;
 }
 
-hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipStream_t st, bool plain);
+// Scratch buffers of the streamed kernels supplied by the caller (the entry point that
+// allocates nothing): tile state of every search of the launch, and G, G^T above WIDE_N.
+struct StreamScratch {
+    int4 *tile_work;
+    uint8_t *gwork;
+};
+
+hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipStream_t st, bool plain,
+                         const StreamScratch *pre = nullptr);
 
 hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t *d_table, int k, int iters,
                            int lo, int hi, uint64_t seed, int64_t start_base, int64_t *d_cost, int32_t *d_steps,
-                           hipStream_t st, bool plain, int32_t *d_freq = nullptr, int div = 0, int attr = 0) {
+                           hipStream_t st, bool plain, int32_t *d_freq = nullptr, int div = 0, int attr = 0,
+                           int ri = -1, const StreamScratch *pre = nullptr) {
     // one shape for the whole launch: its kernel and its tile list
-    const int ri = launch_shape(h, algo, k);
+    if (ri < 0) ri = launch_shape(h, algo, k);
     if (ri < 0) return hipErrorInvalidValue;
     SearchArgs a = base_args(h, ri);
     a.table = d_table;
@@ -250,13 +260,24 @@ hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t
         const hipError_t e2 = hipFreeAsync(a.uloc, st);
         return e != hipSuccess ? e : e2;
     }
-    return launch_shaped(h, algo, ri, a, k, st, plain);
+    return launch_shaped(h, algo, ri, a, k, st, plain, pre);
 }
 
 // The launches of one search call with tile shape ri (the streamed kernel takes its tile
-// state from stream-ordered scratch).
-hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipStream_t st, bool plain) {
+// state from stream-ordered scratch, or from `pre`).
+hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipStream_t st, bool plain,
+                         const StreamScratch *pre) {
     hipError_t e = hipSuccess;
+    if (ri == kStream && pre) {
+        a.tile_stride = stream_tile_int4(a.ntiles);
+        a.tile_work = pre->tile_work;
+        if (h->n > WIDE_N) {
+            a.gstride = wide_g_bytes(h->n, h->sym);
+            a.gwork = pre->gwork;
+        }
+        a.job0 = 0;
+        return launch_stream(algo == 0, a, k, st);
+    }
     if (ri == kStream) {
         // tile state in stream-ordered scratch, one slice per search of a launch
         a.tile_stride = stream_tile_int4(a.ntiles);
@@ -387,6 +408,36 @@ namespace {
 
 int item_variant(const Item &it) { return batch_variant(it.n, it.rows, it.stream != 0, it.ntiles, it.sym); }
 
+// ---- fixed scratch of qap_tabu_noalloc_async: one array per GPU, held until the process
+//      ends.  Host code never passes the array's name to a kernel (on the host it only
+//      names the symbol); the device address of each GPU's copy is looked up once, with
+//      that GPU current, and kept in noalloc_ptr.
+__device__ __align__(256) unsigned char scratch[QAP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mu;
+unsigned char *noalloc_ptr[kMaxDevices] = {};
+
+// Look up this device's copy of `scratch` (the current device); QAP_OK once known.
+int noalloc_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return QAP_E_DEVICE;
+    std::lock_guard<std::mutex> g(noalloc_mu);
+    if (noalloc_ptr[device]) return QAP_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return dev_err(e != hipSuccess ? e : hipErrorInvalidSymbol);
+    noalloc_ptr[device] = static_cast<unsigned char *>(ptr);
+    return QAP_OK;
+}
+
+unsigned char *noalloc_base(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(noalloc_mu);
+    return noalloc_ptr[device];
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 }  // namespace
 
 extern "C" {
@@ -401,6 +452,7 @@ const char *qap_strerror(int code) {
         case QAP_E_NOMEM: return "out of memory";
         case QAP_E_BUSY: return "server queue full";
         case QAP_E_UNSUPPORTED: return "unsupported by this build";
+        case QAP_E_SCRATCH: return "the call needs more than the fixed scratch of qap_tabu_noalloc_async";
         default: return "unknown error";
     }
 }
@@ -446,6 +498,12 @@ int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out) {
     if (e != hipSuccess) {
         qap_destroy(h);
         return dev_err(e);
+    }
+    // once per device, with it current: the address of its fixed scratch array
+    const int src = noalloc_setup(h->device);
+    if (src != QAP_OK) {
+        qap_destroy(h);
+        return src;
     }
     h->stream_ok = stream_shape_ok(n, h->sym, h->max_smem);
     const int d = default_rows(h);   // -1: no search kernel shape fits this n
@@ -640,6 +698,36 @@ int qap_tabu_with_table_async(qap_handle h, int32_t *d_perms, const int32_t *d_t
     if (k == 0) return QAP_OK;
     return dev_err(launch_searches(h, 0, d_perms, d_table, k, iters, lo, hi, seed, start_base, d_best, d_done,
                                    (hipStream_t)stream, false));
+}
+
+int qap_tabu_noalloc_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo, int32_t hi,
+                           uint64_t seed, int64_t start_base, int64_t *d_best, int32_t *d_done, void *stream) {
+    if (!tabu_args_ok(h, d_perms, k, iters, lo, hi, d_best)) return QAP_E_INVALID;
+    if (h->rows_choice[0] < 0) return QAP_E_UNSUPPORTED;
+    if (k == 0) return QAP_OK;
+    unsigned char *base = noalloc_base(h->device);
+    if (!base) return QAP_E_DEVICE;
+    // the shape of this launch decides what it needs beside the tables
+    const int ri = launch_shape(h, 0, k);
+    if (ri < 0) return QAP_E_UNSUPPORTED;
+    const size_t table_bytes = align256((size_t)k * h->m * sizeof(int32_t));
+    size_t tile_bytes = 0, g_bytes = 0;
+    if (ri == kStream) {
+        tile_bytes = align256((size_t)k * stream_tile_int4(shape_tiles(h, ri).ntiles) * sizeof(int4));
+        if (h->n > WIDE_N) g_bytes = (size_t)k * wide_g_bytes(h->n, h->sym);
+    }
+    if (table_bytes + tile_bytes + g_bytes > (size_t)QAP_NOALLOC_SCRATCH_BYTES) return QAP_E_SCRATCH;
+    // every byte used is written before it is read (tables by the table kernel, tile state
+    // and G when each search starts), so nothing needs clearing
+    int32_t *d_table = reinterpret_cast<int32_t *>(base);
+    StreamScratch pre{reinterpret_cast<int4 *>(base + table_bytes), base + table_bytes + tile_bytes};
+    const hipStream_t st = (hipStream_t)stream;
+    TableArgs ta{h->d_mats, d_perms, nullptr, d_table, h->n, h->m, k, h->sym};
+    hipError_t e = launch_table(ta, st);
+    if (e == hipSuccess)
+        e = launch_searches(h, 0, d_perms, d_table, k, iters, lo, hi, seed, start_base, d_best, d_done, st, false,
+                            nullptr, 0, 0, ri, &pre);
+    return dev_err(e);
 }
 
 // ---- blocking host entry points: validate, copy in, run on a private stream, copy out

@@ -25,12 +25,15 @@ QAP_E_DEVICE = -4
 QAP_E_NOMEM = -5
 QAP_E_BUSY = -6
 QAP_E_UNSUPPORTED = -7
+QAP_E_SCRATCH = -8
+QAP_NOALLOC_SCRATCH_BYTES = 64 << 20
 QAP_NMAX = 512
 QAP_NMAX_BATCH = 256   # batched and served searches
 
 EXPORTS = [
     "qap_strerror", "qap_create", "qap_destroy", "qap_size", "qap_cost", "qap_cost_async", "qap_delta_table",
-    "qap_delta_table_async", "qap_2opt", "qap_2opt_async", "qap_tabu", "qap_tabu_async", "qap_tabu_freq_async",
+    "qap_delta_table_async", "qap_2opt", "qap_2opt_async", "qap_tabu", "qap_tabu_async", "qap_tabu_noalloc_async",
+    "qap_tabu_freq_async",
     "qap_tabu_plain_async", "qap_2opt_with_table_async", "qap_tabu_with_table_async", "qap_set_tile_rows",
     "qap_get_tile_rows", "qap_launch_tile_rows", "qap_batch_create", "qap_batch_size", "qap_batch_groups",
     "qap_batch_run_async",
@@ -81,6 +84,8 @@ def lib():
                 "qap_2opt_async": (ctypes.c_int, [_vp, _vp, i32, i32, _vp, _vp, _vp]),
                 "qap_tabu": (ctypes.c_int, [_vp, _i32p, i32, i32, i32, i32, u64, _i64p, _i32p]),
                 "qap_tabu_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, _vp, _vp, _vp]),
+                "qap_tabu_noalloc_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, _vp, _vp,
+                                                          _vp]),
                 "qap_tabu_freq_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, i32, i32, _vp,
                                                         _vp, _vp, _vp]),
                 "qap_tabu_plain_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, _vp, _vp,
@@ -286,6 +291,15 @@ class Handle:
         _check(f(self.ptr, _dptr(d_perms, "int32"), d_perms.shape[0], int(iters), int(lo), int(hi), int(seed),
                  int(start_base), _dptr(d_best, "int64"), _dptr(d_done, "int32"), _stream_ptr(stream)),
                "qap_tabu_async")
+
+    def tabu_noalloc_async(self, d_perms, iters, lo, hi, seed, d_best, d_done=None, start_base: int = 0,
+                           stream=None):
+        """tabu_async with its scratch taken from the library's fixed device array
+        (``qap_tabu_noalloc_async``); raises QapError(QAP_E_SCRATCH) if it would not fit."""
+        _check(lib().qap_tabu_noalloc_async(self.ptr, _dptr(d_perms, "int32"), d_perms.shape[0], int(iters),
+                                            int(lo), int(hi), int(seed), int(start_base), _dptr(d_best, "int64"),
+                                            _dptr(d_done, "int32"), _stream_ptr(stream)),
+               "qap_tabu_noalloc_async")
 
     def tabu_freq_async(self, d_perms, iters, lo, hi, seed, d_best, d_freq, d_done=None, start_base: int = 0,
                         div: int = 0, attr: int = 0, stream=None):

@@ -30,7 +30,7 @@ def test_library_exports_every_header_symbol():
 
 def test_strerror_codes():
     L = qap.lib()
-    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert L.qap_strerror(code)
     assert L.qap_strerror(-99) == b"unknown error"
 
@@ -71,3 +71,14 @@ def test_binding_size_limits_match_the_header():
     defs = dict(re.findall(r"#define (QAP_NMAX\w*) (\d+)", txt))
     assert int(defs["QAP_NMAX"]) == qap.QAP_NMAX == 512
     assert int(defs["QAP_NMAX_BATCH"]) == qap.QAP_NMAX_BATCH == 256
+
+
+def test_noalloc_scratch_size_matches_the_header():
+    txt = open(os.path.join(ROOT, "include", "qap.h")).read()
+    m = re.search(r"#define QAP_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == qap.QAP_NOALLOC_SCRATCH_BYTES
+
+
+def test_noalloc_rejects_bad_arguments():
+    L = qap.lib()
+    assert L.qap_tabu_noalloc_async(None, None, 1, 10, 1, 2, 0, 0, None, None, None) == qap.QAP_E_INVALID
