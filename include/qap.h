@@ -254,6 +254,29 @@ typedef struct qap_batch *qap_batch_handle;
 int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *k_per, int32_t iters,
                      const int32_t *lo_per, const int32_t *hi_per, const uint64_t *seed_per,
                      const int32_t *rows_per, qap_batch_handle *out);
+/*
+ * qap_batch_create for searches that keep the frequency memory of Sec. 4.3 and may use
+ * the extensions of qap_tabu_freq_async: instance i's searches run with diversification
+ * patience div_per[i] and tabu attribute attr_per[i] (as div and attr of
+ * qap_tabu_freq_async; either array may be NULL for 0 everywhere).  Every result equals
+ * qap_tabu_freq_async on the instance alone with start_base 0.  The plan owns the counts
+ * of every search (int32 per packed pair) and, for attr 2, the unit x location table of
+ * every such search (n_i * n_i int32).  All searches of such a plan run in one launch of
+ * 512-lane workgroups with tiles of 2, 4 or 8 rows or the streamed form (rows_per as for
+ * qap_batch_create; by default the library's shape, or the next larger tile that fits 512
+ * lanes).  QAP_E_INVALID for div < 0 or attr outside 0..2, otherwise as qap_batch_create.
+ * qap_batch_run_async, qap_batch_tables_async and qap_batch_search_async run such plans
+ * as any other; qap_batch_groups returns 1 and counts the searches per tile shape in the
+ * slots of the 512-lane kernels and the streamed form.
+ * qap_batch_freq_async enqueues on `stream` a copy of the counts of the plan's last run
+ * into d_freq (device int32[sum_i k_i n_i (n_i - 1) / 2]: instance order, start order,
+ * packed pair order); QAP_E_INVALID for a plan made by qap_batch_create.
+ */
+int qap_batch_create_freq(const qap_handle *hs, int32_t m, const int32_t *k_per, int32_t iters,
+                          const int32_t *lo_per, const int32_t *hi_per, const uint64_t *seed_per,
+                          const int32_t *rows_per, const int32_t *div_per, const int32_t *attr_per,
+                          qap_batch_handle *out);
+int qap_batch_freq_async(qap_batch_handle b, int32_t *d_freq, void *stream);
 int qap_batch_size(qap_batch_handle b, int64_t *starts_out, int64_t *perm_ints_out);
 /* Kernel dispatches of one qap_batch_search_async: returns the number of tile-shape
  * variants the plan uses (one dispatch each, forked onto side streams of `stream` and

@@ -402,6 +402,13 @@ struct qap_batch {
     size_t group_smem[BV_COUNT] = {};
     hipStream_t side[BV_COUNT] = {};
     hipEvent_t ev_fork = nullptr, ev_join[BV_COUNT] = {};
+    // plans made by qap_batch_create_freq: every search keeps its frequency memory (and may
+    // diversify or use a unit attribute); all run in one launch of batch_freq_kernel
+    bool freq_mode = false;
+    size_t freq_smem = 0;
+    long long freq_ints = 0;        // counts of every search, instance order, start order
+    int32_t *d_freq = nullptr;
+    int32_t *d_uloc = nullptr;      // attr 2: unit x location table of every such search
 };
 
 namespace {
@@ -810,26 +817,54 @@ int qap_tabu(qap_handle h, int32_t *perms, int32_t k, int32_t iters, int32_t lo,
 
 // ---- batched tabu over many instances of uneven n
 
-extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *k_per, int32_t iters,
-                                const int32_t *lo_per, const int32_t *hi_per, const uint64_t *seed_per,
-                                const int32_t *rows_per, qap_batch_handle *out) {
+namespace {
+
+// Whether tile shape ri serves this instance in batch_freq_kernel (BATCH_LANES lanes,
+// rows 2, 4, 8 or the streamed form).
+bool batch_freq_fits(const qap_ctx *h, int ri) {
+    if (h->n > WIDE_N) return false;
+    if (ri == kStream) return h->stream_ok != 0;
+    if (ri < kBatchFirst || ri > kBatchFirst + 2) return false;
+    const TileSet &ts = h->tiles[ri];
+    const int rows = kRowsChoices[ri];
+    return ts.d_tiles && batch_shape_ok(h->n, rows, ts.ntiles, h->sym) &&
+           search_smem_bytes(h->n, rows, BATCH_LANES, h->sym) <= h->max_smem;
+}
+
+int batch_create_impl(const qap_handle *hs, int32_t m, const int32_t *k_per, int32_t iters, const int32_t *lo_per,
+                      const int32_t *hi_per, const uint64_t *seed_per, const int32_t *rows_per, bool freq,
+                      const int32_t *div_per, const int32_t *attr_per, qap_batch_handle *out) {
     if (!hs || !k_per || !lo_per || !hi_per || !seed_per || !out || m < 0 || iters < 0) return QAP_E_INVALID;
     *out = nullptr;
     std::vector<Item> items;
-    long long perm_off = 0, out_off = 0, table_off = 0, tile_off = 0;
-    size_t gsmem[BV_COUNT] = {}, tsmem = 0;
+    long long perm_off = 0, out_off = 0, table_off = 0, tile_off = 0, freq_off = 0, uloc_off = 0;
+    size_t gsmem[BV_COUNT] = {}, tsmem = 0, fsmem = 0;
     for (int i = 0; i < m; ++i) {
         qap_ctx *h = hs[i];
         if (!h || k_per[i] < 0 || !tenure_args_ok(iters, lo_per[i], hi_per[i])) return QAP_E_INVALID;
-        const int ri = rows_per && rows_per[i] != 0 ? rows_index(rows_per[i]) : batch_shape(h);
-        if (ri < 0 || !batch_fits(h, ri)) return QAP_E_UNSUPPORTED;
+        const int div = div_per ? div_per[i] : 0, attr = attr_per ? attr_per[i] : 0;
+        if (div < 0 || attr < 0 || attr > 2) return QAP_E_INVALID;
+        int ri = rows_per && rows_per[i] != 0 ? rows_index(rows_per[i]) : batch_shape(h);
+        if (freq && !(rows_per && rows_per[i] != 0) && ri >= 0 && !batch_freq_fits(h, ri)) {
+            // the library's shape needs more than BATCH_LANES lanes: the next larger tile
+            // that fits, else the streamed form
+            int alt = -1;
+            for (int c = ri + 1; c <= kBatchFirst + 2 && alt < 0; ++c)
+                if (batch_freq_fits(h, c)) alt = c;
+            ri = alt >= 0 ? alt : kStream;
+        }
+        if (ri < 0 || !(freq ? batch_freq_fits(h, ri) : batch_fits(h, ri))) return QAP_E_UNSUPPORTED;
         const bool streamed = ri == kStream;
         const TileSet &ts = shape_tiles(h, ri);
         const int rows = streamed ? STREAM_ROWS : kRowsChoices[ri];
         const int var = batch_variant(h->n, rows, streamed, ts.ntiles, h->sym);
         const size_t sm = streamed ? stream_smem_bytes(h->n, h->sym)
-                                   : search_smem_bytes(h->n, rows, batch_variant_lanes(var), h->sym);
-        gsmem[var] = std::max(gsmem[var], sm);
+                                   : search_smem_bytes(h->n, rows, freq ? BATCH_LANES : batch_variant_lanes(var),
+                                                       h->sym);
+        if (freq)
+            fsmem = std::max(fsmem, sm);
+        else
+            gsmem[var] = std::max(gsmem[var], sm);
         tsmem = std::max(tsmem, table_smem_bytes(h->n));
         for (int j = 0; j < k_per[i]; ++j) {
             Item it{};
@@ -854,6 +889,18 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
             it.perm_off = perm_off;
             it.out_off = out_off;
             it.table_off = table_off;
+            if (freq) {
+                // offsets into the plan's count and unit-location buffers, made absolute
+                // once they are allocated
+                it.div = div;
+                it.attr = attr;
+                it.freq_off = freq_off;
+                freq_off += h->m;
+                if (attr == 2) {
+                    it.uloc_off = uloc_off;
+                    uloc_off += (long long)h->n * h->n;
+                }
+            }
             items.push_back(it);
             perm_off += h->n;
             out_off += 1;
@@ -862,8 +909,8 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
     }
     // grouped by kernel variant; longest first inside a group (the hardware starts blocks
     // in index order)
-    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
-        const int va = item_variant(a), vb = item_variant(b);
+    std::stable_sort(items.begin(), items.end(), [freq](const Item &a, const Item &b) {
+        const int va = freq ? 0 : item_variant(a), vb = freq ? 0 : item_variant(b);
         if (va != vb) return va < vb;
         return (long long)a.n * a.n > (long long)b.n * b.n;
     });
@@ -874,6 +921,9 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
     b->table_ints = table_off;
     b->tile_int4 = tile_off;
     b->table_smem = tsmem;
+    b->freq_mode = freq;
+    b->freq_smem = fsmem;
+    b->freq_ints = freq_off;
     for (int i = (int)items.size() - 1; i >= 0; --i) {
         const int v = item_variant(items[i]);
         b->group_begin[v] = i;
@@ -890,7 +940,7 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
     };
     std::stable_sort(b->group_order, b->group_order + BV_COUNT, [&](int x, int y) { return longest(x) > longest(y); });
     hipError_t e = hipSuccess;
-    if (ngroups > 1) {
+    if (ngroups > 1 && !freq) {
         e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
         for (int v = 0; v < BV_COUNT && e == hipSuccess; ++v) {
             if (!b->group_count[v]) continue;
@@ -902,6 +952,14 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
         if (e == hipSuccess) e = hipMalloc((void **)&b->d_items, items.size() * sizeof(Item));
         if (e == hipSuccess) e = hipMalloc((void **)&b->d_table, (size_t)table_off * sizeof(int32_t) + 16);
         if (e == hipSuccess && tile_off > 0) e = hipMalloc((void **)&b->d_tile_work, (size_t)tile_off * sizeof(int4));
+        if (e == hipSuccess && freq) e = hipMalloc((void **)&b->d_freq, (size_t)freq_off * sizeof(int32_t) + 16);
+        if (e == hipSuccess && uloc_off > 0)
+            e = hipMalloc((void **)&b->d_uloc, (size_t)uloc_off * sizeof(int32_t) + 16);
+        if (e == hipSuccess && freq)
+            for (Item &it : items) {
+                it.freq = b->d_freq + it.freq_off;
+                if (it.attr == 2) it.uloc = b->d_uloc + it.uloc_off;
+            }
         if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
@@ -910,6 +968,28 @@ extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *
     }
     *out = b;
     return QAP_OK;
+}
+
+}  // namespace
+
+extern "C" int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *k_per, int32_t iters,
+                                const int32_t *lo_per, const int32_t *hi_per, const uint64_t *seed_per,
+                                const int32_t *rows_per, qap_batch_handle *out) {
+    return batch_create_impl(hs, m, k_per, iters, lo_per, hi_per, seed_per, rows_per, false, nullptr, nullptr, out);
+}
+
+extern "C" int qap_batch_create_freq(const qap_handle *hs, int32_t m, const int32_t *k_per, int32_t iters,
+                                     const int32_t *lo_per, const int32_t *hi_per, const uint64_t *seed_per,
+                                     const int32_t *rows_per, const int32_t *div_per, const int32_t *attr_per,
+                                     qap_batch_handle *out) {
+    return batch_create_impl(hs, m, k_per, iters, lo_per, hi_per, seed_per, rows_per, true, div_per, attr_per, out);
+}
+
+extern "C" int qap_batch_freq_async(qap_batch_handle b, int32_t *d_freq, void *stream) {
+    if (!b || !b->freq_mode || (b->freq_ints > 0 && !d_freq)) return QAP_E_INVALID;
+    if (b->freq_ints == 0) return QAP_OK;
+    return dev_err(hipMemcpyAsync(d_freq, b->d_freq, (size_t)b->freq_ints * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, (hipStream_t)stream));
 }
 
 extern "C" int qap_batch_size(qap_batch_handle b, int64_t *starts_out, int64_t *perm_ints_out) {
@@ -921,6 +1001,18 @@ extern "C" int qap_batch_size(qap_batch_handle b, int64_t *starts_out, int64_t *
 
 extern "C" int qap_batch_groups(qap_batch_handle b, int32_t *count_out) {
     if (!b) return QAP_E_INVALID;
+    if (b->freq_mode) {   // one launch of every search: the searches per tile shape
+        if (count_out) {
+            for (int v = 0; v < BV_COUNT; ++v) count_out[v] = 0;
+            for (int v = 0; v < BV_COUNT; ++v) {
+                if (!b->group_count[v]) continue;
+                const int rows = v == BV_R4 || v == BV_R4_256 || v == BV_R4_768 ? 4 : (v == BV_R8 ? 8 : 2);
+                count_out[v == BV_STREAM ? BV_STREAM : (rows == 2 ? BV_R2 : (rows == 4 ? BV_R4 : BV_R8))] +=
+                    b->group_count[v];
+            }
+        }
+        return b->count > 0 ? 1 : 0;
+    }
     int groups = 0;
     for (int v = 0; v < BV_COUNT; ++v) {
         if (count_out) count_out[v] = b->group_count[v];
@@ -941,6 +1033,10 @@ extern "C" int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int6
     if (!b || (b->count > 0 && (!d_perms || !d_best))) return QAP_E_INVALID;
     if (b->count == 0) return QAP_OK;
     hipStream_t st = (hipStream_t)stream;
+    if (b->freq_mode) {
+        BatchArgs a{b->d_items, b->count, d_perms, d_best, d_done, b->d_table, b->d_tile_work};
+        return dev_err(launch_batch_freq(a, b->freq_smem, st));
+    }
     int ngroups = 0;
     for (int v = 0; v < BV_COUNT; ++v) ngroups += b->group_count[v] > 0;
     hipError_t e = hipSuccess;
@@ -973,6 +1069,8 @@ extern "C" int qap_batch_destroy(qap_batch_handle b) {
     if (b->d_items) (void)hipFree(b->d_items);
     if (b->d_table) (void)hipFree(b->d_table);
     if (b->d_tile_work) (void)hipFree(b->d_tile_work);
+    if (b->d_freq) (void)hipFree(b->d_freq);
+    if (b->d_uloc) (void)hipFree(b->d_uloc);
     for (int v = 0; v < BV_COUNT; ++v) {
         if (b->side[v]) (void)hipStreamDestroy(b->side[v]);
         if (b->ev_join[v]) (void)hipEventDestroy(b->ev_join[v]);

@@ -195,6 +195,9 @@ struct Item {
     // to a location it left (a move is tabu when both units would return)
     int attr;
     int32_t *uloc;            // attr 2: [n][n], unit x location -> until when it may not return
+    // batched plans that keep the frequency memory: offsets of freq and uloc in the
+    // plan's buffers (host side, while the plan is built)
+    long long freq_off, uloc_off;
     uint8_t *gmat;            // wide streamed kernel: G, then G^T (unless symmetric), rows of RS bytes
 };
 
@@ -237,6 +240,10 @@ int batch_variant(int n, int rows, bool streamed, int ntiles, int sym);
 // Lanes of a workgroup of that variant.
 int batch_variant_lanes(int variant);
 hipError_t launch_batch_group(int variant, const BatchArgs &b, size_t smem, hipStream_t st);
+// Batched searches that keep the frequency memory (Item::freq, and Item::div, Item::attr,
+// Item::uloc): one launch of BATCH_LANES lanes over items of tile rows 2, 4, 8 and the
+// streamed form.
+hipError_t launch_batch_freq(const BatchArgs &b, size_t smem, hipStream_t st);
 int search_max_lanes(int rows);
 // Workgroups of the register-tile search kernel for this shape that fit on one compute
 // unit at once (HIP's occupancy query; 0 if it fails).

@@ -1241,6 +1241,31 @@ batch_group_kernel(BatchArgs b) {
     search_body<ROWS, true, MAXT, false, STREAM, ROWS <= 4 && LANES <= 512 && (MAXT > 1 || ROWS == 4)>(it, sm);
 }
 
+// The batched launch of plans whose searches keep the frequency memory (and may use the
+// diversification move or a unit attribute): one kernel for every tile shape, 512
+// lanes, the shape taken from the item; the items' freq and uloc pointers are absolute.
+__global__ void __launch_bounds__(BATCH_LANES) batch_freq_kernel(BatchArgs b) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    Item it = b.items[blockIdx.x];
+    it.perm_in = b.perms + it.perm_off;
+    it.perm_out = b.perms + it.perm_off;
+    it.cost_out = b.best + it.out_off;
+    it.steps_out = b.done ? b.done + it.out_off : nullptr;
+    it.table = b.table + it.table_off;
+    constexpr int T = 1024 / BATCH_LANES;
+    if (it.stream) {
+        it.tile_d = b.tile_work + it.tile_off;
+        it.tile_u = it.tile_d + stream_tile_int4(it.ntiles) / 2;
+        search_body<STREAM_ROWS, true, T, false, true, false, true>(it, sm);
+        return;
+    }
+    switch (it.rows) {
+        case 2: search_body<2, true, T, false, false, false, true>(it, sm); break;
+        case 4: search_body<4, true, T, false, false, false, true>(it, sm); break;
+        default: search_body<8, true, T, false, false, false, true>(it, sm); break;
+    }
+}
+
 // Chunked runs: block i runs one chunk of items[i] (absolute pointers, st != null).
 __global__ void __launch_bounds__(BATCH_LANES) resume_kernel(const Item *items) {
     extern __shared__ __align__(16) unsigned char sm[];
@@ -1401,6 +1426,12 @@ hipError_t launch_batch_group(int variant, const BatchArgs &b, size_t smem, hipS
     return report(hipGetLastError(), "batch kernel launch");
 }
 
+
+hipError_t launch_batch_freq(const BatchArgs &b, size_t smem, hipStream_t st) {
+    if (b.count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_freq_kernel, dim3(b.count), dim3(BATCH_LANES), smem, st, b);
+    return report(hipGetLastError(), "batch kernel launch");
+}
 
 hipError_t launch_resume(const Item *d_items, int count, size_t smem, hipStream_t st) {
     if (count <= 0) return hipSuccess;

@@ -35,7 +35,7 @@ EXPORTS = [
     "qap_delta_table_async", "qap_2opt", "qap_2opt_async", "qap_tabu", "qap_tabu_async", "qap_tabu_noalloc_async",
     "qap_tabu_freq_async",
     "qap_tabu_plain_async", "qap_2opt_with_table_async", "qap_tabu_with_table_async", "qap_set_tile_rows",
-    "qap_get_tile_rows", "qap_launch_tile_rows", "qap_batch_create", "qap_batch_size", "qap_batch_groups",
+    "qap_get_tile_rows", "qap_launch_tile_rows", "qap_batch_create", "qap_batch_create_freq", "qap_batch_freq_async", "qap_batch_size", "qap_batch_groups",
     "qap_batch_run_async",
     "qap_batch_tables_async", "qap_batch_search_async", "qap_batch_destroy", "qap_tabu_batch",
     "qap_tabu_batch_concat",
@@ -115,6 +115,9 @@ def lib():
                 "qap_server_destroy": (ctypes.c_int, [_vp]),
                 "qap_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), i32, _i32p, i32, _i32p, _i32p, _u64p,
                                                     _i32p, ctypes.POINTER(_vp)]),
+                "qap_batch_create_freq": (ctypes.c_int, [ctypes.POINTER(_vp), i32, _i32p, i32, _i32p, _i32p, _u64p,
+                                                         _i32p, _i32p, _i32p, ctypes.POINTER(_vp)]),
+                "qap_batch_freq_async": (ctypes.c_int, [_vp, _vp, _vp]),
                 "qap_batch_size": (ctypes.c_int, [_vp, _i64p, _i64p]),
                 "qap_batch_groups": (ctypes.c_int, [_vp, _i32p]),
                 "qap_batch_run_async": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -344,14 +347,31 @@ class Batch:
 
     Instance i (``handles[i]``) runs ``ks[i]`` starts with tenure range [lo[i], hi[i]]
     and seed seeds[i]; starts and results are concatenated in instance order.
+
+    With ``freq=True`` every search keeps the frequency memory and may use the extensions
+    of ``tabu_freq_async`` (``div`` and ``attr`` per instance, or None for 0):
+    ``qap_batch_create_freq``; ``freq_async`` copies the counts out.
     """
 
-    def __init__(self, handles, ks, iters, lo, hi, seeds, rows=None):
+    def __init__(self, handles, ks, iters, lo, hi, seeds, rows=None, freq=False, div=None, attr=None):
         m, hs, ks, lo, hi, seeds = _batch_args(handles, ks, lo, hi, seeds)
         rows_p = None if rows is None else _ptr(_arr(rows, np.int32, (m,)), _i32p)
         b = _vp()
-        _check(lib().qap_batch_create(hs, m, _ptr(ks, _i32p), int(iters), _ptr(lo, _i32p), _ptr(hi, _i32p),
-                                      _ptr(seeds, _u64p), rows_p, ctypes.byref(b)), "qap_batch_create")
+        self.freq_ints = 0
+        if freq:
+            div_a = None if div is None else _arr(div, np.int32, (m,))
+            attr_a = None if attr is None else _arr(attr, np.int32, (m,))
+            _check(lib().qap_batch_create_freq(hs, m, _ptr(ks, _i32p), int(iters), _ptr(lo, _i32p), _ptr(hi, _i32p),
+                                               _ptr(seeds, _u64p), rows_p,
+                                               None if div_a is None else _ptr(div_a, _i32p),
+                                               None if attr_a is None else _ptr(attr_a, _i32p), ctypes.byref(b)),
+                   "qap_batch_create_freq")
+            self.freq_ints = int(sum(int(k) * h.m for k, h in zip(ks, handles)))
+        else:
+            if div is not None or attr is not None:
+                raise ValueError("div and attr need freq=True")
+            _check(lib().qap_batch_create(hs, m, _ptr(ks, _i32p), int(iters), _ptr(lo, _i32p), _ptr(hi, _i32p),
+                                          _ptr(seeds, _u64p), rows_p, ctypes.byref(b)), "qap_batch_create")
         self._b = b
         self._handles = list(handles)   # the plan refers to their device matrices
         s, p = ctypes.c_int64(0), ctypes.c_int64(0)
@@ -368,6 +388,12 @@ class Batch:
         c = np.zeros(8, dtype=np.int32)
         g = _check(lib().qap_batch_groups(self._b, _ptr(c, _i32p)), "qap_batch_groups")
         return (g, c) if counts else g
+
+    def freq_async(self, d_freq, stream=None):
+        """Copy the frequency memory of the last run (int32[sum k_i m_i], instance order,
+        start order, packed pair order) into d_freq (``qap_batch_freq_async``)."""
+        _check(lib().qap_batch_freq_async(self._b, _dptr(d_freq, "int32"), _stream_ptr(stream)),
+               "qap_batch_freq_async")
 
     def tables_async(self, d_perms, stream=None):
         _check(lib().qap_batch_tables_async(self._b, _dptr(d_perms, "int32"), _stream_ptr(stream)),

@@ -328,3 +328,62 @@ def test_tile_cache_round_trip(tmp_path):
     assert [h.tile_rows("batch")[0] for h in hs] == rows1
     for h in hs:
         h.close()
+
+
+@pytest.mark.parametrize("sizes,k,iters,divs,attrs", [
+    # every attribute and diversification in one batch, n across the register shapes
+    ([12, 40, 64, 33, 97, 128, 150, 5], [2, 2, 1, 2, 2, 1, 2, 3], 600,
+     [0, 25, 0, 40, 30, 0, 50, 10], [0, 0, 1, 1, 2, 2, 0, 1]),
+    # the streamed form (n above 176) beside register tiles, Zhu's short tenure for attr 1
+    ([200, 180, 60, 21], [1, 2, 2, 2], 300, [0, 20, 15, 0], [2, 1, 0, 2]),
+])
+def test_batch_freq_equals_oracle(sizes, k, iters, divs, attrs):
+    """Batched searches with the frequency memory, the diversification move and the unit
+    attributes (qap_batch_create_freq) against oracle.tabu_freq start by start: best
+    permutation, best cost, moves made and the exchange counts."""
+    import torch
+    insts, lohi, seeds = mixed_batch(7 * sum(sizes) + 1, sizes, k)
+    for t, n in enumerate(sizes):
+        if attrs[t] == 1 and t % 2 == 1:
+            lohi[t] = (3, 3 + n // 10)
+    note("batch freq sizes=%s k=%s iters=%d div=%s attr=%s" % (sizes, k, iters, divs, attrs))
+    hs = [qap.Handle(F, D) for F, D, _ in insts]
+    b = qap.Batch(hs, k, iters, [a for a, _ in lohi], [c for _, c in lohi], seeds, freq=True, div=divs, attr=attrs)
+    perms = torch.from_numpy(np.concatenate([P.reshape(-1) for _, _, P in insts]).astype(np.int32)).cuda()
+    best = torch.zeros(b.starts, dtype=torch.int64, device="cuda")
+    done = torch.zeros(b.starts, dtype=torch.int32, device="cuda")
+    freq = torch.full((b.freq_ints,), -1, dtype=torch.int32, device="cuda")
+    b.run_async(perms, best, done)
+    b.freq_async(freq)
+    torch.cuda.synchronize()
+    gp, gb, gd, gf = perms.cpu().numpy(), best.cpu().numpy(), done.cpu().numpy(), freq.cpu().numpy()
+    jobs = [(i, j) for i in range(len(insts)) for j in range(k[i])]
+
+    def one(a):
+        i, j = a
+        F, D, P = insts[i]
+        return oracle.tabu_freq(F, D, P[j], iters, lohi[i][0], lohi[i][1], seeds[i], start=j, div=divs[i],
+                                attr=attrs[i])
+
+    res = pmap(one, jobs)
+    po = fo = 0
+    for t, ((i, j), r) in enumerate(zip(jobs, res)):
+        n = sizes[i]
+        m = n * (n - 1) // 2
+        bp, bc, bd, bf, _ = r
+        assert (gp[po:po + n] == bp).all(), "instance %d start %d: permutation" % (i, j)
+        assert gb[t] == bc and gd[t] == bd, "instance %d start %d: (%d, %d) vs oracle (%d, %d)" % (
+            i, j, gb[t], gd[t], bc, bd)
+        assert (gf[fo:fo + m] == bf).all(), "instance %d start %d: exchange counts" % (i, j)
+        po += n
+        fo += m
+    assert fo == b.freq_ints
+    # a second run of the same plan resets the counts and gives the same results
+    perms2 = torch.from_numpy(np.concatenate([P.reshape(-1) for _, _, P in insts]).astype(np.int32)).cuda()
+    b.run_async(perms2, best, done)
+    b.freq_async(freq)
+    torch.cuda.synchronize()
+    assert (perms2.cpu().numpy() == gp).all() and (freq.cpu().numpy() == gf).all()
+    b.close()
+    for h in hs:
+        h.close()
