@@ -257,7 +257,7 @@ def run_batch(args, w):
                       "iters": w.iters, "tenure": "[0.9n, 1.1n]", "graph": True,
                       "tile_rows_per_instance": rows_hist, "tuning_s": tune_s,
                       "searches_per_variant": dict(zip(["r2_512", "r4_512", "r8_512", "stream_512", "r2_128",
-                                                        "r2_256", "r4_256", "r4_768"],
+                                                        "r2_256", "r4_256", "r4_768", "wide_512"],
                                                        map(int, b.groups(counts=True)[1])))},
            "solves_per_s": m * k / (ms_step / 1e3), "table_kernel_ms": table_ms, "roofline": roof}
 
@@ -487,7 +487,7 @@ def main():
     search_evals = int(moves.sum()) * m
     kname = ("search_kernel<%d,%s>" % (rows, "true" if algo == "tabu" else "false") if rows > 0 else
              "stream_kernel<%s,false,%s>" % ("true" if algo == "tabu" else "false",
-                                             "true" if n > qap.QAP_NMAX_BATCH else "false"))
+                                             "true" if n > 256 else "false"))
     roof = roofline(search_evals, search_ms, kname, traffic_for(w.name), VALU_PER_EVAL[algo])
 
     out = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,

@@ -41,9 +41,9 @@ extern "C" {
 #endif
 
 #define QAP_NMAX 512
-/* Largest n of the batched (qap_batch_*) and served (qap_server_*) searches; above it
- * those return QAP_E_UNSUPPORTED. */
-#define QAP_NMAX_BATCH 256
+/* Largest n of the batched (qap_batch_*) and served (qap_server_*) searches: every n up
+ * to QAP_NMAX. */
+#define QAP_NMAX_BATCH 512
 
 enum {
     QAP_OK = 0,
@@ -70,16 +70,15 @@ const char *qap_strerror(int code);
  * Create a handle for one instance (F, D) of size n (Sec. 2.1) on the current HIP
  * device.  F and D are host pointers, read once and copied; the handle owns its device
  * copies until qap_destroy.  Returns QAP_E_RANGE if an entry lies outside [0, 255].
- * Every entry point serves every n <= QAP_NMAX_BATCH: the searches hold the
- * neighbourhood in registers and F, F^T, D, D^T in LDS while that fits one workgroup
- * (n <= 176 in the batched kernels), and above that run the streamed kernel
- * (neighbourhood in global memory, only G = F[p][p] in LDS).  For QAP_NMAX_BATCH < n <=
- * QAP_NMAX the single-instance entry points (cost, neighbourhood table, qap_2opt*,
- * qap_tabu*) run the wide streamed kernel, which keeps G and
- * G^T in global memory too (2 n RS bytes of stream-ordered scratch per search, RS = n
- * rounded up to 32, plus 16), and the neighbourhood table is evaluated entry by entry
- * from Eq. (2).  QAP_E_UNSUPPORTED is left for a device whose LDS is smaller than the
- * streamed kernel needs.
+ * Every entry point serves every n <= QAP_NMAX: the searches hold the neighbourhood in
+ * registers and F, F^T, D, D^T in LDS while that fits one workgroup (n <= 176 in the
+ * batched kernels), and above that run the streamed kernel (neighbourhood in global
+ * memory, only G = F[p][p] in LDS).  Above n = 256 they run its wide form, which keeps G
+ * and G^T in global memory too (2 n RS bytes of scratch per search, RS = n rounded up to
+ * 32, plus 16: stream-ordered for the single-instance calls, owned by the plan in a
+ * batch, in the pool for a served request), and the neighbourhood table is evaluated
+ * entry by entry from Eq. (2).  QAP_E_UNSUPPORTED is left for a device whose LDS is
+ * smaller than the streamed kernel needs.
  */
 int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out);
 
@@ -187,11 +186,25 @@ int qap_tabu_freq_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters
                         int64_t *d_best, int32_t *d_done, int32_t *d_freq, void *stream);
 
 /*
+ * Debugging aid, to find the first step at which the device and a reference disagree:
+ * qap_tabu_freq_async (same arguments and results) that also records the first
+ * trace_cap moves of every start: d_trace is device int64[k][trace_cap][4], and move t
+ * (made at iteration t + 1, t < trace_cap) of start j is written as (r, s, delta, cost
+ * after the move) at d_trace[(j * trace_cap + t) * 4]; entries past the moves made are
+ * left as they are.  It runs the frequency-memory kernels, so it is slower than
+ * qap_tabu_async.  QAP_E_INVALID also for d_trace NULL with k > 0 or trace_cap < 0.
+ */
+int qap_tabu_trace_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo,
+                         int32_t hi, uint64_t seed, int64_t start_base, int32_t div, int32_t attr,
+                         int64_t *d_best, int32_t *d_done, int32_t *d_freq, int64_t *d_trace,
+                         int32_t trace_cap, void *stream);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): qap_tabu_async with the same
  * arguments, semantics and results, which calls no allocating routine.  Its scratch (the
  * neighbourhood tables, int32[k][n(n-1)/2] rounded up to 256 bytes, and for the streamed
- * kernels the tile state of every search, plus G and G^T above QAP_NMAX_BATCH) is carved
+ * kernels the tile state of every search, plus G and G^T above n = 256) is carved
  * from one fixed array of QAP_NOALLOC_SCRATCH_BYTES per GPU, which the library holds
  * from the first qap_create on that GPU until the process ends.  A call that would need
  * more returns QAP_E_SCRATCH and enqueues nothing.  Every call on one GPU shares that
@@ -280,9 +293,9 @@ int qap_batch_freq_async(qap_batch_handle b, int32_t *d_freq, void *stream);
 int qap_batch_size(qap_batch_handle b, int64_t *starts_out, int64_t *perm_ints_out);
 /* Kernel dispatches of one qap_batch_search_async: returns the number of tile-shape
  * variants the plan uses (one dispatch each, forked onto side streams of `stream` and
- * joined back), and, when count_out (int32[8]) is not NULL, the searches per variant in
+ * joined back), and, when count_out (int32[9]) is not NULL, the searches per variant in
  * the order: tiles of 2, 4, 8 rows on 512 lanes, streamed, 2 rows on 128 and on 256
- * lanes, 4 rows on 256 and on 768 lanes. */
+ * lanes, 4 rows on 256 and on 768 lanes, the wide streamed form (n above 256). */
 int qap_batch_groups(qap_batch_handle b, int32_t *count_out);
 int qap_batch_run_async(qap_batch_handle b, int32_t *d_perms, int64_t *d_best, int32_t *d_done,
                         void *stream);
@@ -317,14 +330,15 @@ int qap_tabu_batch_concat(const qap_handle *hs, int32_t m, int32_t *perms, const
  * Both check as qap_create and qap_tabu do (QAP_E_INVALID, QAP_E_RANGE, QAP_E_NOT_PERM),
  * return QAP_E_NOMEM at once if the request's footprint (qap_server_footprint(s, n, sym)
  * bytes with its own matrices, sym = 1 when F and D are both symmetric, 4 n RS bytes
- * less on a handle) exceeds the whole pool, QAP_E_UNSUPPORTED if no tile shape of the
- * batched kernel serves n (n > QAP_NMAX_BATCH), and QAP_E_BUSY if the queue already holds
+ * less on a handle) exceeds the whole pool, QAP_E_UNSUPPORTED if no kernel shape serves
+ * n on this device, and QAP_E_BUSY if the queue already holds
  * qap_server_set_queue_limit requests (default 65536).
  *
  * Stepping: each step admits queued requests in arrival order while a slot is free and
  * their footprint fits the pool (a request that does not fit is passed over by later
  * ones that do, for at most 8 steps, after which nothing behind it is admitted first),
- * then runs one chunk of every admitted search in one launch: each search runs until
+ * then runs one chunk of every admitted search in one launch (a second one for searches
+ * above n = 256): each search runs until
  * about chunk_ms of device time has passed, stopping at an iteration boundary, with its
  * permutation, neighbourhood, tabu list and best solution kept in the pool in between.
  * Searches that finished are then collected and their slot and memory freed.  Every

@@ -232,7 +232,8 @@ hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipS
 hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t *d_table, int k, int iters,
                            int lo, int hi, uint64_t seed, int64_t start_base, int64_t *d_cost, int32_t *d_steps,
                            hipStream_t st, bool plain, int32_t *d_freq = nullptr, int div = 0, int attr = 0,
-                           int ri = -1, const StreamScratch *pre = nullptr) {
+                           int ri = -1, const StreamScratch *pre = nullptr, long long *d_trace = nullptr,
+                           int trace_cap = 0) {
     // one shape for the whole launch: its kernel and its tile list
     if (ri < 0) ri = launch_shape(h, algo, k);
     if (ri < 0) return hipErrorInvalidValue;
@@ -250,6 +251,8 @@ hipError_t launch_searches(qap_ctx *h, int algo, int32_t *d_perms, const int32_t
     a.freq = d_freq;
     a.div = div;
     a.attr = attr;
+    a.trace = d_trace;
+    a.trace_cap = trace_cap;
     hipError_t e = hipSuccess;
     if (d_freq && attr == 2) {
         // the unit-location table of every search, in stream-ordered scratch
@@ -325,14 +328,15 @@ hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipS
 
 int run_search(qap_ctx *h, int algo, int32_t *d_perms, int k, int iters, int lo, int hi, uint64_t seed,
                int64_t start_base, int64_t *d_cost, int32_t *d_steps, hipStream_t st, bool plain,
-               int32_t *d_freq = nullptr, int div = 0, int attr = 0) {
+               int32_t *d_freq = nullptr, int div = 0, int attr = 0, long long *d_trace = nullptr,
+               int trace_cap = 0) {
     if (h->rows_choice[algo] < 0) return QAP_E_UNSUPPORTED;
     if (k == 0) return QAP_OK;
     int32_t *d_table = nullptr;
     int rc = make_tables(h, d_perms, k, &d_table, st);
     if (rc != QAP_OK) return rc;
     hipError_t e = launch_searches(h, algo, d_perms, d_table, k, iters, lo, hi, seed, start_base, d_cost,
-                                   d_steps, st, plain, d_freq, div, attr);
+                                   d_steps, st, plain, d_freq, div, attr, -1, nullptr, d_trace, trace_cap);
     hipError_t e2 = hipFreeAsync(d_table, st);
     if (e == hipSuccess) e = e2;
     return dev_err(e);
@@ -341,8 +345,8 @@ int run_search(qap_ctx *h, int algo, int32_t *d_perms, int k, int iters, int lo,
 // Whether tile shape ri serves this instance in the batched kernel (fixed workgroup of
 // BATCH_LANES lanes, rows 2, 4 or 8).
 bool batch_fits(const qap_ctx *h, int ri) {
-    if (h->n > WIDE_N) return false;   // the wide streamed kernel runs single-instance searches only
-    if (ri == kStream) return h->stream_ok != 0;
+    if (ri == kStream) return h->stream_ok != 0;   // above WIDE_N, the wide streamed form
+    if (h->n > WIDE_N) return false;
     if (ri < kBatchFirst || ri > kBatchFirst + 2) return false;
     const TileSet &ts = h->tiles[ri];
     const int rows = kRowsChoices[ri];
@@ -355,7 +359,7 @@ bool batch_fits(const qap_ctx *h, int ri) {
 int batch_default(const qap_ctx *h) {
     for (int i = kBatchFirst; i < kBatchFirst + 3; ++i)
         if (batch_fits(h, i)) return i;
-    return h->stream_ok && h->n <= WIDE_N ? kStream : -1;
+    return h->stream_ok ? kStream : -1;
 }
 
 bool algo_fits(const qap_ctx *h, int algo, int ri) { return algo == 2 ? batch_fits(h, ri) : shape_fits(h, ri); }
@@ -386,13 +390,26 @@ void timing_starts(int n, int k, std::vector<int32_t> &p) {
 
 }  // namespace
 
+// Starting neighbourhoods of one instance above WIDE_N in a batch: its k starts and
+// tables are contiguous at these offsets of the run's starts and the plan's tables.
+struct WideTable {
+    const uint8_t *mats;
+    int n, m, k, sym;
+    long long perm_off, table_off;
+};
+
 struct qap_batch {
     int count = 0;                  // searches (items)
     long long perm_ints = 0, table_ints = 0, tile_int4 = 0;
     Item *d_items = nullptr;
     int32_t *d_table = nullptr;
     int4 *d_tile_work = nullptr;    // tile state of the streamed searches
+    uint8_t *d_gwork = nullptr;     // G and G^T of the searches above WIDE_N
     size_t table_smem = 0;
+    // starting neighbourhoods of instances above WIDE_N: one Eq. (2) launch per instance
+    // (offsets into the run's starts and the plan's tables); the matrix-core table kernel
+    // takes every other item
+    std::vector<WideTable> wide_tables;
     // items are grouped by kernel variant (tile shape); one launch per non-empty group,
     // the groups forked onto side streams so that they share the device
     int group_begin[BV_COUNT] = {}, group_count[BV_COUNT] = {};
@@ -681,6 +698,16 @@ int qap_tabu_freq_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters
                       false, d_freq, div, attr);
 }
 
+int qap_tabu_trace_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo, int32_t hi,
+                         uint64_t seed, int64_t start_base, int32_t div, int32_t attr, int64_t *d_best,
+                         int32_t *d_done, int32_t *d_freq, int64_t *d_trace, int32_t trace_cap, void *stream) {
+    if (!tabu_args_ok(h, d_perms, k, iters, lo, hi, d_best) || (k > 0 && (!d_freq || !d_trace)) || div < 0 ||
+        attr < 0 || attr > 2 || trace_cap < 0)
+        return QAP_E_INVALID;
+    return run_search(h, 0, d_perms, k, iters, lo, hi, seed, start_base, d_best, d_done, (hipStream_t)stream,
+                      false, d_freq, div, attr, reinterpret_cast<long long *>(d_trace), trace_cap);
+}
+
 int qap_tabu_plain_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iters, int32_t lo, int32_t hi,
                          uint64_t seed, int64_t start_base, int64_t *d_best, int32_t *d_done, void *stream) {
     if (!tabu_args_ok(h, d_perms, k, iters, lo, hi, d_best)) return QAP_E_INVALID;
@@ -837,7 +864,8 @@ int batch_create_impl(const qap_handle *hs, int32_t m, const int32_t *k_per, int
     if (!hs || !k_per || !lo_per || !hi_per || !seed_per || !out || m < 0 || iters < 0) return QAP_E_INVALID;
     *out = nullptr;
     std::vector<Item> items;
-    long long perm_off = 0, out_off = 0, table_off = 0, tile_off = 0, freq_off = 0, uloc_off = 0;
+    std::vector<WideTable> wide_tables;
+    long long perm_off = 0, out_off = 0, table_off = 0, tile_off = 0, freq_off = 0, uloc_off = 0, g_off = 0;
     size_t gsmem[BV_COUNT] = {}, tsmem = 0, fsmem = 0;
     for (int i = 0; i < m; ++i) {
         qap_ctx *h = hs[i];
@@ -865,7 +893,13 @@ int batch_create_impl(const qap_handle *hs, int32_t m, const int32_t *k_per, int
             fsmem = std::max(fsmem, sm);
         else
             gsmem[var] = std::max(gsmem[var], sm);
-        tsmem = std::max(tsmem, table_smem_bytes(h->n));
+        const bool wide = h->n > WIDE_N;
+        if (wide) {
+            if (k_per[i] > 0)
+                wide_tables.push_back(WideTable{h->d_mats, h->n, h->m, k_per[i], h->sym, perm_off, table_off});
+        } else {
+            tsmem = std::max(tsmem, table_smem_bytes(h->n));
+        }
         for (int j = 0; j < k_per[i]; ++j) {
             Item it{};
             it.mats = h->d_mats;
@@ -880,6 +914,10 @@ int batch_create_impl(const qap_handle *hs, int32_t m, const int32_t *k_per, int
             if (streamed) {
                 it.tile_off = tile_off;
                 tile_off += stream_tile_int4(ts.ntiles);
+            }
+            if (wide) {
+                it.g_off = g_off;
+                g_off += wide_g_bytes(h->n, h->sym);
             }
             it.iters = iters;
             it.lo = lo_per[i];
@@ -924,6 +962,7 @@ int batch_create_impl(const qap_handle *hs, int32_t m, const int32_t *k_per, int
     b->freq_mode = freq;
     b->freq_smem = fsmem;
     b->freq_ints = freq_off;
+    b->wide_tables = wide_tables;
     for (int i = (int)items.size() - 1; i >= 0; --i) {
         const int v = item_variant(items[i]);
         b->group_begin[v] = i;
@@ -952,6 +991,7 @@ int batch_create_impl(const qap_handle *hs, int32_t m, const int32_t *k_per, int
         if (e == hipSuccess) e = hipMalloc((void **)&b->d_items, items.size() * sizeof(Item));
         if (e == hipSuccess) e = hipMalloc((void **)&b->d_table, (size_t)table_off * sizeof(int32_t) + 16);
         if (e == hipSuccess && tile_off > 0) e = hipMalloc((void **)&b->d_tile_work, (size_t)tile_off * sizeof(int4));
+        if (e == hipSuccess && g_off > 0) e = hipMalloc((void **)&b->d_gwork, (size_t)g_off);
         if (e == hipSuccess && freq) e = hipMalloc((void **)&b->d_freq, (size_t)freq_off * sizeof(int32_t) + 16);
         if (e == hipSuccess && uloc_off > 0)
             e = hipMalloc((void **)&b->d_uloc, (size_t)uloc_off * sizeof(int32_t) + 16);
@@ -1024,8 +1064,18 @@ extern "C" int qap_batch_groups(qap_batch_handle b, int32_t *count_out) {
 extern "C" int qap_batch_tables_async(qap_batch_handle b, const int32_t *d_perms, void *stream) {
     if (!b || (b->count > 0 && !d_perms)) return QAP_E_INVALID;
     if (b->count == 0) return QAP_OK;
-    BatchArgs a{b->d_items, b->count, const_cast<int32_t *>(d_perms), nullptr, nullptr, b->d_table, b->d_tile_work};
-    return dev_err(launch_table_batch(a, b->table_smem, (hipStream_t)stream));
+    const hipStream_t st = (hipStream_t)stream;
+    // the searches above WIDE_N come last (their variant is the last one)
+    const int narrow = b->count - (b->freq_mode ? 0 : b->group_count[BV_WIDE]);
+    BatchArgs a{b->d_items, narrow, const_cast<int32_t *>(d_perms), nullptr, nullptr, b->d_table, b->d_tile_work,
+                b->d_gwork};
+    hipError_t e = launch_table_batch(a, b->table_smem, st);
+    for (size_t i = 0; i < b->wide_tables.size() && e == hipSuccess; ++i) {
+        const WideTable &w = b->wide_tables[i];
+        const TableArgs ta{w.mats, d_perms + w.perm_off, nullptr, b->d_table + w.table_off, w.n, w.m, w.k, w.sym};
+        e = launch_table(ta, st);
+    }
+    return dev_err(e);
 }
 
 extern "C" int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int64_t *d_best, int32_t *d_done,
@@ -1034,7 +1084,7 @@ extern "C" int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int6
     if (b->count == 0) return QAP_OK;
     hipStream_t st = (hipStream_t)stream;
     if (b->freq_mode) {
-        BatchArgs a{b->d_items, b->count, d_perms, d_best, d_done, b->d_table, b->d_tile_work};
+        BatchArgs a{b->d_items, b->count, d_perms, d_best, d_done, b->d_table, b->d_tile_work, b->d_gwork};
         return dev_err(launch_batch_freq(a, b->freq_smem, st));
     }
     int ngroups = 0;
@@ -1045,7 +1095,7 @@ extern "C" int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int6
         const int v = b->group_order[g];
         if (!b->group_count[v]) continue;
         BatchArgs a{b->d_items + b->group_begin[v], b->group_count[v], d_perms, d_best, d_done, b->d_table,
-                    b->d_tile_work};
+                    b->d_tile_work, b->d_gwork};
         if (ngroups == 1) {
             e = launch_batch_group(v, a, b->group_smem[v], st);
             continue;
@@ -1069,6 +1119,7 @@ extern "C" int qap_batch_destroy(qap_batch_handle b) {
     if (b->d_items) (void)hipFree(b->d_items);
     if (b->d_table) (void)hipFree(b->d_table);
     if (b->d_tile_work) (void)hipFree(b->d_tile_work);
+    if (b->d_gwork) (void)hipFree(b->d_gwork);
     if (b->d_freq) (void)hipFree(b->d_freq);
     if (b->d_uloc) (void)hipFree(b->d_uloc);
     for (int v = 0; v < BV_COUNT; ++v) {

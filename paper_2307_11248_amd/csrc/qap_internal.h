@@ -126,6 +126,8 @@ struct SearchArgs {
     int32_t *uloc;           // attr 2: [k][n][n] per search, until when a unit may not return to a location
     uint8_t *gwork;          // wide streamed kernel: per search, gstride bytes holding G and G^T
     long long gstride;
+    long long *trace;        // with freq: [k][trace_cap][4] (r, s, delta, cost after) per move, or null
+    int trace_cap;
 };
 
 // With QAP_VERBOSE set in the environment, report a failed HIP call on stderr.
@@ -198,7 +200,12 @@ struct Item {
     // batched plans that keep the frequency memory: offsets of freq and uloc in the
     // plan's buffers (host side, while the plan is built)
     long long freq_off, uloc_off;
+    // batched launches, n above WIDE_N: offset of gmat in the launch's G scratch
+    long long g_off;
     uint8_t *gmat;            // wide streamed kernel: G, then G^T (unless symmetric), rows of RS bytes
+    // with freq: the first trace_cap moves as (r, s, delta, cost after), or null
+    long long *trace;
+    int trace_cap;
 };
 
 // The batched launch: one block per item of `items`; per-start buffers are shared by
@@ -211,6 +218,7 @@ struct BatchArgs {
     int32_t *done;     // or null
     int32_t *table;    // neighbourhood of every start
     int4 *tile_work;   // tile state of the searches that run streamed
+    uint8_t *gwork;    // G and G^T of the searches above WIDE_N (Item::g_off)
 };
 
 hipError_t launch_cost(const TableArgs &a, hipStream_t st);
@@ -231,11 +239,14 @@ int batch_shape_ok(int n, int rows, int ntiles, int sym);
 // that more small searches share a compute unit; tiles of 4 rows also on 768 lanes (one
 // task per lane, three waves per SIMD) for searches with more than BATCH_LANES tiles.
 // One launch per variant.
-enum { BV_R2 = 0, BV_R4, BV_R8, BV_STREAM, BV_R2_128, BV_R2_256, BV_R4_256, BV_R4_768, BV_COUNT };
+// The wide streamed form (n above WIDE_N: G and G^T in global scratch, up to WIDE_MAXT
+// tasks a lane) is the last variant.
+enum { BV_R2 = 0, BV_R4, BV_R8, BV_STREAM, BV_R2_128, BV_R2_256, BV_R4_256, BV_R4_768, BV_WIDE, BV_COUNT };
 // Whether a batched launch serves tile shape rows for this n (batch_shape_ok, or tiles of
 // 4 rows on the 768-lane variant).
 int batch_shape_ok_wide(int n, int rows, int ntiles, int sym);
-// Variant of a batched search: rows 2, 4, 8 or the streamed form, ntiles tiles.
+// Variant of a batched search: rows 2, 4, 8 or the streamed form (the wide one above
+// WIDE_N), ntiles tiles.
 int batch_variant(int n, int rows, bool streamed, int ntiles, int sym);
 // Lanes of a workgroup of that variant.
 int batch_variant_lanes(int variant);
@@ -271,6 +282,8 @@ hipError_t launch_stream(bool tabu, const SearchArgs &a, int grid, hipStream_t s
 // items that start now (into their `table`), then one chunk of every item.
 hipError_t launch_table_items(const Item *d_items, int count, size_t smem, hipStream_t st);
 hipError_t launch_resume(const Item *d_items, int count, size_t smem, hipStream_t st);
+// The same for items above WIDE_N (the wide streamed form; Item::gmat set).
+hipError_t launch_resume_wide(const Item *d_items, int count, size_t smem, hipStream_t st);
 // Lanes of a search workgroup for a tile shape, or 0 if the shape cannot serve n.
 int search_lanes(int n, int rows, int ntiles, int sym);
 

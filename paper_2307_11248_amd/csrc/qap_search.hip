@@ -117,6 +117,10 @@ __device__ inline long long wave_sum64(long long v) {
     return v;
 }
 
+// Product of two differences of u8 entries (|a|, |b| <= 255): a 24-bit multiply, which
+// issues at the full VALU rate (a 32-bit multiply issues at a quarter of it).
+__device__ inline int mul8(int a, int b) { return __mul24(a, b); }
+
 __device__ inline int pack16(int lo, int hi) {
     return (int)(((unsigned)hi << 16) | ((unsigned)lo & 0xffffu));
 }
@@ -170,75 +174,89 @@ __device__ inline unsigned dot_rows(const uint8_t *a, const uint8_t *b, int rs) 
     return acc;
 }
 
-// Two dot products sharing the row `a`, over the first rs bytes (a multiple of 32), 32
-// bytes a step; the loads of the next step are issued before the current one is used.
-__device__ inline void dot_rows2(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
-                                 unsigned &o2) {
+// Bytes [w, w + 16 * N) of three rows, one uint4 per 16 bytes.
+template <int N>
+struct RowStep {
+    uint4 x[N], y[N], z[N];
+};
+
+template <int N>
+__device__ inline void load_step(RowStep<N> &q, const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int w) {
+#pragma unroll
+    for (int h = 0; h < N; ++h) {
+        q.x[h] = *reinterpret_cast<const uint4 *>(a + w + 16 * h);
+        q.y[h] = *reinterpret_cast<const uint4 *>(b1 + w + 16 * h);
+        q.z[h] = *reinterpret_cast<const uint4 *>(b2 + w + 16 * h);
+    }
+}
+
+template <int N>
+__device__ inline void dot_step(const RowStep<N> &q, unsigned &c1, unsigned &c2) {
+#pragma unroll
+    for (int h = 0; h < N; ++h) {
+        c1 = __builtin_amdgcn_udot4(q.x[h].x, q.y[h].x, c1, false);
+        c1 = __builtin_amdgcn_udot4(q.x[h].y, q.y[h].y, c1, false);
+        c1 = __builtin_amdgcn_udot4(q.x[h].z, q.y[h].z, c1, false);
+        c1 = __builtin_amdgcn_udot4(q.x[h].w, q.y[h].w, c1, false);
+        c2 = __builtin_amdgcn_udot4(q.x[h].x, q.z[h].x, c2, false);
+        c2 = __builtin_amdgcn_udot4(q.x[h].y, q.z[h].y, c2, false);
+        c2 = __builtin_amdgcn_udot4(q.x[h].z, q.z[h].z, c2, false);
+        c2 = __builtin_amdgcn_udot4(q.x[h].w, q.z[h].w, c2, false);
+    }
+}
+
+// Two dot products sharing the row `a`, over the first rs bytes (a multiple of 16 N),
+// 16 N bytes a step.  Two register sets take turns, so the loads of the next step are in
+// flight while the current one is summed, without copying registers between steps.
+template <int N>
+__device__ inline void dot_rows2_t(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
+                                   unsigned &o2) {
+    constexpr int S = 16 * N;
     unsigned c1 = 0, c2 = 0;
-    uint4 x0 = *reinterpret_cast<const uint4 *>(a), x1 = *reinterpret_cast<const uint4 *>(a + 16);
-    uint4 y0 = *reinterpret_cast<const uint4 *>(b1), y1 = *reinterpret_cast<const uint4 *>(b1 + 16);
-    uint4 z0 = *reinterpret_cast<const uint4 *>(b2), z1 = *reinterpret_cast<const uint4 *>(b2 + 16);
-    for (int w = 32; w <= rs; w += 32) {
-        uint4 nx0 = x0, nx1 = x1, ny0 = y0, ny1 = y1, nz0 = z0, nz1 = z1;
-        if (w < rs) {
-            nx0 = *reinterpret_cast<const uint4 *>(a + w);
-            nx1 = *reinterpret_cast<const uint4 *>(a + w + 16);
-            ny0 = *reinterpret_cast<const uint4 *>(b1 + w);
-            ny1 = *reinterpret_cast<const uint4 *>(b1 + w + 16);
-            nz0 = *reinterpret_cast<const uint4 *>(b2 + w);
-            nz1 = *reinterpret_cast<const uint4 *>(b2 + w + 16);
-        }
-        c1 = __builtin_amdgcn_udot4(x0.x, y0.x, c1, false);
-        c1 = __builtin_amdgcn_udot4(x0.y, y0.y, c1, false);
-        c1 = __builtin_amdgcn_udot4(x0.z, y0.z, c1, false);
-        c1 = __builtin_amdgcn_udot4(x0.w, y0.w, c1, false);
-        c2 = __builtin_amdgcn_udot4(x0.x, z0.x, c2, false);
-        c2 = __builtin_amdgcn_udot4(x0.y, z0.y, c2, false);
-        c2 = __builtin_amdgcn_udot4(x0.z, z0.z, c2, false);
-        c2 = __builtin_amdgcn_udot4(x0.w, z0.w, c2, false);
-        c1 = __builtin_amdgcn_udot4(x1.x, y1.x, c1, false);
-        c1 = __builtin_amdgcn_udot4(x1.y, y1.y, c1, false);
-        c1 = __builtin_amdgcn_udot4(x1.z, y1.z, c1, false);
-        c1 = __builtin_amdgcn_udot4(x1.w, y1.w, c1, false);
-        c2 = __builtin_amdgcn_udot4(x1.x, z1.x, c2, false);
-        c2 = __builtin_amdgcn_udot4(x1.y, z1.y, c2, false);
-        c2 = __builtin_amdgcn_udot4(x1.z, z1.z, c2, false);
-        c2 = __builtin_amdgcn_udot4(x1.w, z1.w, c2, false);
-        x0 = nx0; x1 = nx1; y0 = ny0; y1 = ny1; z0 = nz0; z1 = nz1;
+    RowStep<N> p, q;
+    load_step<N>(p, a, b1, b2, 0);
+    for (int w = S;; w += S) {
+        if (w < rs) load_step<N>(q, a, b1, b2, w);
+        dot_step<N>(p, c1, c2);
+        if (w >= rs) break;
+        w += S;
+        if (w < rs) load_step<N>(p, a, b1, b2, w);
+        dot_step<N>(q, c1, c2);
+        if (w >= rs) break;
     }
     o1 = c1;
     o2 = c2;
 }
 
-// dot_rows2 in 16-byte steps (half the registers of the 32-byte form; for kernels held
-// to 128 VGPRs, where the wider steps spill).
-__device__ inline void dot_rows2_16(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
-                                    unsigned &o2) {
+// 32 bytes a step (rs a multiple of 32)
+__device__ inline void dot_rows2(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
+                                 unsigned &o2) {
+    dot_rows2_t<2>(a, b1, b2, rs, o1, o2);
+}
+
+// dot_rows2 with one register set carried across steps (the next step's loads go to
+// fresh registers that are copied over after the sums): fewer live registers at once,
+// at the price of the copies; used by the 2opt kernels, whose tiles leave less room.
+__device__ inline void dot_rows2_carry(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs,
+                                       unsigned &o1, unsigned &o2) {
     unsigned c1 = 0, c2 = 0;
-    uint4 x = *reinterpret_cast<const uint4 *>(a);
-    uint4 y = *reinterpret_cast<const uint4 *>(b1);
-    uint4 z = *reinterpret_cast<const uint4 *>(b2);
-    for (int w = 16; w <= rs; w += 16) {
-        uint4 xn = x, yn = y, zn = z;
-        if (w < rs) {
-            xn = *reinterpret_cast<const uint4 *>(a + w);
-            yn = *reinterpret_cast<const uint4 *>(b1 + w);
-            zn = *reinterpret_cast<const uint4 *>(b2 + w);
-        }
-        c1 = __builtin_amdgcn_udot4(x.x, y.x, c1, false);
-        c1 = __builtin_amdgcn_udot4(x.y, y.y, c1, false);
-        c1 = __builtin_amdgcn_udot4(x.z, y.z, c1, false);
-        c1 = __builtin_amdgcn_udot4(x.w, y.w, c1, false);
-        c2 = __builtin_amdgcn_udot4(x.x, z.x, c2, false);
-        c2 = __builtin_amdgcn_udot4(x.y, z.y, c2, false);
-        c2 = __builtin_amdgcn_udot4(x.z, z.z, c2, false);
-        c2 = __builtin_amdgcn_udot4(x.w, z.w, c2, false);
-        x = xn;
-        y = yn;
-        z = zn;
+    RowStep<2> p;
+    load_step<2>(p, a, b1, b2, 0);
+    for (int w = 32; w <= rs; w += 32) {
+        RowStep<2> q = p;
+        if (w < rs) load_step<2>(q, a, b1, b2, w);
+        dot_step<2>(p, c1, c2);
+        p = q;
     }
     o1 = c1;
     o2 = c2;
+}
+
+// 16 bytes a step (half the registers of the 32-byte form; for kernels held to 128 VGPRs,
+// where the wider steps spill)
+__device__ inline void dot_rows2_16(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
+                                    unsigned &o2) {
+    dot_rows2_t<1>(a, b1, b2, rs, o1, o2);
 }
 
 // dot_rows2 for rows of exactly 64 bytes with every load in flight at once: one memory
@@ -449,7 +467,9 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     // (delta << 32 | key), key = u << 9 | v; among equal deltas the lowest slot, i.e. the
     // lowest key.  Up to 8 rows: one 32-bit key per slot, delta * 2^SB + slot, with
     // inadmissible and non-move slots at LIM (above every delta, |delta| < 2^26), so one
-    // v_min per slot finds both.
+    // v_min per slot finds both.  Tabu searches need no clamp of BIG: a slot that is not a
+    // move has a tabu state that never expires (INT32_MAX) and BIG is never below the
+    // aspiration threshold (best - cur <= 0), so it is never admissible.
     auto tile_min = [&](const int (&d)[ROWS][4], const int (&u_)[UTR][4], int tu0, int tv0, int itx,
                         int thr) -> long long {
         int bd = INT32_MAX, bs = -1;
@@ -467,7 +487,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                     for (int e = 0; e < 4; ++e) {
                         const int x = d[j][e];
                         const bool adm = TABU ? (u_[j][e] <= itx || x < thr) : true;
-                        const int m = adm ? min(x, LIM) : LIM;
+                        const int m = adm ? (TABU ? x : min(x, LIM)) : LIM;
                         kv[j * 4 + e] = m * (1 << SB) + (j * 4 + e);
                     }
                 }
@@ -483,7 +503,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 for (int e = 0; e < 4; ++e) {
                     const int x = d[j][e];
                     const bool adm = TABU ? (u_[j][e] <= itx || x < thr) : true;
-                    const int m = adm ? min(x, LIM) : LIM;
+                    const int m = adm ? (TABU ? x : min(x, LIM)) : LIM;
                     best = min(best, m * (1 << SB) + (j * 4 + e));
                 }
             }
@@ -693,6 +713,14 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         // nothing waits for; the zeroing above finished before the first barrier)
         if (FREQ && a.freq && t == 0)
             __hip_atomic_fetch_add(a.freq + pidx(n, r, s), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // step record (debugging aid): move it - 1 of the search
+        if (FREQ && a.trace && t == 0 && it - 1 < a.trace_cap) {
+            long long *tr = a.trace + 4LL * (it - 1);
+            tr[0] = r;
+            tr[1] = s;
+            tr[2] = dstar;
+            tr[3] = cur;
+        }
 
         // words of rows r and s of G and G^T for the exchange in C (read now, G is not
         // written before B2); lanes 0 .. 63 of wave 0 (the bytes of n <= 256), or in the
@@ -747,13 +775,14 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             const uint8_t *side1 = f < 2 ? Df + r * rs : Gf + s * rs;
             const uint8_t *side2 = f < 2 ? Df + s * rs : Gf + r * rs;
             unsigned d1, d2;
-            if constexpr (NARROW) {
+            // rows of 64 bytes in one step where the registers allow it (one LDS latency)
+            constexpr bool ONE_SHOT = MAXT == 1 && !FREQ && (!NARROW || ROWS <= 2);
+            if (ONE_SHOT && nb32 == 64) {
+                dot_rows2_64(shared, side1, side2, d1, d2);
+            } else if constexpr (NARROW) {
                 dot_rows2_16(shared, side1, side2, nb16, d1, d2);
-            } else if constexpr (MAXT == 1) {
-                if (nb32 == 64)
-                    dot_rows2_64(shared, side1, side2, d1, d2);
-                else
-                    dot_rows2(shared, side1, side2, nb32, d1, d2);
+            } else if constexpr (!TABU) {
+                dot_rows2_carry(shared, side1, side2, nb32, d1, d2);
             } else {
                 dot_rows2(shared, side1, side2, nb32, d1, d2);
             }
@@ -790,8 +819,8 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             const int ar2 = f == 0 ? a0 : (f == 1 ? a1 : (f == 2 ? G_rs - G_rr : G_sr - G_rr));
             const int cr1 = f == 0 ? D_rr - D_rs : (f == 1 ? D_rr - D_sr : (f == 2 ? d_ur - d_us : d_ru - d_su));
             const int cr2 = f == 0 ? D_sr - D_ss : (f == 1 ? D_rs - D_ss : (f == 2 ? d_ur - d_us : d_ru - d_su));
-            const int x = (int)d1 + ar1 * cr1;
-            const int y = (int)d2 + ar2 * cr2;
+            const int x = (int)d1 + mul8(ar1, cr1);
+            const int y = (int)d2 + mul8(ar2, cr2);
             // the four families of u (two when symmetric), shared inside the quad
             int xf[4], yf[4];
             if (sym) {
@@ -815,8 +844,8 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 rdn = yf[2];
                 cdn = yf[3];
             } else {
-                rdn = rdv[i] - A * B;
-                cdn = cdv[i] - C * E;
+                rdn = rdv[i] - mul8(A, B);
+                cdn = cdv[i] - mul8(C, E);
             }
             rdv[i] = rdn;
             cdv[i] = cdn;
@@ -842,9 +871,9 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 const int dbb = q == 0 ? D_rr : D_ss, gbb = q == 0 ? G_ss : G_rr;
                 const int dub = q == 0 ? d_ur : d_us, dbu = q == 0 ? d_ru : d_su;
                 const int gub = q == 0 ? g_us : g_ur, gbu = q == 0 ? g_su : g_ru;
-                const int rowex = (dbu - duu) * (guu - gbu) + (dbb - dub) * (gub - gbb);
-                const int colex = (dub - duu) * (guu - gub) + (dbb - dbu) * (gbu - gbb);
-                const int diag = (dbb - duu) * (guu - gbb) + (dbu - dub) * (gub - gbu);
+                const int rowex = mul8(dbu - duu, guu - gbu) + mul8(dbb - dub, gub - gbb);
+                const int colex = mul8(dub - duu, guu - gub) + mul8(dbb - dbu, gbu - gbb);
+                const int diag = mul8(dbb - duu, guu - gbb) + mul8(dbu - dub, gub - gbu);
                 (q == 0 ? rpr : rps)[u] = X + Y + Z + Wv - rdn - cdn - rowex - colex + diag;
             }
             if (u == r) guv[i] = G_ss;
@@ -974,8 +1003,71 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 }
             }
             // the rows and columns of r and s; the row/column inside the tile is the same for
-            // every lane that holds it, so the slot choice is a scalar branch
+            // every lane that holds it, so the slot is picked by a uniform index: tiles of 1
+            // and 2 rows select every slot against it (a select per slot, the condition
+            // uniform), tiles of 4 and 8 rows are viewed as one vector whose picked slots
+            // are written by register-indexed moves, tiles of 16 rows take a scalar branch
+            // per row
             const int jr = r % ROWS, js = s % ROWS, er = r & 3, es = s & 3;
+            if constexpr (ROWS <= 2) {
+                if (g == r / ROWS) {
+                    const int vr[4] = {rv.x - kr, rv.y - kr, rv.z - kr, rv.w - kr};
+#pragma unroll
+                    for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) dl[j][e] = j == jr ? vr[e] : dl[j][e];
+                }
+                if (g == s / ROWS) {
+                    const int vs[4] = {sv.x - ks, sv.y - ks, sv.z - ks, sv.w - ks};
+#pragma unroll
+                    for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) dl[j][e] = j == js ? vs[e] : dl[j][e];
+                }
+                if (b == (r >> 2)) {
+#pragma unroll
+                    for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) dl[j][e] = e == er ? rpru[j] - kr : dl[j][e];
+                }
+                if (b == (s >> 2)) {
+#pragma unroll
+                    for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) dl[j][e] = e == es ? rpsu[j] - ks : dl[j][e];
+                }
+            } else if constexpr (ROWS <= 8) {
+                typedef int tilevec __attribute__((ext_vector_type(ROWS * 4)));
+                tilevec tv;
+#pragma unroll
+                for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) tv[j * 4 + e] = dl[j][e];
+                if (g == r / ROWS) {
+                    tv[jr * 4 + 0] = rv.x - kr;
+                    tv[jr * 4 + 1] = rv.y - kr;
+                    tv[jr * 4 + 2] = rv.z - kr;
+                    tv[jr * 4 + 3] = rv.w - kr;
+                }
+                if (g == s / ROWS) {
+                    tv[js * 4 + 0] = sv.x - ks;
+                    tv[js * 4 + 1] = sv.y - ks;
+                    tv[js * 4 + 2] = sv.z - ks;
+                    tv[js * 4 + 3] = sv.w - ks;
+                }
+                if (b == (r >> 2)) {
+#pragma unroll
+                    for (int j = 0; j < ROWS; ++j) tv[j * 4 + er] = rpru[j] - kr;
+                }
+                if (b == (s >> 2)) {
+#pragma unroll
+                    for (int j = 0; j < ROWS; ++j) tv[j * 4 + es] = rpsu[j] - ks;
+                }
+#pragma unroll
+                for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) dl[j][e] = tv[j * 4 + e];
+            } else {
             if (g == r / ROWS) {
                 const int vr[4] = {rv.x - kr, rv.y - kr, rv.z - kr, rv.w - kr};
 #pragma unroll
@@ -1009,6 +1101,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
 #pragma unroll
                         for (int j = 0; j < ROWS; ++j) dl[j][e] = rpsu[j] - ks;
                     }
+            }
             }
             bool tabu_set = false;
             if (FREQ && TABU && a.attr == 1) {
@@ -1202,6 +1295,8 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
     it.div = FREQ ? a.div : 0;
     it.attr = FREQ ? a.attr : 0;
     it.uloc = FREQ && a.uloc ? a.uloc + (size_t)job * a.n * a.n : nullptr;
+    it.trace = FREQ && a.trace ? a.trace + (size_t)job * a.trace_cap * 4 : nullptr;
+    it.trace_cap = FREQ ? a.trace_cap : 0;
     it.st = nullptr;
     it.n = a.n;
     it.m = a.m;
@@ -1214,7 +1309,8 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
     it.hi = a.hi;
     it.seed = a.seed;
     it.start_id = a.start_base + job;
-    search_body<ROWS, TABU, max_tasks<ROWS>(), false, false, !TABU && ROWS == 8, FREQ>(it, sm);
+    search_body<ROWS, TABU, max_tasks<ROWS>(), false, false,
+                TABU ? (ROWS <= 2 || (FREQ && ROWS <= 4)) : ROWS == 8, FREQ>(it, sm);
 }
 
 // The batched launch, one kernel per tile shape: block i runs items[i] as one tabu
@@ -1224,7 +1320,7 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
 // compute unit and hide each other's latency; 8-row and streamed tiles need more
 // registers and run one search per compute unit.  (A persistent loop over a work queue
 // inside one block was tried: keeping its state live made the register tiles spill.)
-template <int ROWS, int LANES, int MAXT, bool STREAM>
+template <int ROWS, int LANES, int MAXT, bool STREAM, bool WIDE = false>
 __global__ void __launch_bounds__(LANES) __attribute__((amdgpu_waves_per_eu(LANES > 512 ? 3 : (ROWS <= 4 ? 4 : 2))))
 batch_group_kernel(BatchArgs b) {
     extern __shared__ __align__(16) unsigned char sm[];
@@ -1238,7 +1334,12 @@ batch_group_kernel(BatchArgs b) {
         it.tile_d = b.tile_work + it.tile_off;
         it.tile_u = it.tile_d + stream_tile_int4(it.ntiles) / 2;
     }
-    search_body<ROWS, true, MAXT, false, STREAM, ROWS <= 4 && LANES <= 512 && (MAXT > 1 || ROWS == 4)>(it, sm);
+    if constexpr (WIDE) {
+        it.gmat = b.gwork + it.g_off;
+        search_body<STREAM_ROWS, true, WIDE_MAXT, false, true, false, false, true>(it, sm);
+    } else {
+        search_body<ROWS, true, MAXT, false, STREAM, ROWS <= 4 && LANES <= 512>(it, sm);
+    }
 }
 
 // The batched launch of plans whose searches keep the frequency memory (and may use the
@@ -1281,6 +1382,14 @@ __global__ void __launch_bounds__(BATCH_LANES) resume_kernel(const Item *items) 
     }
 }
 
+// Chunked runs of searches above WIDE_N: block i runs one chunk of items[i] (the wide
+// streamed form, G and G^T at items[i].gmat).
+__global__ void __launch_bounds__(BATCH_LANES) resume_wide_kernel(const Item *items) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    const Item it = items[blockIdx.x];
+    search_body<STREAM_ROWS, true, WIDE_MAXT, true, true, false, false, true>(it, sm);
+}
+
 // Streamed search, one per workgroup: block b runs search job0 + b of the launch.  WIDE
 // (n above WIDE_N): G and G^T in global scratch, up to four (index, family) tasks a lane.
 template <bool TABU, bool FREQ = false, bool WIDE = false>
@@ -1299,6 +1408,8 @@ __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     it.div = FREQ ? a.div : 0;
     it.attr = FREQ ? a.attr : 0;
     it.uloc = FREQ && a.uloc ? a.uloc + (size_t)job * a.n * a.n : nullptr;
+    it.trace = FREQ && a.trace ? a.trace + (size_t)job * a.trace_cap * 4 : nullptr;
+    it.trace_cap = FREQ ? a.trace_cap : 0;
     it.n = a.n;
     it.m = a.m;
     it.sym = a.sym;
@@ -1378,7 +1489,7 @@ int search_lanes(int n, int rows, int ntiles, int sym) {
 }
 
 int batch_variant(int n, int rows, bool streamed, int ntiles, int sym) {
-    if (streamed) return BV_STREAM;
+    if (streamed) return n > WIDE_N ? BV_WIDE : BV_STREAM;
     // lanes a one-task workgroup needs: one per tile and one per (index, family) task
     const int need = ntiles > families(sym) * n ? ntiles : families(sym) * n;
     if (rows == 2) return need <= 128 ? BV_R2_128 : (need <= 256 ? BV_R2_256 : BV_R2);
@@ -1421,6 +1532,11 @@ hipError_t launch_batch_group(int variant, const BatchArgs &b, size_t smem, hipS
         case BV_STREAM:
             hipLaunchKernelGGL((batch_group_kernel<STREAM_ROWS, L, T, true>), dim3(b.count), dim3(L), smem, st, b);
             break;
+        case BV_WIDE:
+            if (!b.gwork) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((batch_group_kernel<STREAM_ROWS, L, WIDE_MAXT, true, true>), dim3(b.count), dim3(L),
+                               smem, st, b);
+            break;
         default: return hipErrorInvalidValue;
     }
     return report(hipGetLastError(), "batch kernel launch");
@@ -1431,6 +1547,12 @@ hipError_t launch_batch_freq(const BatchArgs &b, size_t smem, hipStream_t st) {
     if (b.count <= 0) return hipSuccess;
     hipLaunchKernelGGL(batch_freq_kernel, dim3(b.count), dim3(BATCH_LANES), smem, st, b);
     return report(hipGetLastError(), "batch kernel launch");
+}
+
+hipError_t launch_resume_wide(const Item *d_items, int count, size_t smem, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(resume_wide_kernel, dim3(count), dim3(BATCH_LANES), smem, st, d_items);
+    return report(hipGetLastError(), "resume kernel launch");
 }
 
 hipError_t launch_resume(const Item *d_items, int count, size_t smem, hipStream_t st) {

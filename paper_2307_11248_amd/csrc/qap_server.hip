@@ -87,14 +87,15 @@ private:
 
 // Byte layout of one request's device state inside the pool.  Register-tile searches
 // save their neighbourhood as (delta, tabu until) pairs between chunks (st_du); streamed
-// searches keep their tiles in tile_work throughout.
+// searches keep their tiles in tile_work throughout, and above WIDE_N also G and G^T in
+// gwork (rebuilt from the saved permutation at the start of every chunk).
 struct Layout {
-    size_t mats, perm, st_perm, st_bestp, table, st_du, tile_work, total;
+    size_t mats, perm, st_perm, st_bestp, table, st_du, tile_work, gwork, total;
 };
 
 // own_mats: the request brought its own F and D (a copy lives in the pool); otherwise it
 // runs on an existing handle's device matrices.
-Layout layout_for(int n, bool streamed, int ntiles, bool own_mats = true) {
+Layout layout_for(int n, int sym, bool streamed, int ntiles, bool own_mats = true) {
     const size_t m = (size_t)n * (n - 1) / 2;
     Layout L{};
     size_t o = 0;
@@ -105,6 +106,7 @@ Layout layout_for(int n, bool streamed, int ntiles, bool own_mats = true) {
     L.table = o;    o += up(m * 4 + 16);
     L.st_du = o;    if (!streamed) o += up(m * 8 + 16);
     L.tile_work = o; if (streamed) o += up((size_t)stream_tile_int4(ntiles) * sizeof(int4));
+    L.gwork = o;    if (n > WIDE_N) o += up((size_t)wide_g_bytes(n, sym));
     L.total = o;
     return L;
 }
@@ -206,14 +208,12 @@ const Tiles *tiles_for(qap_server *s, int n, int rows, int *rc) {
 }
 
 // The tile shape a request runs with: the smallest of 2, 4, 8 rows that fits the
-// register-tile kernel, else the streamed kernel (rows = -STREAM_ROWS); -1 if none.
+// register-tile kernel, else the streamed kernel (rows = -STREAM_ROWS; its wide form
+// above WIDE_N); -1 if none.
 int server_rows(qap_server *s, int n, int sym, int *rc) {
     *rc = QAP_OK;
-    if (n > WIDE_N) {   // the wide streamed kernel serves single-instance searches only
-        *rc = QAP_E_UNSUPPORTED;
-        return -1;
-    }
     for (int rows : {2, 4, 8}) {
+        if (n > WIDE_N) break;
         int ninner = 0;
         const int nt = (int)enumerate_tiles(n, rows, &ninner).size();
         if (batch_shape_ok(n, rows, nt, sym) && search_smem_bytes(n, rows, BATCH_LANES, sym) <= s->max_smem)
@@ -244,6 +244,7 @@ Item make_item(qap_server *s, const Request *r) {
         it.tile_d = reinterpret_cast<int4 *>(base + r->lay.tile_work);
         it.tile_u = it.tile_d + stream_tile_int4(ts.ntiles) / 2;
     }
+    if (r->n > WIDE_N) it.gmat = base + r->lay.gwork;
     it.n = r->n;
     it.m = r->m;
     it.sym = r->sym;
@@ -294,7 +295,7 @@ int plan_request(qap_server *s, Request *r, int n) {
     if (rc != QAP_OK) return rc;
     r->streamed = r->rows < 0;
     const Tiles &ts = s->tiles[n * 16 + (r->streamed ? STREAM_ROWS : r->rows)];
-    r->lay = layout_for(n, r->streamed, ts.ntiles, r->ext_mats == nullptr);
+    r->lay = layout_for(n, r->sym, r->streamed, ts.ntiles, r->ext_mats == nullptr);
     if (up(r->lay.total) > s->pool_bytes) return QAP_E_NOMEM;   // could never be admitted
     return QAP_OK;
 }
@@ -303,9 +304,9 @@ int plan_request(qap_server *s, Request *r, int n) {
 // Called with s->step_mu held; takes s->mu only around the shared state.
 int step_locked(qap_server *s, int32_t *active_out, int32_t *pending_out) {
     hipError_t e = hipSuccess;
-    int nnew = 0, count = 0;
-    size_t smem = 0, tsmem = 0;
-    std::vector<Request *> admitted, injected;
+    int nnew = 0, count = 0, nnarrow = 0;
+    size_t smem = 0, wsmem = 0, tsmem = 0;
+    std::vector<Request *> admitted, injected, fresh_wide;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         // cancelled searches leave now
@@ -341,14 +342,23 @@ int step_locked(qap_server *s, int32_t *active_out, int32_t *pending_out) {
         }
         s->pending.swap(still);
         count = (int)s->active.size();
+        // searches above WIDE_N (the wide streamed form) go last: a launch of their own
+        std::stable_partition(s->active.begin(), s->active.end(), [](const Request *r) { return r->n <= WIDE_N; });
         for (int i = 0; i < count; ++i) {
             Request *r = s->active[i];
             s->h_items[i] = make_item(s, r);
-            smem = std::max(smem, r->streamed ? stream_smem_bytes(r->n, r->sym)
-                                              : search_smem_bytes(r->n, r->rows, BATCH_LANES, r->sym));
+            const bool wide = r->n > WIDE_N;
+            if (!wide) ++nnarrow;
+            size_t &sm = wide ? wsmem : smem;
+            sm = std::max(sm, r->streamed ? stream_smem_bytes(r->n, r->sym)
+                                          : search_smem_bytes(r->n, r->rows, BATCH_LANES, r->sym));
             if (r->fresh) {
-                s->h_new[nnew++] = s->h_items[i];
-                tsmem = std::max(tsmem, table_smem_bytes(r->n));
+                if (wide) {
+                    fresh_wide.push_back(r);
+                } else {
+                    s->h_new[nnew++] = s->h_items[i];
+                    tsmem = std::max(tsmem, table_smem_bytes(r->n));
+                }
                 r->fresh = false;
             }
             if (r->inject) {
@@ -376,6 +386,14 @@ int step_locked(qap_server *s, int32_t *active_out, int32_t *pending_out) {
         if (e == hipSuccess)
             e = hipMemcpyAsync(s->d_items, s->h_items, (size_t)count * sizeof(Item), hipMemcpyHostToDevice, s->st);
         if (e == hipSuccess && nnew) e = launch_table_items(s->d_new, nnew, tsmem, s->st);
+        for (Request *r : fresh_wide) {   // Eq. (2) entry by entry above WIDE_N
+            if (e != hipSuccess) break;
+            uint8_t *base = s->pool + r->off;
+            const TableArgs ta{r->ext_mats ? r->ext_mats : base + r->lay.mats,
+                               reinterpret_cast<const int32_t *>(base + r->lay.perm), nullptr,
+                               reinterpret_cast<int32_t *>(base + r->lay.table), r->n, r->m, 1, r->sym};
+            e = launch_table(ta, s->st);
+        }
         // test hook: a corrupted saved permutation (every entry 0), which the search
         // detects when it resumes; it then stops with its failure code
         for (Request *r : injected) {
@@ -384,7 +402,8 @@ int step_locked(qap_server *s, int32_t *active_out, int32_t *pending_out) {
             e = hipMemsetAsync(base + r->lay.perm, 0, (size_t)r->n * 4, s->st);
             if (e == hipSuccess) e = hipMemsetAsync(base + r->lay.st_perm, 0, (size_t)r->n * 4, s->st);
         }
-        if (e == hipSuccess) e = launch_resume(s->d_items, count, smem, s->st);
+        if (e == hipSuccess) e = launch_resume(s->d_items, nnarrow, smem, s->st);
+        if (e == hipSuccess) e = launch_resume_wide(s->d_items + nnarrow, count - nnarrow, wsmem, s->st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(s->h_state, s->d_state, (size_t)s->max_active * sizeof(SearchState),
                                hipMemcpyDeviceToHost, s->st);
@@ -512,7 +531,7 @@ int64_t qap_server_footprint(qap_server_handle s, int32_t n, int32_t sym) {
     if (rc != QAP_OK) return rc;
     int ninner = 0;
     const int nt = (int)enumerate_tiles(n, rows < 0 ? STREAM_ROWS : rows, &ninner).size();
-    return (int64_t)layout_for(n, rows < 0, nt).total;
+    return (int64_t)layout_for(n, sym ? 1 : 0, rows < 0, nt).total;
 }
 
 int qap_server_submit_matrices(qap_server_handle s, const int32_t *F, const int32_t *D, int32_t n,

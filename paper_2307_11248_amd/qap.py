@@ -28,12 +28,12 @@ QAP_E_UNSUPPORTED = -7
 QAP_E_SCRATCH = -8
 QAP_NOALLOC_SCRATCH_BYTES = 64 << 20
 QAP_NMAX = 512
-QAP_NMAX_BATCH = 256   # batched and served searches
+QAP_NMAX_BATCH = 512   # batched and served searches
 
 EXPORTS = [
     "qap_strerror", "qap_create", "qap_destroy", "qap_size", "qap_cost", "qap_cost_async", "qap_delta_table",
     "qap_delta_table_async", "qap_2opt", "qap_2opt_async", "qap_tabu", "qap_tabu_async", "qap_tabu_noalloc_async",
-    "qap_tabu_freq_async",
+    "qap_tabu_freq_async", "qap_tabu_trace_async",
     "qap_tabu_plain_async", "qap_2opt_with_table_async", "qap_tabu_with_table_async", "qap_set_tile_rows",
     "qap_get_tile_rows", "qap_launch_tile_rows", "qap_batch_create", "qap_batch_create_freq", "qap_batch_freq_async", "qap_batch_size", "qap_batch_groups",
     "qap_batch_run_async",
@@ -88,6 +88,8 @@ def lib():
                                                           _vp]),
                 "qap_tabu_freq_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, i32, i32, _vp,
                                                         _vp, _vp, _vp]),
+                "qap_tabu_trace_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, i32, i32, _vp,
+                                                        _vp, _vp, _vp, i32, _vp]),
                 "qap_tabu_plain_async": (ctypes.c_int, [_vp, _vp, i32, i32, i32, i32, u64, i64, _vp, _vp,
                                                         _vp]),
                 "qap_2opt_with_table_async": (ctypes.c_int, [_vp, _vp, _vp, i32, i32, _vp, _vp, _vp]),
@@ -317,6 +319,19 @@ class Handle:
                                          _dptr(d_done, "int32"), _dptr(d_freq, "int32"), _stream_ptr(stream)),
                "qap_tabu_freq_async")
 
+    def tabu_trace_async(self, d_perms, iters, lo, hi, seed, d_best, d_freq, d_trace, d_done=None,
+                         start_base: int = 0, div: int = 0, attr: int = 0, stream=None):
+        """tabu_freq_async that also records the first d_trace.shape[1] moves of every start
+        as (r, s, delta, cost after) into d_trace (int64[k][cap][4]) (``qap_tabu_trace_async``)."""
+        cap = int(d_trace.shape[1]) if d_trace.dim() == 3 else 0
+        if d_trace.dim() != 3 or d_trace.shape[0] != d_perms.shape[0] or d_trace.shape[2] != 4:
+            raise ValueError("d_trace must be int64[k][cap][4]")
+        _check(lib().qap_tabu_trace_async(self.ptr, _dptr(d_perms, "int32"), d_perms.shape[0], int(iters), int(lo),
+                                          int(hi), int(seed), int(start_base), int(div), int(attr),
+                                          _dptr(d_best, "int64"), _dptr(d_done, "int32"), _dptr(d_freq, "int32"),
+                                          _dptr(d_trace, "int64"), cap, _stream_ptr(stream)),
+               "qap_tabu_trace_async")
+
     def two_opt_with_table_async(self, d_perms, d_table, d_costs, d_steps=None, max_iters: int = 0, stream=None):
         _check(lib().qap_2opt_with_table_async(self.ptr, _dptr(d_perms, "int32"), _dptr(d_table, "int32"),
                                                d_perms.shape[0], int(max_iters), _dptr(d_costs, "int64"),
@@ -384,8 +399,8 @@ class Batch:
 
     def groups(self, counts: bool = False):
         """Kernel dispatches of one search phase (one per tile-shape variant in use); with
-        counts=True also the searches per variant (int32[8], the header's order)."""
-        c = np.zeros(8, dtype=np.int32)
+        counts=True also the searches per variant (int32[9], the header's order)."""
+        c = np.zeros(9, dtype=np.int32)
         g = _check(lib().qap_batch_groups(self._b, _ptr(c, _i32p)), "qap_batch_groups")
         return (g, c) if counts else g
 

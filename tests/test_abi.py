@@ -70,7 +70,7 @@ def test_binding_size_limits_match_the_header():
     txt = open(os.path.join(ROOT, "include", "qap.h")).read()
     defs = dict(re.findall(r"#define (QAP_NMAX\w*) (\d+)", txt))
     assert int(defs["QAP_NMAX"]) == qap.QAP_NMAX == 512
-    assert int(defs["QAP_NMAX_BATCH"]) == qap.QAP_NMAX_BATCH == 256
+    assert int(defs["QAP_NMAX_BATCH"]) == qap.QAP_NMAX_BATCH == 512
 
 
 def test_noalloc_scratch_size_matches_the_header():

@@ -264,8 +264,9 @@ def test_batch_full_size_every_variant_sampled():
     with qap.Batch(hs, [k] * m, w.iters, lo, hi, seeds) as b:
         _, counts = b.groups(counts=True)
         expect = [k * kind.count(v) for v in VARIANTS]
-        assert list(counts) == expect, (list(counts), expect)
-        assert all(c > 0 for c in counts), counts
+        assert list(counts[:len(VARIANTS)]) == expect, (list(counts), expect)
+        assert all(c > 0 for c in counts[:len(VARIANTS)]), counts
+        assert counts[len(VARIANTS)] == 0   # no instance above n = 256 here
         b.run_async(work, best, done)
         torch.cuda.synchronize()
     ep, ec, ed = work.cpu().numpy(), best.cpu().numpy(), done.cpu().numpy()

@@ -104,24 +104,91 @@ def test_wide_extreme_entries_and_plain_launches():
         assert (p[j] == r[0]).all() and c[j] == r[1] and d[j] == r[2], j
 
 
-def test_wide_paths_that_stop_at_256_say_so():
+def test_wide_register_tiles_say_so():
     n = 300
     rng = np.random.default_rng(9400)
     F, D = W.random_instance(rng, n, 0, 99)
-    perms = W.starts(rng, n, 1)
-    note("wide rejections n=300")
+    note("wide register-tile rejections n=300")
     with qap.Handle(F, D) as h:
         for rows in (1, 2, 4, 8, 16):
             with pytest.raises(qap.QapError) as ei:
                 h.set_tile_rows("tabu", rows)
             assert ei.value.code == qap.QAP_E_UNSUPPORTED
-        with pytest.raises(qap.QapError) as ei:
-            qap.tabu_batch([h], perms.reshape(-1), [1], 10, [30], [90], [1])
-        assert ei.value.code == qap.QAP_E_UNSUPPORTED
-    with qap.Server(1 << 26, 4, 0.1) as s:
-        with pytest.raises(qap.QapError) as ei:
-            s.footprint(n)
-        assert ei.value.code == qap.QAP_E_UNSUPPORTED
+
+
+def test_wide_in_a_batch_equals_the_oracle():
+    """Instances above n = 256 (the wide streamed form, G in the plan's scratch, their
+    starting tables by Eq. (2)) beside register-tile and streamed ones in one batch, run
+    twice from a captured-graph-free plan: every start equals oracle.tabu."""
+    sizes, ks, iters = [300, 40, 384, 200, 257], [2, 2, 1, 1, 1], 120
+    rng = np.random.default_rng(9410)
+    insts, lohi, seeds = [], [], []
+    for t, n in enumerate(sizes):
+        F, D = W.random_instance(rng, n, 0, 99, symmetric=(t == 2))
+        insts.append((F, D, W.starts(rng, n, ks[t])))
+        lohi.append(W.paper_tenure_range(n))
+        seeds.append(int(rng.integers(0, 2**62)))
+    note("wide batch sizes=%s k=%s iters=%d" % (sizes, ks, iters))
+    hs = [qap.Handle(F, D) for F, D, _ in insts]
+    perms = np.concatenate([P.reshape(-1) for _, _, P in insts]).astype(np.int32)
+    p, c, d = qap.tabu_batch(hs, perms, ks, iters, [a for a, _ in lohi], [b for _, b in lohi], seeds)
+    jobs = [(i, j) for i in range(len(sizes)) for j in range(ks[i])]
+    res = pmap(lambda a: oracle.tabu(insts[a[0]][0], insts[a[0]][1], insts[a[0]][2][a[1]], iters,
+                                     lohi[a[0]][0], lohi[a[0]][1], seeds[a[0]], a[1]), jobs)
+    off = 0
+    for t, ((i, j), r) in enumerate(zip(jobs, res)):
+        n = sizes[i]
+        assert (p[off:off + n] == r[0]).all() and c[t] == r[1] and d[t] == r[2], (i, j)
+        off += n
+    for h in hs:
+        h.close()
+
+
+def test_wide_in_the_server_equals_the_oracle():
+    """Requests above n = 256 served in chunks beside smaller ones (a launch of the wide
+    resume kernel of their own each step): every result equals oracle.tabu."""
+    sizes, iters = [300, 60, 260, 180], [160, 400, 120, 200]
+    rng = np.random.default_rng(9420)
+    reqs = []
+    for n, it in zip(sizes, iters):
+        F, D = W.random_instance(rng, n, 0, 99)
+        reqs.append((F, D, W.starts(rng, n, 1)[0], it, W.tabu_tenure_range(n), int(rng.integers(0, 2**62))))
+    note("wide server sizes=%s iters=%s" % (sizes, iters))
+    with qap.Server(1 << 28, 8, 0.3) as s:
+        tickets = [s.submit(F, D, p0, it, lo, hi, seed) for F, D, p0, it, (lo, hi), seed in reqs]
+        out = {}
+        for _ in range(10000):
+            s.step()
+            for t in tickets:
+                if t not in out:
+                    r = s.poll(t)
+                    if r is not None:
+                        out[t] = r
+            if len(out) == len(tickets):
+                break
+        assert len(out) == len(tickets)
+        assert s.stats()["steps"] > 1   # chunked
+    res = pmap(lambda q: oracle.tabu(q[0], q[1], q[2], q[3], q[4][0], q[4][1], q[5], 0), reqs)
+    for t, r in zip(tickets, res):
+        assert (out[t][0] == r[0]).all() and out[t][1] == r[1], t
+
+
+@pytest.mark.parametrize("sym", [False, True])
+def test_wide_short_tenure_past_the_tenure_ring(sym):
+    """n = 512 with the paper's short tenure and more iterations than the 512-entry tenure
+    ring holds, so tabu expiry, aspiration against expired moves and the ring refill all
+    run on the wide kernel, against oracle.tabu."""
+    n, k, iters = 512, 2, 700
+    rng = np.random.default_rng(9430 + sym)
+    F, D = W.random_instance(rng, n, 0, 99, symmetric=sym)
+    perms = W.starts(rng, n, k)
+    lo, hi = W.paper_tenure_range(n)
+    note("wide short tenure n=512 sym=%d iters=%d" % (sym, iters))
+    with qap.Handle(F, D) as h:
+        p, c, d = h.tabu(perms, iters, lo, hi, 21)
+    res = pmap(lambda j: oracle.tabu(F, D, perms[j], iters, lo, hi, 21, j), range(k))
+    for j, r in enumerate(res):
+        assert (p[j] == r[0]).all() and c[j] == r[1] and d[j] == r[2], j
 
 
 def test_wide_table_taking_entry_points_and_full_descent():
