@@ -87,7 +87,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3-2opt", "c3-tabu", "c4", "c5", "wide"])
-    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="tile rows of the searches (uneven batch: for every instance it fits, else the tuner's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-start comparison")
     ap.add_argument("--cpu-starts", type=int, default=32,
@@ -195,6 +196,13 @@ def run_batch(args, w):
         rows = cache.apply_all(hs, "batch")
         cache.save()
         tune_s = time.perf_counter() - t0
+        if args.tile_rows:
+            for t, h in enumerate(hs):
+                try:
+                    h.set_tile_rows("batch", args.tile_rows)
+                    rows[t] = args.tile_rows
+                except qap.QapError:
+                    pass
         rows_hist = {str(r): rows.count(r) for r in sorted(set(rows))}
     b = qap.Batch(hs, [k] * m, w.iters, lo, hi, seeds)
     stream = torch.cuda.Stream()

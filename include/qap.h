@@ -378,6 +378,22 @@ int qap_server_submit_matrices(qap_server_handle s, const int32_t *F, const int3
                                const int32_t *start, int32_t iters, int32_t lo, int32_t hi, uint64_t seed,
                                int64_t *ticket_out);
 int qap_server_set_queue_limit(qap_server_handle s, int32_t max_queued);
+/*
+ * A served request with the extensions of qap_tabu_freq_async (div, attr as there): the
+ * search keeps the frequency memory of Sec. 4.3 in the pool (with attr 2 its unit-location
+ * table, with attr 1 its unit marks between chunks, n (n - 1) / 2 + n^2 or + n int32 more),
+ * and its result equals qap_tabu_freq_async on the handle with start_base 0, however it
+ * was chunked.  Such requests run in a launch of their own each step.  On a handle only;
+ * QAP_E_UNSUPPORTED above n = 256; otherwise as qap_server_submit.
+ * qap_server_poll_freq is qap_server_poll that also copies the counts into freq_out (host
+ * int32[n (n - 1) / 2], packed pair order; may be NULL); QAP_E_INVALID, leaving the
+ * request alone, if freq_out is not NULL and the request was not submitted this way.
+ */
+int qap_server_submit_freq(qap_server_handle s, qap_handle h, const int32_t *start, int32_t iters,
+                           int32_t lo, int32_t hi, uint64_t seed, int32_t div, int32_t attr,
+                           int64_t *ticket_out);
+int qap_server_poll_freq(qap_server_handle s, int64_t ticket, int32_t *best_perm, int64_t *best_cost,
+                         int32_t *freq_out);
 int qap_server_step(qap_server_handle s, int32_t *active_out, int32_t *pending_out);
 int qap_server_start(qap_server_handle s);
 int qap_server_stop(qap_server_handle s);

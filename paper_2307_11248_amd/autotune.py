@@ -19,6 +19,11 @@ import tempfile
 
 from . import qap
 
+# Relative time difference below which two tile shapes of a batched search count as
+# equally fast, and the size of the timing runs of batched shapes.
+BATCH_MARGIN = 0.03
+BATCH_STARTS, BATCH_ITERS = 4096, 150
+
 DEFAULT_PATH = os.path.join(os.path.expanduser("~"), ".cache", "paper_2307_11248_amd", "tile_rows.json")
 
 
@@ -63,9 +68,22 @@ class TileCache:
             except qap.QapError:
                 pass                      # the cached shape no longer fits: measure again
         # the batched kernels run several searches per compute unit: time enough searches
-        # to fill the device, so the choice reflects throughput, not one search's latency
-        starts = max(self.k, 1024) if algo == "batch" else self.k
-        rows, times = h.tune_tile_rows(algo, starts, self.iters)
+        # to fill the device several times over (4096, about 16 a compute unit, more than
+        # fit at once), so the choice reflects throughput, not one search's latency
+        if algo == "batch":
+            starts, iters = max(self.k, BATCH_STARTS), BATCH_ITERS
+        else:
+            starts, iters = self.k, self.iters
+        rows, times = h.tune_tile_rows(algo, starts, iters)
+        if algo == "batch" and times:
+            # shapes within BATCH_MARGIN of the fastest time within noise of each other; take
+            # the largest register tile among them (fewer lanes per search, so more searches
+            # share a compute unit in a mixed batch), which keeps the choice stable
+            fastest = min(times.values())
+            near = [r for r, t in times.items() if r > 0 and t <= fastest * (1 + BATCH_MARGIN)]
+            if near and max(near) != rows:
+                rows = max(near)
+                h.set_tile_rows(algo, rows)
         self.entries[k] = {"rows": rows, "ms": {str(r): t for r, t in times.items()}}
         self.tuned += 1
         return rows

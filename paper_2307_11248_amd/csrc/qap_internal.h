@@ -155,7 +155,7 @@ struct SearchState {
     int it;      // next iteration to run, 1-based; 1 = not started
     int done;    // 1 once the last iteration ran or no move was allowed
     int moves;   // moves made so far
-    int pad;
+    int last_imp;   // with the frequency memory: the iteration of the last new best or diversification
 };
 
 // One search as the search kernels see it.
@@ -197,6 +197,7 @@ struct Item {
     // to a location it left (a move is tabu when both units would return)
     int attr;
     int32_t *uloc;            // attr 2: [n][n], unit x location -> until when it may not return
+    int32_t *st_mark;         // attr 1, chunked runs: the unit marks per location, kept between chunks
     // batched plans that keep the frequency memory: offsets of freq and uloc in the
     // plan's buffers (host side, while the plan is built)
     long long freq_off, uloc_off;
@@ -282,6 +283,8 @@ hipError_t launch_stream(bool tabu, const SearchArgs &a, int grid, hipStream_t s
 // items that start now (into their `table`), then one chunk of every item.
 hipError_t launch_table_items(const Item *d_items, int count, size_t smem, hipStream_t st);
 hipError_t launch_resume(const Item *d_items, int count, size_t smem, hipStream_t st);
+// The same for items that keep the frequency memory (n up to WIDE_N).
+hipError_t launch_resume_freq(const Item *d_items, int count, size_t smem, hipStream_t st);
 // The same for items above WIDE_N (the wide streamed form; Item::gmat set).
 hipError_t launch_resume_wide(const Item *d_items, int count, size_t smem, hipStream_t st);
 // Lanes of a search workgroup for a tile shape, or 0 if the shape cannot serve n.

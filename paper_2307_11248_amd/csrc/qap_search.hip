@@ -344,9 +344,10 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     }
     if (t == 0) s_bad = 0;
     for (int u = t; u < np; u += L) pinv[u] = -1;
-    if (FREQ && a.freq)
+    // (a resumed search keeps its counts and unit-location table from earlier chunks)
+    if (FREQ && a.freq && !resume)
         for (int i = t; i < a.m; i += L) a.freq[i] = 0;
-    if (FREQ && a.attr == 2)
+    if (FREQ && a.attr == 2 && !resume)
         for (int i = t; i < n * n; i += L) a.uloc[i] = 0;
     __syncthreads();
     const int32_t *pin = resume ? a.st_perm : a.perm_in;
@@ -585,9 +586,10 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     if (t >= W && t < 16) red[t] = NO_MOVE;   // unused wave-minimum slots
     if constexpr (FREQ) {
         if (t >= W && t < 16) s_red2[t] = NO_MOVE;
-        for (int u = t; u < np; u += L) s_mark[u] = 0;
+        for (int u = t; u < np; u += L) s_mark[u] = RESUME && resume && a.st_mark && u < n ? a.st_mark[u] : 0;
     }
-    int last_imp = 0;   // diversification: the iteration of the last new best
+    // diversification: the iteration of the last new best (kept between chunks)
+    int last_imp = FREQ && RESUME && resume ? st->last_imp : 0;
     bool stopped = false;
     __syncthreads();
 
@@ -1248,12 +1250,15 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             a.st_perm[u] = perm[u];
             a.st_bestp[u] = bestp[u];
         }
+        if (FREQ && a.st_mark)
+            for (int u = t; u < n; u += L) a.st_mark[u] = s_mark[u];
         if (t == 0) {
             st->cur = cur;
             st->best = best;
             st->it = it;
             st->moves = moves;
             st->done = finished ? 1 : 0;
+            st->last_imp = last_imp;
         }
     }
     if (finished) {
@@ -1379,6 +1384,23 @@ __global__ void __launch_bounds__(BATCH_LANES) resume_kernel(const Item *items) 
         case 2: search_body<2, true, 1024 / BATCH_LANES, true, false, true>(it, sm); break;
         case 4: search_body<4, true, 1024 / BATCH_LANES, true, false, true>(it, sm); break;
         default: search_body<8, true, 1024 / BATCH_LANES, true, false, true>(it, sm); break;
+    }
+}
+
+// Chunked runs of searches that keep the frequency memory: block i runs one chunk of
+// items[i] (tiles of 2, 4, 8 rows or the streamed form, n up to WIDE_N).
+__global__ void __launch_bounds__(BATCH_LANES) resume_freq_kernel(const Item *items) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    const Item it = items[blockIdx.x];
+    constexpr int T = 1024 / BATCH_LANES;
+    if (it.stream) {
+        search_body<STREAM_ROWS, true, T, true, true, false, true>(it, sm);
+        return;
+    }
+    switch (it.rows) {
+        case 2: search_body<2, true, T, true, false, false, true>(it, sm); break;
+        case 4: search_body<4, true, T, true, false, false, true>(it, sm); break;
+        default: search_body<8, true, T, true, false, false, true>(it, sm); break;
     }
 }
 
@@ -1547,6 +1569,12 @@ hipError_t launch_batch_freq(const BatchArgs &b, size_t smem, hipStream_t st) {
     if (b.count <= 0) return hipSuccess;
     hipLaunchKernelGGL(batch_freq_kernel, dim3(b.count), dim3(BATCH_LANES), smem, st, b);
     return report(hipGetLastError(), "batch kernel launch");
+}
+
+hipError_t launch_resume_freq(const Item *d_items, int count, size_t smem, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(resume_freq_kernel, dim3(count), dim3(BATCH_LANES), smem, st, d_items);
+    return report(hipGetLastError(), "resume kernel launch");
 }
 
 hipError_t launch_resume_wide(const Item *d_items, int count, size_t smem, hipStream_t st) {

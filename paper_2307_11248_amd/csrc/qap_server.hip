@@ -90,12 +90,14 @@ private:
 // searches keep their tiles in tile_work throughout, and above WIDE_N also G and G^T in
 // gwork (rebuilt from the saved permutation at the start of every chunk).
 struct Layout {
-    size_t mats, perm, st_perm, st_bestp, table, st_du, tile_work, gwork, total;
+    size_t mats, perm, st_perm, st_bestp, table, st_du, tile_work, gwork, freq, uloc, st_mark, total;
 };
 
 // own_mats: the request brought its own F and D (a copy lives in the pool); otherwise it
 // runs on an existing handle's device matrices.
-Layout layout_for(int n, int sym, bool streamed, int ntiles, bool own_mats = true) {
+// freq: the request keeps the frequency memory (counts per packed pair), and with attr 2
+// the unit-location table, with attr 1 the unit marks between chunks.
+Layout layout_for(int n, int sym, bool streamed, int ntiles, bool own_mats = true, bool freq = false, int attr = 0) {
     const size_t m = (size_t)n * (n - 1) / 2;
     Layout L{};
     size_t o = 0;
@@ -107,6 +109,9 @@ Layout layout_for(int n, int sym, bool streamed, int ntiles, bool own_mats = tru
     L.st_du = o;    if (!streamed) o += up(m * 8 + 16);
     L.tile_work = o; if (streamed) o += up((size_t)stream_tile_int4(ntiles) * sizeof(int4));
     L.gwork = o;    if (n > WIDE_N) o += up((size_t)wide_g_bytes(n, sym));
+    L.freq = o;     if (freq) o += up(m * 4 + 16);
+    L.uloc = o;     if (freq && attr == 2) o += up((size_t)n * n * 4);
+    L.st_mark = o;  if (freq && attr == 1) o += up((size_t)n * 4);
     L.total = o;
     return L;
 }
@@ -116,6 +121,8 @@ struct Request {
     int n = 0, m = 0, sym = 0, rows = 0, iters = 0, lo = 0, hi = 0;
     bool streamed = false;
     uint64_t seed = 0;
+    bool freq = false;       // keeps the frequency memory (qap_server_submit_freq)
+    int div = 0, attr = 0;
     std::vector<uint8_t> mats;          // own copy of [F | F^T | D | D^T], or empty
     const uint8_t *ext_mats = nullptr;  // else the device matrices of a handle
     std::vector<int32_t> start;
@@ -131,6 +138,8 @@ struct Request {
 
 struct Result {
     std::vector<int32_t> perm;
+    std::vector<int32_t> freq;   // exchange counts, for requests that kept them
+    bool has_freq = false;
     int64_t best = 0;
     int32_t moves = 0;
     int status = QAP_OK;     // QAP_E_DEVICE when the search failed on the device
@@ -245,6 +254,13 @@ Item make_item(qap_server *s, const Request *r) {
         it.tile_u = it.tile_d + stream_tile_int4(ts.ntiles) / 2;
     }
     if (r->n > WIDE_N) it.gmat = base + r->lay.gwork;
+    if (r->freq) {
+        it.freq = reinterpret_cast<int32_t *>(base + r->lay.freq);
+        it.div = r->div;
+        it.attr = r->attr;
+        if (r->attr == 2) it.uloc = reinterpret_cast<int32_t *>(base + r->lay.uloc);
+        if (r->attr == 1) it.st_mark = reinterpret_cast<int32_t *>(base + r->lay.st_mark);
+    }
     it.n = r->n;
     it.m = r->m;
     it.sym = r->sym;
@@ -295,7 +311,7 @@ int plan_request(qap_server *s, Request *r, int n) {
     if (rc != QAP_OK) return rc;
     r->streamed = r->rows < 0;
     const Tiles &ts = s->tiles[n * 16 + (r->streamed ? STREAM_ROWS : r->rows)];
-    r->lay = layout_for(n, r->sym, r->streamed, ts.ntiles, r->ext_mats == nullptr);
+    r->lay = layout_for(n, r->sym, r->streamed, ts.ntiles, r->ext_mats == nullptr, r->freq, r->attr);
     if (up(r->lay.total) > s->pool_bytes) return QAP_E_NOMEM;   // could never be admitted
     return QAP_OK;
 }
@@ -304,8 +320,8 @@ int plan_request(qap_server *s, Request *r, int n) {
 // Called with s->step_mu held; takes s->mu only around the shared state.
 int step_locked(qap_server *s, int32_t *active_out, int32_t *pending_out) {
     hipError_t e = hipSuccess;
-    int nnew = 0, count = 0, nnarrow = 0;
-    size_t smem = 0, wsmem = 0, tsmem = 0;
+    int nnew = 0, count = 0, ngroup[3] = {0, 0, 0};
+    size_t smem = 0, fsmem = 0, wsmem = 0, tsmem = 0;
     std::vector<Request *> admitted, injected, fresh_wide;
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -342,14 +358,18 @@ int step_locked(qap_server *s, int32_t *active_out, int32_t *pending_out) {
         }
         s->pending.swap(still);
         count = (int)s->active.size();
-        // searches above WIDE_N (the wide streamed form) go last: a launch of their own
-        std::stable_partition(s->active.begin(), s->active.end(), [](const Request *r) { return r->n <= WIDE_N; });
+        // one launch per kernel: plain searches up to WIDE_N, then those that keep the
+        // frequency memory, then those above WIDE_N (the wide streamed form)
+        auto group = [](const Request *r) { return r->n > WIDE_N ? 2 : (r->freq ? 1 : 0); };
+        std::stable_sort(s->active.begin(), s->active.end(),
+                         [&](const Request *x, const Request *y) { return group(x) < group(y); });
         for (int i = 0; i < count; ++i) {
             Request *r = s->active[i];
             s->h_items[i] = make_item(s, r);
-            const bool wide = r->n > WIDE_N;
-            if (!wide) ++nnarrow;
-            size_t &sm = wide ? wsmem : smem;
+            const int gr = group(r);
+            const bool wide = gr == 2;
+            ++ngroup[gr];
+            size_t &sm = gr == 2 ? wsmem : (gr == 1 ? fsmem : smem);
             sm = std::max(sm, r->streamed ? stream_smem_bytes(r->n, r->sym)
                                           : search_smem_bytes(r->n, r->rows, BATCH_LANES, r->sym));
             if (r->fresh) {
@@ -402,8 +422,10 @@ int step_locked(qap_server *s, int32_t *active_out, int32_t *pending_out) {
             e = hipMemsetAsync(base + r->lay.perm, 0, (size_t)r->n * 4, s->st);
             if (e == hipSuccess) e = hipMemsetAsync(base + r->lay.st_perm, 0, (size_t)r->n * 4, s->st);
         }
-        if (e == hipSuccess) e = launch_resume(s->d_items, nnarrow, smem, s->st);
-        if (e == hipSuccess) e = launch_resume_wide(s->d_items + nnarrow, count - nnarrow, wsmem, s->st);
+        if (e == hipSuccess) e = launch_resume(s->d_items, ngroup[0], smem, s->st);
+        if (e == hipSuccess) e = launch_resume_freq(s->d_items + ngroup[0], ngroup[1], fsmem, s->st);
+        if (e == hipSuccess)
+            e = launch_resume_wide(s->d_items + ngroup[0] + ngroup[1], ngroup[2], wsmem, s->st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(s->h_state, s->d_state, (size_t)s->max_active * sizeof(SearchState),
                                hipMemcpyDeviceToHost, s->st);
@@ -427,10 +449,16 @@ int step_locked(qap_server *s, int32_t *active_out, int32_t *pending_out) {
             if (s->h_state[r->slot].done) fin.push_back(r);
     }
     perms.resize(fin.size());
+    std::vector<std::vector<int32_t>> freqs(fin.size());
     for (size_t i = 0; i < fin.size() && e == hipSuccess; ++i) {
         perms[i].resize(fin[i]->n);
         e = hipMemcpyAsync(perms[i].data(), s->pool + fin[i]->off + fin[i]->lay.perm, (size_t)fin[i]->n * 4,
                            hipMemcpyDeviceToHost, s->st);
+        if (e == hipSuccess && fin[i]->freq) {
+            freqs[i].resize(fin[i]->m);
+            e = hipMemcpyAsync(freqs[i].data(), s->pool + fin[i]->off + fin[i]->lay.freq, (size_t)fin[i]->m * 4,
+                               hipMemcpyDeviceToHost, s->st);
+        }
     }
     if (e == hipSuccess && !fin.empty()) e = hipStreamSynchronize(s->st);
     if (e != hipSuccess) return dev_err(e);
@@ -447,6 +475,8 @@ int step_locked(qap_server *s, int32_t *active_out, int32_t *pending_out) {
         } else {
             Result &res = s->done[r->ticket];
             res.perm.swap(perms[i]);
+            res.has_freq = r->freq;
+            res.freq.swap(freqs[i]);
             res.best = s->h_cost[r->slot];
             res.moves = s->h_moves[r->slot];
             // a search that found its state corrupted stops with moves = -2 (it never
@@ -569,6 +599,30 @@ int qap_server_submit(qap_server_handle s, qap_handle h, const int32_t *start, i
     return rc;
 }
 
+int qap_server_submit_freq(qap_server_handle s, qap_handle h, const int32_t *start, int32_t iters, int32_t lo,
+                           int32_t hi, uint64_t seed, int32_t div, int32_t attr, int64_t *ticket_out) {
+    const uint8_t *mats = nullptr;
+    int n = 0, sym = 0, dev = 0;
+    if (!s || !start || !ticket_out || !handle_view(h, &mats, &n, &sym, &dev) || !tenure_args_ok(iters, lo, hi) ||
+        div < 0 || attr < 0 || attr > 2)
+        return QAP_E_INVALID;
+    if (dev != s->device) return QAP_E_INVALID;
+    if (n > WIDE_N) return QAP_E_UNSUPPORTED;
+    if (!check_perms(start, 1, n)) return QAP_E_NOT_PERM;
+    Request *r = new (std::nothrow) Request;
+    if (!r) return QAP_E_NOMEM;
+    r->ext_mats = mats;
+    r->sym = sym;
+    r->freq = true;
+    r->div = div;
+    r->attr = attr;
+    std::lock_guard<std::mutex> lk(s->mu);
+    int rc = plan_request(s, r, n);
+    if (rc == QAP_OK) rc = enqueue(s, r, n, start, iters, lo, hi, seed, ticket_out);
+    if (rc != QAP_OK) delete r;
+    return rc;
+}
+
 int qap_server_set_queue_limit(qap_server_handle s, int32_t max_queued) {
     if (!s || max_queued < 1) return QAP_E_INVALID;
     std::lock_guard<std::mutex> lk(s->mu);
@@ -640,6 +694,28 @@ int qap_server_poll(qap_server_handle s, int64_t ticket, int32_t *best_perm, int
     if (rc == 1) {
         if (best_perm) std::copy(r.perm.begin(), r.perm.end(), best_perm);
         if (best_cost) *best_cost = r.best;
+    }
+    return rc;
+}
+
+int qap_server_poll_freq(qap_server_handle s, int64_t ticket, int32_t *best_perm, int64_t *best_cost,
+                         int32_t *freq_out) {
+    if (!s) return QAP_E_INVALID;
+    Result r;
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        // a request that kept no counts is left to qap_server_poll
+        auto st = s->state.find(ticket);
+        if (freq_out && st != s->state.end() && st->second == 2 && !s->done[ticket].has_freq) return QAP_E_INVALID;
+        auto lv = s->live.find(ticket);
+        if (freq_out && lv != s->live.end() && !lv->second->freq) return QAP_E_INVALID;
+        rc = take_result(s, ticket, &r);
+    }
+    if (rc == 1) {
+        if (best_perm) std::copy(r.perm.begin(), r.perm.end(), best_perm);
+        if (best_cost) *best_cost = r.best;
+        if (freq_out) std::copy(r.freq.begin(), r.freq.end(), freq_out);
     }
     return rc;
 }

@@ -159,55 +159,7 @@ __global__ void __launch_bounds__(256) cost_wide_kernel(TableArgs a) {
     }
 }
 
-// Neighbourhood row r of start `job` (block (r, job)): wave w evaluates the exchanges of
-// locations r and s = r + 1 + w, r + 1 + w + W, ... by Eq. (2), with G = F[p][p]:
-//   delta(r, s) = sum_{k != r, s} (G_sk - G_rk)(D_rk - D_sk) + (G_ks - G_kr)(D_kr - D_ks)
-//               + (G_ss - G_rr)(D_rr - D_ss) + (G_sr - G_rs)(D_rs - D_sr),
-// its 64 lanes splitting k (so each row of F, F^T, D, D^T at s is read by one wave, in
-// one contiguous stretch) and summing their parts at the end.  Row r's bytes (G_rk, G_kr,
-// D_rk, D_kr) are staged in LDS.
-__global__ void __launch_bounds__(TB_LANES) table_wide_kernel(TableArgs a) {
-    extern __shared__ __align__(16) unsigned char sm[];
-    __shared__ int bad;
-    const int n = a.n, rs = row_stride(n), r = blockIdx.x, job = blockIdx.y, t = threadIdx.x;
-    int32_t *out = a.table + (size_t)job * a.m;
-    int *perm = reinterpret_cast<int *>(sm), *pinv = perm + n;
-    uint8_t *gr = reinterpret_cast<uint8_t *>(pinv + n), *gtr = gr + n, *dr = gtr + n, *dtr = dr + n;
-    const int s = r + 1 + t;
-    if (!tb_stage_perm(a.perms + (size_t)job * n, n, perm, pinv, &bad)) {
-        if (s < n) out[pidx(n, r, s)] = 0;
-        return;
-    }
-    const uint8_t *F = a.mats, *FT = F + (size_t)n * rs, *D = F + (size_t)2 * n * rs, *DT = F + (size_t)3 * n * rs;
-    const int pr = perm[r];
-    for (int k = t; k < n; k += blockDim.x) {
-        const int pk = perm[k];
-        gr[k] = F[(size_t)pr * rs + pk];
-        gtr[k] = FT[(size_t)pr * rs + pk];
-        dr[k] = D[(size_t)r * rs + k];
-        dtr[k] = DT[(size_t)r * rs + k];
-    }
-    __syncthreads();
-    const int lane = t & 63, W = blockDim.x >> 6;
-    for (int sw = r + 1 + (t >> 6); sw < n; sw += W) {
-        const int ps = perm[sw];
-        const uint8_t *Fs = F + (size_t)ps * rs, *FTs = FT + (size_t)ps * rs, *Ds = D + (size_t)sw * rs,
-                      *DTs = DT + (size_t)sw * rs;
-        int acc = 0;
-        for (int k = lane; k < n; k += 64) {
-            const int pk = perm[k];
-            const int term = ((int)Fs[pk] - (int)gr[k]) * ((int)dr[k] - (int)Ds[k]) +
-                             ((int)FTs[pk] - (int)gtr[k]) * ((int)dtr[k] - (int)DTs[k]);
-            acc += (k == r || k == sw) ? 0 : term;
-        }
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (lane == 0)
-            out[pidx(n, r, sw)] = acc + ((int)Fs[ps] - (int)gr[r]) * ((int)dr[r] - (int)Ds[sw]) +
-                                  ((int)Fs[pr] - (int)gr[sw]) * ((int)dr[sw] - (int)Ds[r]);
-    }
-}
-
-// (I, J), I <= J, of tile pair q in row-major order over nt x nt tiles
+// (I, J), I <= J, of pair q in row-major order over nt x nt
 __device__ inline void tb_pair(int q, int nt, int &I, int &J) {
     I = 0;
     while (q >= nt - I) {
@@ -218,6 +170,199 @@ __device__ inline void tb_pair(int q, int nt, int &I, int &J) {
 }
 
 __device__ inline long long tb_load8(const uint8_t *p) { return *reinterpret_cast<const long long *>(p); }
+
+// ---- whole neighbourhood above WIDE_N: the same contraction, blocked
+//
+// X = G' and Y = D' no longer fit in LDS for a whole start, so a workgroup takes one pair
+// (BI <= BJ) of 128-row blocks of one start and streams k through LDS in chunks of
+// TW_KC: each chunk stages X and Y of both row blocks (X gathered from global F through
+// the permutation, Y read from global D, both shifted to int8), adds its part of the row
+// sums and diagonal terms of those rows, and accumulates the 32 x 32 output tiles of the
+// pair (two per wave) with v_mfma_i32_32x32x16_i8.  The epilogue is the one of the
+// single-block kernel, with the entries of D and G at (i, j), (j, i), (i, i), (j, j)
+// read from global memory.
+
+constexpr int TW_ROWS = 128;                 // rows of a block
+constexpr int TW_KC = 128;                   // k per chunk
+constexpr int TW_RS = TW_KC + 16;            // LDS row stride of a staged chunk
+constexpr int TW_TILES = TW_ROWS / 32;       // 32 x 32 tiles per block side
+
+struct TwPlan {
+    int perm, xi, yi, xj, yj, ui, uj, ti, tj, total;
+};
+
+__host__ __device__ inline TwPlan tw_plan(int n) {
+    TwPlan q;
+    int o = 0;
+    q.perm = o; o += ((n + 3) & ~3) * 4;
+    o = (o + 255) & ~255;
+    q.xi = o; o += TW_ROWS * TW_RS;
+    q.yi = o; o += TW_ROWS * TW_RS;
+    q.xj = o; o += TW_ROWS * TW_RS;
+    q.yj = o; o += TW_ROWS * TW_RS;
+    q.ui = o; o += TW_ROWS * 4;
+    q.uj = o; o += TW_ROWS * 4;
+    q.ti = o; o += TW_ROWS * 4;
+    q.tj = o; o += TW_ROWS * 4;
+    q.total = o;
+    return q;
+}
+
+__global__ void __launch_bounds__(TB_LANES) table_wide_mfma_kernel(TableArgs a) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    __shared__ int bad;
+    const int n = a.n, rs = row_stride(n), job = blockIdx.y, t = threadIdx.x, L = blockDim.x;
+    const int lane = t & 63, w = t >> 6;
+    const TwPlan P = tw_plan(n);
+    int32_t *out = a.table + (size_t)job * a.m;
+    int *perm = reinterpret_cast<int *>(sm + P.perm);
+    int *U_i = reinterpret_cast<int *>(sm + P.ui), *U_j = reinterpret_cast<int *>(sm + P.uj);
+    int *T_i = reinterpret_cast<int *>(sm + P.ti), *T_j = reinterpret_cast<int *>(sm + P.tj);
+    uint8_t *Xi = sm + P.xi, *Yi = sm + P.yi, *Xj = sm + P.xj, *Yj = sm + P.yj;
+    const int nb = (n + TW_ROWS - 1) / TW_ROWS;
+    int BI, BJ;
+    tb_pair(blockIdx.x, nb, BI, BJ);
+    const bool same = BI == BJ;
+    // check the start (its inverse in the X chunk buffer, which is free until staging)
+    {
+        int *pinv = reinterpret_cast<int *>(Xi);
+        if (t == 0) bad = 0;
+        for (int u = t; u < n; u += L) pinv[u] = -1;
+        __syncthreads();
+        const int32_t *p = a.perms + (size_t)job * n;
+        for (int u = t; u < n; u += L) {
+            const int v = p[u];
+            perm[u] = v;
+            if (v < 0 || v >= n || atomicExch(&pinv[v], u) != -1) bad = 1;
+        }
+        __syncthreads();
+        if (bad) {
+            // every block of the start clears its own entries
+            for (int x = t; x < TW_ROWS * TW_ROWS; x += L) {
+                const int i = BI * TW_ROWS + x / TW_ROWS, j = BJ * TW_ROWS + x % TW_ROWS;
+                if (i < j && j < n) out[pidx(n, i, j)] = 0;
+            }
+            return;
+        }
+    }
+    for (int x = t; x < TW_ROWS; x += L) U_i[x] = U_j[x] = T_i[x] = T_j[x] = 0;
+
+    // the wave's output tiles: (ti, tj) in the pair, ti <= tj when the blocks are the same
+    const int ntiles = same ? TW_TILES * (TW_TILES + 1) / 2 : TW_TILES * TW_TILES;
+    int tI[2], tJ[2];
+    bool has[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int id = w + 8 * q;
+        has[q] = id < ntiles;
+        if (same) {
+            tb_pair(has[q] ? id : 0, TW_TILES, tI[q], tJ[q]);
+        } else {
+            tI[q] = id / TW_TILES;
+            tJ[q] = id % TW_TILES;
+        }
+    }
+    v16i acc[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[q][r] = 0;
+
+    // per row of the two blocks (threads 0 .. 2 TW_ROWS - 1): sum x', sum y', sum x y
+    int sx = 0, sy = 0, dxy = 0, u_acc = 0, t_acc = 0;
+    const int phases = a.sym ? 1 : 2;
+    const int wpr = TW_KC / 4;   // words per staged row
+    for (int ph = 0; ph < phases; ++ph) {
+        const uint8_t *Fp = a.mats + (size_t)(ph ? 1 : 0) * n * rs;   // F, then F^T
+        const uint8_t *Dp = a.mats + (size_t)(ph ? 3 : 2) * n * rs;   // D, then D^T
+        sx = sy = dxy = 0;
+        for (int k0 = 0; k0 < n; k0 += TW_KC) {
+            __syncthreads();   // the previous chunk is consumed
+            const int sides = same ? 1 : 2;
+            for (int v = t; v < sides * TW_ROWS * wpr; v += L) {
+                const int side = v / (TW_ROWS * wpr), rem = v - side * TW_ROWS * wpr;
+                const int ri = rem / wpr, c = (rem - ri * wpr) * 4;
+                const int i = (side ? BJ : BI) * TW_ROWS + ri, k = k0 + c;
+                unsigned xw = 0, yw = 0;
+                if (i < n) {
+                    const uint8_t *frow = Fp + (size_t)perm[i] * rs, *drow = Dp + (size_t)i * rs;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (k + e < n) {
+                            xw |= (unsigned)(frow[perm[k + e]] ^ 0x80u) << (8 * e);
+                            yw |= (unsigned)(drow[k + e] ^ 0x80u) << (8 * e);
+                        }
+                }
+                reinterpret_cast<unsigned *>(side ? Xj : Xi)[(ri * TW_RS + c) / 4] = xw;
+                reinterpret_cast<unsigned *>(side ? Yj : Yi)[(ri * TW_RS + c) / 4] = yw;
+            }
+            __syncthreads();
+            // row sums and diagonal terms of this chunk
+            if (t < (same ? 1 : 2) * TW_ROWS) {
+                const int side = t / TW_ROWS, ri = t - side * TW_ROWS;
+                const int *xr = reinterpret_cast<const int *>((side ? Xj : Xi) + ri * TW_RS);
+                const int *yr = reinterpret_cast<const int *>((side ? Yj : Yi) + ri * TW_RS);
+                for (int c = 0; c < wpr; ++c) {
+                    sx = __builtin_amdgcn_sdot4(xr[c], 0x01010101, sx, false);
+                    sy = __builtin_amdgcn_sdot4(yr[c], 0x01010101, sy, false);
+                    dxy = __builtin_amdgcn_sdot4(xr[c], yr[c], dxy, false);
+                }
+            }
+            // S += X_I . Y_J^T + Y_I . X_J^T over this chunk
+            const int row = lane & 31, kh = 8 * (lane >> 5);
+            const uint8_t *XJ = same ? Xi : Xj, *YJ = same ? Yi : Yj;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                if (!has[q]) continue;
+                const uint8_t *xi = Xi + (tI[q] * 32 + row) * TW_RS + kh, *yj = YJ + (tJ[q] * 32 + row) * TW_RS + kh;
+                const uint8_t *yi = Yi + (tI[q] * 32 + row) * TW_RS + kh, *xj = XJ + (tJ[q] * 32 + row) * TW_RS + kh;
+#pragma unroll
+                for (int kk = 0; kk < TW_KC; kk += 16) {
+                    acc[q] = __builtin_amdgcn_mfma_i32_32x32x16_i8(tb_load8(xi + kk), tb_load8(yj + kk), acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_i32_32x32x16_i8(tb_load8(yi + kk), tb_load8(xj + kk), acc[q], 0, 0, 0);
+                }
+            }
+        }
+        // this phase's share of the row sums and diagonal terms
+        u_acc += sx + sy;
+        t_acc += dxy + 128 * (sx + sy) + 16384 * n;
+    }
+    if (t < (same ? 1 : 2) * TW_ROWS) {
+        const int side = t / TW_ROWS, ri = t - side * TW_ROWS;
+        (side ? U_j : U_i)[ri] = u_acc;
+        (side ? T_j : T_i)[ri] = t_acc;
+    }
+    __syncthreads();
+    const int *UJ = same ? U_i : U_j, *TJ = same ? T_i : T_j;
+
+    // ---- epilogue: delta(i, j) for i < j of the wave's tiles
+    const uint8_t *F = a.mats, *FT = F + (size_t)n * rs, *D = F + (size_t)2 * n * rs, *DT = F + (size_t)3 * n * rs;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (!has[q]) continue;
+        const int jl = tJ[q] * 32 + (lane & 31), j = BJ * TW_ROWS + jl;
+        if (j >= n) continue;
+        const int pj = perm[j];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int il = tI[q] * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), i = BI * TW_ROWS + il;
+            if (i < j) {
+                const int pi = perm[i];
+                const int s_ij = a.sym ? 2 * (acc[q][r] + 128 * (U_i[il] + UJ[jl]) + 32768 * n)
+                                       : acc[q][r] + 128 * (U_i[il] + UJ[jl]) + 65536 * n;
+                const int t_ii = a.sym ? 2 * T_i[il] : T_i[il], t_jj = a.sym ? 2 * TJ[jl] : TJ[jl];
+                const int Dij = D[(size_t)i * rs + j], Dji = DT[(size_t)i * rs + j];
+                const int Dii = D[(size_t)i * rs + i], Djj = D[(size_t)j * rs + j];
+                const int Gij = F[(size_t)pi * rs + pj], Gji = FT[(size_t)pi * rs + pj];
+                const int Gii = F[(size_t)pi * rs + pi], Gjj = F[(size_t)pj * rs + pj];
+                const int c = -(Dji - Dii) * (Gii - Gji) - (Djj - Dij) * (Gij - Gjj) - (Dij - Dii) * (Gii - Gij)
+                              - (Djj - Dji) * (Gji - Gjj) + (Dji - Dij) * (Gij - Gji) + (Djj - Dii) * (Gii - Gjj);
+                out[pidx(n, i, j)] = s_ij - t_ii - t_jj + c;
+            }
+        }
+    }
+}
+
 
 // The whole neighbourhood of one start, perm already in LDS (tb_plan layout at sm).
 __device__ __attribute__((always_inline)) void table_mfma_body(const uint8_t *mats, int n, int sym, unsigned char *sm, int32_t *out) {
@@ -418,13 +563,14 @@ hipError_t launch_cost(const TableArgs &a, hipStream_t st) {
 hipError_t launch_table(const TableArgs &a, hipStream_t st) {
     if (a.k == 0) return hipSuccess;
     if (a.n > WIDE_N) {   // starts in groups of at most 65535 (the grid's y extent)
+        const int nb = (a.n + TW_ROWS - 1) / TW_ROWS;
         for (int j0 = 0; j0 < a.k; j0 += 65535) {
             TableArgs b = a;
             b.perms += (size_t)j0 * a.n;
             b.table += (size_t)j0 * a.m;
             b.k = a.k - j0 < 65535 ? a.k - j0 : 65535;
-            hipLaunchKernelGGL(table_wide_kernel, dim3(a.n - 1, b.k), dim3(TB_LANES), (size_t)2 * a.n * 4 + 4 * a.n,
-                               st, b);
+            hipLaunchKernelGGL(table_wide_mfma_kernel, dim3(nb * (nb + 1) / 2, b.k), dim3(TB_LANES),
+                               (size_t)tw_plan(a.n).total, st, b);
             const hipError_t e = report(hipGetLastError(), "kernel launch");
             if (e != hipSuccess) return e;
         }

@@ -40,7 +40,7 @@ EXPORTS = [
     "qap_batch_tables_async", "qap_batch_search_async", "qap_batch_destroy", "qap_tabu_batch",
     "qap_tabu_batch_concat",
     "qap_tune_tile_rows", "qap_server_create", "qap_server_footprint", "qap_server_submit",
-    "qap_server_submit_matrices", "qap_server_set_queue_limit", "qap_server_step", "qap_server_start",
+    "qap_server_submit_matrices", "qap_server_submit_freq", "qap_server_poll_freq", "qap_server_set_queue_limit", "qap_server_step", "qap_server_start",
     "qap_server_stop", "qap_server_poll", "qap_server_result", "qap_server_cancel", "qap_server_inject_failure",
     "qap_server_stats", "qap_server_destroy",
 ]
@@ -104,6 +104,8 @@ def lib():
                 "qap_server_submit": (ctypes.c_int, [_vp, _vp, _i32p, i32, i32, i32, u64, _i64p]),
                 "qap_server_submit_matrices": (ctypes.c_int, [_vp, _i32p, _i32p, i32, _i32p, i32, i32, i32, u64,
                                                               _i64p]),
+                "qap_server_submit_freq": (ctypes.c_int, [_vp, _vp, _i32p, i32, i32, i32, u64, i32, i32, _i64p]),
+                "qap_server_poll_freq": (ctypes.c_int, [_vp, i64, _i32p, _i64p, _i32p]),
                 "qap_server_set_queue_limit": (ctypes.c_int, [_vp, i32]),
                 "qap_server_step": (ctypes.c_int, [_vp, _i32p, _i32p]),
                 "qap_server_start": (ctypes.c_int, [_vp]),
@@ -501,6 +503,33 @@ class Server:
                                        ctypes.byref(t)), "qap_server_submit")
         self._n[t.value] = h.n
         return t.value
+
+    def submit_freq(self, h: "Handle", start, iters: int, lo: int, hi: int, seed: int, div: int = 0,
+                    attr: int = 0) -> int:
+        """A request on handle h that keeps the frequency memory and may diversify or use a
+        unit attribute (qap_server_submit_freq); collect it with poll_freq."""
+        start = _arr(start, np.int32, (h.n,))
+        t = ctypes.c_int64(0)
+        _check(lib().qap_server_submit_freq(self._s, h.ptr, _ptr(start, _i32p), int(iters), int(lo), int(hi),
+                                            int(seed), int(div), int(attr), ctypes.byref(t)),
+               "qap_server_submit_freq")
+        self._n[t.value] = h.n
+        return t.value
+
+    def poll_freq(self, ticket: int):
+        """None while queued or running, else (best permutation, best cost, exchange counts)."""
+        n = self._n[ticket]
+        perm = np.zeros(n, dtype=np.int32)
+        freq = np.zeros(max(1, n * (n - 1) // 2), dtype=np.int32)
+        best = ctypes.c_int64(0)
+        rc = lib().qap_server_poll_freq(self._s, int(ticket), _ptr(perm, _i32p), ctypes.byref(best),
+                                        _ptr(freq, _i32p))
+        if rc == 0:
+            return None
+        if rc == 1 or rc == QAP_E_DEVICE:   # collected (or failed): the ticket is forgotten
+            del self._n[ticket]
+        _check(rc, "qap_server_poll_freq")
+        return perm, best.value, freq[:n * (n - 1) // 2]
 
     def set_queue_limit(self, max_queued: int):
         _check(lib().qap_server_set_queue_limit(self._s, int(max_queued)), "qap_server_set_queue_limit")

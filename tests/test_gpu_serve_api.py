@@ -247,3 +247,58 @@ def test_tabu_batch_per_instance_arrays():
     finally:
         for h in hs:
             h.close()
+
+
+def test_served_frequency_memory_equals_the_oracle():
+    """Requests that keep the frequency memory (qap_server_submit_freq), with and without
+    the diversification move and with each tabu attribute, served in small chunks beside
+    plain requests: every result and every count equals oracle.tabu_freq (plain ones
+    oracle.tabu), so the counts, unit marks, unit-location table and the iteration of the
+    last new best survive the chunk boundaries."""
+    rng = np.random.default_rng(771)
+    # (n, iters, div, attr, symmetric); the streamed form at n = 200
+    spec = [(40, 900, 0, 0, False), (64, 700, 25, 0, True), (97, 600, 30, 1, False), (33, 800, 0, 2, False),
+            (150, 400, 20, 2, False), (200, 250, 15, 1, True), (71, 500, 0, 1, False)]
+    reqs = []
+    for n, it, div, attr, sym in spec:
+        F, D = W.random_instance(rng, n, 0, 99, symmetric=sym)
+        lo, hi = (3, 3 + n // 10) if attr == 1 else W.paper_tenure_range(n)
+        reqs.append((F, D, W.starts(rng, n, 1)[0], it, lo, hi, int(rng.integers(0, 2**62)), div, attr))
+    plain = make_reqs(772, [50, 120], 300, 600)
+    note("served frequency memory: %d requests" % (len(reqs) + len(plain)))
+    hs = [qap.Handle(q[0], q[1]) for q in reqs]
+    out, outp = {}, {}
+    with qap.Server(1 << 28, 16, 0.2) as s:
+        tickets = [s.submit_freq(h, q[2], q[3], q[4], q[5], q[6], div=q[7], attr=q[8]) for h, q in zip(hs, reqs)]
+        ptick = [s.submit(*q) for q in plain]
+        with pytest.raises(qap.QapError) as ei:   # a plain request has no counts to give
+            while s.poll_freq(ptick[0]) is None:
+                s.step()
+        assert ei.value.code == qap.QAP_E_INVALID
+        for _ in range(200000):
+            if len(out) == len(tickets) and len(outp) == len(ptick):
+                break
+            s.step()
+            for t in tickets:
+                if t not in out:
+                    r = s.poll_freq(t)
+                    if r is not None:
+                        out[t] = r
+            for t in ptick:
+                if t not in outp:
+                    r = s.poll(t)
+                    if r is not None:
+                        outp[t] = r
+        assert s.stats()["steps"] > 3   # chunked
+    for t, q in zip(tickets, reqs):
+        F, D, p0, it, lo, hi, seed, div, attr = q
+        bp, bc, _, freq, _ = oracle.tabu_freq(F, D, p0, it, lo, hi, seed, start=0, div=div, attr=attr)
+        gp, gc, gf = out[t]
+        assert (gp == bp).all() and gc == bc, (q[3], div, attr)
+        assert (gf == freq).all(), (q[3], div, attr)
+    for t, q in zip(ptick, plain):
+        F, D, p0, it, lo, hi, seed = q
+        bp, bc, _, _ = oracle.tabu(F, D, p0, it, lo, hi, seed, 0)
+        assert (outp[t][0] == bp).all() and outp[t][1] == bc
+    for h in hs:
+        h.close()

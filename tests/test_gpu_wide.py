@@ -58,6 +58,28 @@ def test_wide_cost_and_neighbourhood_equal_the_oracle(n, sym):
         assert (t[j] == oracle.delta_table(F, D, perms[j])).all(), j
 
 
+def test_wide_table_row_that_is_no_permutation_is_zero():
+    """The blocked matrix-core table above n = 256: a start that is not a permutation gets
+    a zero row (every block of the start clears its own entries), the others are exact."""
+    import torch
+    n = 300
+    rng = np.random.default_rng(9150)
+    F, D = W.random_instance(rng, n, 0, 255, diag=True)
+    perms = W.starts(rng, n, 3)
+    bad = perms.copy()
+    bad[1, 5] = bad[1, 6]
+    note("wide table with a bad row n=300")
+    with qap.Handle(F, D) as h:
+        dp = torch.from_numpy(bad).cuda()
+        dt = torch.full((3, n * (n - 1) // 2), 7, dtype=torch.int32, device="cuda")
+        h.delta_table_async(dp, dt)
+        torch.cuda.synchronize()
+        t = dt.cpu().numpy()
+    assert (t[1] == 0).all()
+    for j in (0, 2):
+        assert (t[j] == oracle.delta_table(F, D, bad[j])).all(), j
+
+
 @pytest.mark.parametrize("n,sym,diag", [(257, False, False), (300, True, False), (384, False, True),
                                         (451, True, True), (512, False, False)])
 def test_wide_tabu_and_two_opt_equal_the_oracle(n, sym, diag):
