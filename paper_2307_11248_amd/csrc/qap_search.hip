@@ -1321,12 +1321,14 @@ __attribute__((amdgpu_waves_per_eu(!TABU && ROWS <= 8 ? 4 : 1))) search_kernel(S
 // The batched launch, one kernel per tile shape: block i runs items[i] as one tabu
 // search (items come sorted by decreasing work, and the hardware hands blocks to compute
 // units in index order as they free up, so the longest searches start first).  Tiles of
-// 2 and 4 rows ask for four waves per SIMD (at most 128 VGPRs), so two searches share a
-// compute unit and hide each other's latency; 8-row and streamed tiles need more
+// 2 and 4 rows ask for four waves per SIMD (at most 128 VGPRs, row dot products in
+// 16-byte steps), so two searches share a compute unit and hide each other's latency;
+// a 768-lane search (three waves per SIMD) then leaves a wave slot and its registers on
+// every SIMD for a small search of another variant.  8-row and streamed tiles need more
 // registers and run one search per compute unit.  (A persistent loop over a work queue
 // inside one block was tried: keeping its state live made the register tiles spill.)
 template <int ROWS, int LANES, int MAXT, bool STREAM, bool WIDE = false>
-__global__ void __launch_bounds__(LANES) __attribute__((amdgpu_waves_per_eu(LANES > 512 ? 3 : (ROWS <= 4 ? 4 : 2))))
+__global__ void __launch_bounds__(LANES) __attribute__((amdgpu_waves_per_eu(ROWS <= 4 ? 4 : 2)))
 batch_group_kernel(BatchArgs b) {
     extern __shared__ __align__(16) unsigned char sm[];
     Item it = b.items[blockIdx.x];
@@ -1343,7 +1345,7 @@ batch_group_kernel(BatchArgs b) {
         it.gmat = b.gwork + it.g_off;
         search_body<STREAM_ROWS, true, WIDE_MAXT, false, true, false, false, true>(it, sm);
     } else {
-        search_body<ROWS, true, MAXT, false, STREAM, ROWS <= 4 && LANES <= 512>(it, sm);
+        search_body<ROWS, true, MAXT, false, STREAM, ROWS <= 4>(it, sm);
     }
 }
 
