@@ -45,13 +45,14 @@ BYTES_PER_EVAL = 8   # an int32 delta read and written per entry per step if kep
 # valid only for the kernel sources they were taken with.
 KERNEL_SOURCES = ["paper_2307_11248_amd/csrc/qap_search.hip", "paper_2307_11248_amd/csrc/qap_internal.h"]
 TRAFFIC = {
-    "c2_n64_dense_tabu": {"bytes": 2 * 726 * 1024 + 40 * 1024, "sources": "53a1c7390546758b"},
+    "c2_n64_dense_tabu": {"bytes": int((2 * 717.0 + 40.0) * 1024), "sources": "357b0e44fc95e36c"},
+    "c3_n128_euclid_tabu": {"bytes": int((2 * 4406.0 + 144.0) * 1024), "sources": "357b0e44fc95e36c"},
     # sum over the six kernels of one launch (tiles of 2 rows on 128, 256 and 512 lanes, of
     # 4 rows on 256, 512 and 768)
-    "c4_batched_uneven_tabu": {"bytes": int((2 * (1062.9 + 9547.4 + 16606.0 + 2637.2 + 48965.1 + 43353.5)
-                                             + (50.0 + 247.7 + 265.4 + 79.7 + 600.4 + 408.0)) * 1024),
-                               "sources": "53a1c7390546758b"},
-    "n512_dense_tabu": {"bytes": int((2 * 457807363.4 + 299529572.0) * 1024), "sources": "53a1c7390546758b"},
+    "c4_batched_uneven_tabu": {"bytes": int((2 * (61287.0 + 43350.55 + 9552.75 + 4107.06 + 1972.125 + 1740.94)
+                                             + (805.765 + 408.297 + 247.6875 + 65.375 + 92.625 + 37.0625)) * 1024),
+                               "sources": "357b0e44fc95e36c"},
+    "n512_dense_tabu": {"bytes": int((2 * 458643000.0 + 299518000.0) * 1024), "sources": "357b0e44fc95e36c"},
 }
 
 

@@ -70,6 +70,19 @@ int dev_err_at(hipError_t e, const char *where) {
     return e == hipErrorOutOfMemory ? QAP_E_NOMEM : QAP_E_DEVICE;
 }
 
+// Side streams a batched launch forks into: one fewer than the hardware queues HIP gives
+// the process (GPU_MAX_HW_QUEUES, 4 unless set), so that each lane has a queue of its own
+// beside the caller's stream; QAP_BATCH_LANES overrides the count.
+static int side_lanes() {
+    auto env_int = [](const char *name, int dflt) {
+        const char *v = std::getenv(name);
+        return v && *v ? std::atoi(v) : dflt;
+    };
+    const int forced = env_int("QAP_BATCH_LANES", 0);
+    const int lanes = forced > 0 ? forced : env_int("GPU_MAX_HW_QUEUES", 4) - 1;
+    return std::max(1, std::min(lanes, (int)BV_COUNT));
+}
+
 bool check_perms(const int32_t *perms, int k, int n) {
     std::vector<int> seen(n);
     for (int j = 0; j < k; ++j) {
@@ -350,7 +363,9 @@ bool batch_fits(const qap_ctx *h, int ri) {
     if (ri < kBatchFirst || ri > kBatchFirst + 2) return false;
     const TileSet &ts = h->tiles[ri];
     const int rows = kRowsChoices[ri];
-    const int lanes = batch_variant_lanes(batch_variant(h->n, rows, false, ts.ntiles, h->sym));
+    const int var = batch_variant(h->n, rows, false, ts.ntiles, h->sym);
+    if (var < 0) return false;   // no batched kernel for this shape
+    const int lanes = batch_variant_lanes(var);
     return ts.d_tiles && batch_shape_ok_wide(h->n, rows, ts.ntiles, h->sym) &&
            search_smem_bytes(h->n, rows, lanes, h->sym) <= h->max_smem;
 }
@@ -410,13 +425,17 @@ struct qap_batch {
     // (offsets into the run's starts and the plan's tables); the matrix-core table kernel
     // takes every other item
     std::vector<WideTable> wide_tables;
-    // items are grouped by kernel variant (tile shape); one launch per non-empty group,
-    // the groups forked onto side streams so that they share the device
+    // items are grouped by kernel variant (tile shape); one launch per non-empty group
     int group_begin[BV_COUNT] = {}, group_count[BV_COUNT] = {};
-    // launch order of the groups: the one whose longest search is the longest first (the
-    // hardware hands out compute units roughly in launch order)
-    int group_order[BV_COUNT] = {};
     size_t group_smem[BV_COUNT] = {};
+    // The groups run on `nlanes` side streams forked from the caller's stream, the groups
+    // of one lane back to back: lane_groups[lane_begin[l] .. lane_begin[l + 1]).  Streams
+    // beyond the device's hardware queues would share queues, and kernels on one queue
+    // run in order, so there are at most as many lanes as free queues; the groups are
+    // dealt to them by estimated work, largest first, each to the least loaded lane.
+    int nlanes = 0;
+    int lane_begin[BV_COUNT + 1] = {};
+    int lane_groups[BV_COUNT] = {};
     hipStream_t side[BV_COUNT] = {};
     hipEvent_t ev_fork = nullptr, ev_join[BV_COUNT] = {};
     // plans made by qap_batch_create_freq: every search keeps its frequency memory (and may
@@ -965,26 +984,48 @@ int batch_create_impl(const qap_handle *hs, int32_t m, const int32_t *k_per, int
     b->wide_tables = wide_tables;
     for (int i = (int)items.size() - 1; i >= 0; --i) {
         const int v = item_variant(items[i]);
+        if (v < 0) continue;   // (not reached: batch_fits and batch_freq_fits turn such shapes away)
         b->group_begin[v] = i;
         ++b->group_count[v];
     }
     int ngroups = 0;
+    long long work[BV_COUNT] = {};   // a group's work estimate: the sum of n^2 over its searches
+    int order[BV_COUNT];
     for (int v = 0; v < BV_COUNT; ++v) {
         b->group_smem[v] = gsmem[v];
         ngroups += b->group_count[v] > 0;
-        b->group_order[v] = v;
+        for (int i = 0; i < b->group_count[v]; ++i) {
+            const long long nn = items[b->group_begin[v] + i].n;
+            work[v] += nn * nn;
+        }
+        order[v] = v;
     }
-    auto longest = [&](int v) {   // n^2 of the group's first (longest) item
-        return b->group_count[v] ? (long long)items[b->group_begin[v]].n * items[b->group_begin[v]].n : -1LL;
-    };
-    std::stable_sort(b->group_order, b->group_order + BV_COUNT, [&](int x, int y) { return longest(x) > longest(y); });
+    std::stable_sort(order, order + BV_COUNT, [&](int x, int y) { return work[x] > work[y]; });
+    if (!freq && ngroups > 0) {
+        b->nlanes = std::min(ngroups, side_lanes());
+        long long load[BV_COUNT] = {};
+        int lane_of[BV_COUNT], per_lane[BV_COUNT] = {};
+        for (int g = 0; g < ngroups; ++g) {   // largest first, each to the least loaded lane
+            int l = 0;
+            for (int x = 1; x < b->nlanes; ++x)
+                if (load[x] < load[l]) l = x;
+            lane_of[order[g]] = l;
+            load[l] += work[order[g]];
+            ++per_lane[l];
+        }
+        for (int l = 0; l < b->nlanes; ++l) b->lane_begin[l + 1] = b->lane_begin[l] + per_lane[l];
+        int fill[BV_COUNT] = {};
+        for (int g = 0; g < ngroups; ++g) {   // inside a lane, in the same order
+            const int l = lane_of[order[g]];
+            b->lane_groups[b->lane_begin[l] + fill[l]++] = order[g];
+        }
+    }
     hipError_t e = hipSuccess;
-    if (ngroups > 1 && !freq) {
+    if (b->nlanes > 1) {
         e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
-        for (int v = 0; v < BV_COUNT && e == hipSuccess; ++v) {
-            if (!b->group_count[v]) continue;
-            e = hipStreamCreateWithFlags(&b->side[v], hipStreamNonBlocking);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[v], hipEventDisableTiming);
+        for (int l = 0; l < b->nlanes && e == hipSuccess; ++l) {
+            e = hipStreamCreateWithFlags(&b->side[l], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[l], hipEventDisableTiming);
         }
     }
     if (b->count > 0) {
@@ -1087,24 +1128,22 @@ extern "C" int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int6
         BatchArgs a{b->d_items, b->count, d_perms, d_best, d_done, b->d_table, b->d_tile_work, b->d_gwork};
         return dev_err(launch_batch_freq(a, b->freq_smem, st));
     }
-    int ngroups = 0;
-    for (int v = 0; v < BV_COUNT; ++v) ngroups += b->group_count[v] > 0;
-    hipError_t e = hipSuccess;
-    if (ngroups > 1) e = hipEventRecord(b->ev_fork, st);
-    for (int g = 0; g < BV_COUNT && e == hipSuccess; ++g) {
-        const int v = b->group_order[g];
-        if (!b->group_count[v]) continue;
-        BatchArgs a{b->d_items + b->group_begin[v], b->group_count[v], d_perms, d_best, d_done, b->d_table,
-                    b->d_tile_work, b->d_gwork};
-        if (ngroups == 1) {
-            e = launch_batch_group(v, a, b->group_smem[v], st);
-            continue;
+    const bool fork = b->nlanes > 1;
+    hipError_t e = fork ? hipEventRecord(b->ev_fork, st) : hipSuccess;
+    for (int l = 0; l < b->nlanes && e == hipSuccess; ++l) {
+        hipStream_t ls = fork ? b->side[l] : st;
+        if (fork) e = hipStreamWaitEvent(ls, b->ev_fork, 0);
+        for (int g = b->lane_begin[l]; g < b->lane_begin[l + 1] && e == hipSuccess; ++g) {
+            const int v = b->lane_groups[g];
+            BatchArgs a{b->d_items + b->group_begin[v], b->group_count[v], d_perms, d_best, d_done, b->d_table,
+                        b->d_tile_work, b->d_gwork};
+            e = launch_batch_group(v, a, b->group_smem[v], ls);
         }
-        e = hipStreamWaitEvent(b->side[v], b->ev_fork, 0);
-        if (e == hipSuccess) e = launch_batch_group(v, a, b->group_smem[v], b->side[v]);
-        if (e == hipSuccess) e = hipEventRecord(b->ev_join[v], b->side[v]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join[v], 0);
+        if (fork && e == hipSuccess) e = hipEventRecord(b->ev_join[l], ls);
     }
+    // the joins after every lane's launches, so that no wait of the caller's stream sits
+    // in a hardware queue ahead of a lane's kernels
+    for (int l = 0; fork && l < b->nlanes && e == hipSuccess; ++l) e = hipStreamWaitEvent(st, b->ev_join[l], 0);
     return dev_err(e);
 }
 

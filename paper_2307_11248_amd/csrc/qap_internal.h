@@ -247,7 +247,7 @@ enum { BV_R2 = 0, BV_R4, BV_R8, BV_STREAM, BV_R2_128, BV_R2_256, BV_R4_256, BV_R
 // 4 rows on the 768-lane variant).
 int batch_shape_ok_wide(int n, int rows, int ntiles, int sym);
 // Variant of a batched search: rows 2, 4, 8 or the streamed form (the wide one above
-// WIDE_N), ntiles tiles.
+// WIDE_N), ntiles tiles; -1 for a shape no batched kernel serves.
 int batch_variant(int n, int rows, bool streamed, int ntiles, int sym);
 // Lanes of a workgroup of that variant.
 int batch_variant_lanes(int variant);

@@ -228,6 +228,33 @@ __device__ inline void dot_rows2_t(const uint8_t *a, const uint8_t *b1, const ui
     o2 = c2;
 }
 
+// dot_rows2_t for rows of at most MAXB bytes, unrolled over every step: the byte offsets
+// are constants, so each load carries its offset in the instruction instead of an address
+// add per load; the step count still follows rs (the exits are uniform branches).
+template <int N, int MAXB>
+__device__ inline void dot_rows2_u(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
+                                   unsigned &o2) {
+    constexpr int S = 16 * N;
+    static_assert(MAXB % (2 * S) == 0, "whole pairs of steps");
+    // an opaque copy of the (uniform) length: the step tests are scalar compares made
+    // here, not masks hoisted out of the caller's loop and held in registers throughout
+    asm volatile("" : "+s"(rs));
+    unsigned c1 = 0, c2 = 0;
+    RowStep<N> p, q;
+    load_step<N>(p, a, b1, b2, 0);
+#pragma unroll
+    for (int w = S; w < MAXB; w += 2 * S) {
+        if (w < rs) load_step<N>(q, a, b1, b2, w);
+        dot_step<N>(p, c1, c2);
+        if (w >= rs) break;
+        if (w + S < rs) load_step<N>(p, a, b1, b2, w + S);
+        dot_step<N>(q, c1, c2);
+        if (w + S >= rs) break;
+    }
+    o1 = c1;
+    o2 = c2;
+}
+
 // 32 bytes a step (rs a multiple of 32)
 __device__ inline void dot_rows2(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
                                  unsigned &o2) {
@@ -306,6 +333,15 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     const int lane = t & 63, wid = t >> 6, W = L >> 6;
     constexpr int sym = SYM ? 1 : 0;   // F and D both symmetric (the caller checked a.sym)
     constexpr int nq = SYM ? 2 : 4, lq = SYM ? 1 : 2;
+    // bits of a slot's index inside its tile
+    constexpr int KSB = ROWS == 1 ? 2 : (ROWS == 2 ? 3 : (ROWS == 4 ? 4 : 5));
+    // Tabu register tiles of up to 4 rows hold each slot as its selection key,
+    // delta * 2^KSB + slot (|delta| < 2^26, so keys stay below 2^30 in magnitude): the
+    // update scales its (A, C) factors by 2^KSB, and the select needs no shift per slot.
+    constexpr bool PS = TABU && !STREAM && ROWS <= 4;
+    // the value of a slot that is not a move (diagonal, padding): above every key, and
+    // (PS) with room below INT32_MAX for the updates it takes before it is reset
+    constexpr int NOMOVE = PS ? (1 << 30) : BIG;
     const int np = padded_n(n, ROWS);
     const Smem S = smem_plan(n, np, L, sym, STREAM, GGLOB);
     SearchState *const st = RESUME ? a.st : nullptr;   // saved state, chunked runs only
@@ -455,10 +491,10 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 if (!STREAM && RESUME && resume) {
                     // (delta, tabu until) of the slot, saved by the previous chunk
                     const int2 du = real ? a.st_du[ix] : make_int2(BIG, INT32_MAX);
-                    d[j][e] = du.x;
+                    d[j][e] = !real ? NOMOVE : (PS ? du.x * (1 << KSB) + (j * 4 + e) : du.x);
                     if (TABU) u_[j][e] = du.y;
                 } else {
-                    d[j][e] = real ? a.table[ix] : BIG;
+                    d[j][e] = !real ? NOMOVE : (PS ? a.table[ix] * (1 << KSB) + (j * 4 + e) : a.table[ix]);
                     if (TABU) u_[j][e] = real ? 0 : INT32_MAX;
                 }
             }
@@ -474,8 +510,33 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     auto tile_min = [&](const int (&d)[ROWS][4], const int (&u_)[UTR][4], int tu0, int tv0, int itx,
                         int thr) -> long long {
         int bd = INT32_MAX, bs = -1;
-        if constexpr (ROWS <= 8) {
-            constexpr int SB = ROWS == 1 ? 2 : (ROWS == 2 ? 3 : (ROWS == 4 ? 4 : 5));
+        if constexpr (PS) {
+            // Slot values are keys already (thr scaled the same way).  The admissible slots
+            // are the non-tabu ones plus every slot below thr, so their lowest key is the
+            // lower of the lowest non-tabu key and, when it is below thr, the lowest key of
+            // all: one compare and select per slot, no mask arithmetic.
+            int knt[ROWS * 4], kal[ROWS * 4];
+#pragma unroll
+            for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    kal[j * 4 + e] = d[j][e];
+                    knt[j * 4 + e] = u_[j][e] <= itx ? d[j][e] : INT32_MAX;
+                }
+#pragma unroll
+            for (int w2 = ROWS * 2; w2 >= 1; w2 >>= 1)
+#pragma unroll
+                for (int q = 0; q < w2; ++q) {
+                    knt[q] = min(knt[q], knt[q + w2]);
+                    kal[q] = min(kal[q], kal[q + w2]);
+                }
+            const int best = kal[0] < thr ? min(knt[0], kal[0]) : knt[0];
+            if (best != INT32_MAX) {
+                bd = best >> KSB;
+                bs = best & ((1 << KSB) - 1);
+            }
+        } else if constexpr (ROWS <= 8) {
+            constexpr int SB = KSB;
             constexpr int LIM = (1 << 26) - 1;
             int best = INT32_MAX;
             if constexpr (ROWS <= 2 && MAXT == 1) {
@@ -533,6 +594,12 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         if (!TABU) return 0;
         const long long d = best - cur;  // aspiration: cur + delta < best
         return d < (long long)INT32_MIN ? INT32_MIN : (int)d;
+    };
+    // the aspiration threshold on key-valued slots: delta < thr exactly when
+    // delta * 2^KSB + slot < thr * 2^KSB; below -2^26 no delta reaches it
+    auto aspiration_key = [&]() -> int {
+        const int th = aspiration();
+        return th < -(1 << 26) ? INT32_MIN : th * (1 << KSB);
     };
     const int npass = STREAM ? (a.ntiles + L - 1) / L : 1;
     auto tile_of = [&](int tix, int &g, int &b) {
@@ -604,7 +671,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             s_chunk_end = (long long)wall_clock64() >= clock_end;
         // ---- select: lowest (delta, key) over the admissible slots (streamed kernels
         //      found their lane's candidate while updating the tiles)
-        if (!STREAM) sel = active ? tile_min(dl, ut, u0, v0, it, aspiration()) : NO_MOVE;
+        if (!STREAM) sel = active ? tile_min(dl, ut, u0, v0, it, PS ? aspiration_key() : aspiration()) : NO_MOVE;
         const long long kw = wave_min_pair<64>((int)(sel >> 32), (int)(sel & 0xffffffffLL));
         if (lane == 0) red[wid] = kw;
         __syncthreads();  // B1
@@ -692,7 +759,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
 #pragma unroll
                             for (int e = 0; e < 4; ++e)
                                 if (u0 + j == ud && v0 + e == vd) x = dl[j][e];
-                        s_dd = x;
+                        s_dd = PS ? x >> KSB : x;   // (a key: the delta is its upper bits)
                     }
                     __syncthreads();  // the delta is visible
                     dstar = __builtin_amdgcn_readfirstlane(s_dd);
@@ -779,12 +846,16 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             unsigned d1, d2;
             // rows of 64 bytes in one step where the registers allow it (one LDS latency)
             constexpr bool ONE_SHOT = MAXT == 1 && !FREQ && (!NARROW || ROWS <= 2);
+            // (rows of n <= WIDE_N bytes: every step unrolled, offsets in the instructions;
+            // the kernels with the frequency memory keep the loop, their registers are full)
             if (ONE_SHOT && nb32 == 64) {
                 dot_rows2_64(shared, side1, side2, d1, d2);
             } else if constexpr (NARROW) {
-                dot_rows2_16(shared, side1, side2, nb16, d1, d2);
+                dot_rows2_u<1, WIDE_N>(shared, side1, side2, nb16, d1, d2);
             } else if constexpr (!TABU) {
                 dot_rows2_carry(shared, side1, side2, nb32, d1, d2);
+            } else if constexpr (!GGLOB && !FREQ) {
+                dot_rows2_u<2, WIDE_N>(shared, side1, side2, nb32, d1, d2);
             } else {
                 dot_rows2(shared, side1, side2, nb32, d1, d2);
             }
@@ -851,16 +922,21 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             }
             rdv[i] = rdn;
             cdv[i] = cdn;
-            if (q == 0) reinterpret_cast<int2 *>(acbe)[u] = make_int2(pack16(A, C), pack16(B, E));
+            // (key-valued tiles: A and C scaled by 2^KSB, |A|, |C| <= 255, so every
+            // difference of two still fits 16 bits)
+            if (q == 0)
+                reinterpret_cast<int2 *>(acbe)[u] =
+                    make_int2(PS ? pack16(A * (1 << KSB), C * (1 << KSB)) : pack16(A, C), pack16(B, E));
             if (u == r || u == s) {
                 // K_b = RD'_b + CD'_b; every recomputed entry is stored as delta' + K_b, so
-                // the tiles subtract K_b alone: here delta'(b, b) = BIG (a diagonal slot)
+                // the tiles subtract K_b alone: here delta'(b, b) = BIG (a diagonal slot;
+                // 2^26 for key-valued tiles, whose key 2^30 + slot stays in range)
                 // and delta'(r, s) = -dstar (the move undone)
                 const int kb = rdn + cdn;
                 int *rb = u == r ? rpr : rps;
                 if (q == 0) {
                     kc[u == r ? 0 : 1] = kb;
-                    rb[u] = BIG + kb;
+                    rb[u] = (PS ? (1 << 26) : BIG) + kb;
                 } else if (q == 1) {
                     rb[u == r ? s : r] = kb - dstar;
                 }
@@ -1011,16 +1087,20 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             // are written by register-indexed moves, tiles of 16 rows take a scalar branch
             // per row
             const int jr = r % ROWS, js = s % ROWS, er = r & 3, es = s & 3;
+            // the value a recomputed delta takes in slot (j, e) (key-valued tiles: its key)
+            auto slot_val = [&](int v, int j, int e) { return PS ? v * (1 << KSB) + (j * 4 + e) : v; };
             if constexpr (ROWS <= 2) {
                 if (g == r / ROWS) {
-                    const int vr[4] = {rv.x - kr, rv.y - kr, rv.z - kr, rv.w - kr};
+                    const int vr[4] = {slot_val(rv.x - kr, jr, 0), slot_val(rv.y - kr, jr, 1),
+                                       slot_val(rv.z - kr, jr, 2), slot_val(rv.w - kr, jr, 3)};
 #pragma unroll
                     for (int j = 0; j < ROWS; ++j)
 #pragma unroll
                         for (int e = 0; e < 4; ++e) dl[j][e] = j == jr ? vr[e] : dl[j][e];
                 }
                 if (g == s / ROWS) {
-                    const int vs[4] = {sv.x - ks, sv.y - ks, sv.z - ks, sv.w - ks};
+                    const int vs[4] = {slot_val(sv.x - ks, js, 0), slot_val(sv.y - ks, js, 1),
+                                       slot_val(sv.z - ks, js, 2), slot_val(sv.w - ks, js, 3)};
 #pragma unroll
                     for (int j = 0; j < ROWS; ++j)
 #pragma unroll
@@ -1030,13 +1110,13 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
 #pragma unroll
                     for (int j = 0; j < ROWS; ++j)
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) dl[j][e] = e == er ? rpru[j] - kr : dl[j][e];
+                        for (int e = 0; e < 4; ++e) dl[j][e] = e == er ? slot_val(rpru[j] - kr, j, er) : dl[j][e];
                 }
                 if (b == (s >> 2)) {
 #pragma unroll
                     for (int j = 0; j < ROWS; ++j)
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) dl[j][e] = e == es ? rpsu[j] - ks : dl[j][e];
+                        for (int e = 0; e < 4; ++e) dl[j][e] = e == es ? slot_val(rpsu[j] - ks, j, es) : dl[j][e];
                 }
             } else if constexpr (ROWS <= 8) {
                 typedef int tilevec __attribute__((ext_vector_type(ROWS * 4)));
@@ -1046,24 +1126,24 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
 #pragma unroll
                     for (int e = 0; e < 4; ++e) tv[j * 4 + e] = dl[j][e];
                 if (g == r / ROWS) {
-                    tv[jr * 4 + 0] = rv.x - kr;
-                    tv[jr * 4 + 1] = rv.y - kr;
-                    tv[jr * 4 + 2] = rv.z - kr;
-                    tv[jr * 4 + 3] = rv.w - kr;
+                    tv[jr * 4 + 0] = slot_val(rv.x - kr, jr, 0);
+                    tv[jr * 4 + 1] = slot_val(rv.y - kr, jr, 1);
+                    tv[jr * 4 + 2] = slot_val(rv.z - kr, jr, 2);
+                    tv[jr * 4 + 3] = slot_val(rv.w - kr, jr, 3);
                 }
                 if (g == s / ROWS) {
-                    tv[js * 4 + 0] = sv.x - ks;
-                    tv[js * 4 + 1] = sv.y - ks;
-                    tv[js * 4 + 2] = sv.z - ks;
-                    tv[js * 4 + 3] = sv.w - ks;
+                    tv[js * 4 + 0] = slot_val(sv.x - ks, js, 0);
+                    tv[js * 4 + 1] = slot_val(sv.y - ks, js, 1);
+                    tv[js * 4 + 2] = slot_val(sv.z - ks, js, 2);
+                    tv[js * 4 + 3] = slot_val(sv.w - ks, js, 3);
                 }
                 if (b == (r >> 2)) {
 #pragma unroll
-                    for (int j = 0; j < ROWS; ++j) tv[j * 4 + er] = rpru[j] - kr;
+                    for (int j = 0; j < ROWS; ++j) tv[j * 4 + er] = slot_val(rpru[j] - kr, j, er);
                 }
                 if (b == (s >> 2)) {
 #pragma unroll
-                    for (int j = 0; j < ROWS; ++j) tv[j * 4 + es] = rpsu[j] - ks;
+                    for (int j = 0; j < ROWS; ++j) tv[j * 4 + es] = slot_val(rpsu[j] - ks, j, es);
                 }
 #pragma unroll
                 for (int j = 0; j < ROWS; ++j)
@@ -1185,7 +1265,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 for (int j = 0; j < ROWS; ++j)
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        if (pu + j >= n || pv + e >= n) dl[j][e] = BIG;
+                        if (pu + j >= n || pv + e >= n) dl[j][e] = NOMOVE;
             }
             return tabu_set;
         };
@@ -1243,7 +1323,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 const int u = su0 + j, v = sv0 + e;
                 if (active && u < v && v < n) {
                     const long long ix = pidx(n, u, v);
-                    a.st_du[ix] = make_int2(dl[j][e], TABU ? ut[j][e] : 0);
+                    a.st_du[ix] = make_int2(PS ? dl[j][e] >> KSB : dl[j][e], TABU ? ut[j][e] : 0);
                 }
             }
         for (int u = t; u < n; u += L) {
@@ -1515,9 +1595,11 @@ int search_lanes(int n, int rows, int ntiles, int sym) {
 int batch_variant(int n, int rows, bool streamed, int ntiles, int sym) {
     if (streamed) return n > WIDE_N ? BV_WIDE : BV_STREAM;
     // lanes a one-task workgroup needs: one per tile and one per (index, family) task
+    // (the 512-lane kernels of 2 and 4 rows carry one task a lane: at most 512 tiles of
+    // those shapes means n below 128, 4 n < 512 tasks; the checks keep it so)
     const int need = ntiles > families(sym) * n ? ntiles : families(sym) * n;
-    if (rows == 2) return need <= 128 ? BV_R2_128 : (need <= 256 ? BV_R2_256 : BV_R2);
-    if (rows == 4) return need <= 256 ? BV_R4_256 : (ntiles <= BATCH_LANES ? BV_R4 : BV_R4_768);
+    if (rows == 2) return need <= 128 ? BV_R2_128 : (need <= 256 ? BV_R2_256 : (need <= BATCH_LANES ? BV_R2 : -1));
+    if (rows == 4) return need <= 256 ? BV_R4_256 : (need <= BATCH_LANES ? BV_R4 : BV_R4_768);
     return BV_R8;
 }
 
@@ -1538,8 +1620,8 @@ hipError_t launch_batch_group(int variant, const BatchArgs &b, size_t smem, hipS
     if (b.count <= 0) return hipSuccess;
     constexpr int L = BATCH_LANES, T = 1024 / BATCH_LANES;
     switch (variant) {
-        case BV_R2: hipLaunchKernelGGL((batch_group_kernel<2, L, T, false>), dim3(b.count), dim3(L), smem, st, b); break;
-        case BV_R4: hipLaunchKernelGGL((batch_group_kernel<4, L, T, false>), dim3(b.count), dim3(L), smem, st, b); break;
+        case BV_R2: hipLaunchKernelGGL((batch_group_kernel<2, L, 1, false>), dim3(b.count), dim3(L), smem, st, b); break;
+        case BV_R4: hipLaunchKernelGGL((batch_group_kernel<4, L, 1, false>), dim3(b.count), dim3(L), smem, st, b); break;
         case BV_R8: hipLaunchKernelGGL((batch_group_kernel<8, L, T, false>), dim3(b.count), dim3(L), smem, st, b); break;
         case BV_R2_128:
             hipLaunchKernelGGL((batch_group_kernel<2, 128, 1, false>), dim3(b.count), dim3(128), smem, st, b);
