@@ -43,13 +43,21 @@ __host__ __device__ inline long long pidx(int n, int r, int s) {
     return (long long)r * n - (long long)r * (r + 1) / 2 + (s - r - 1);
 }
 
+// Lanes a search workgroup needs: one per register tile, and at least one per (index,
+// dot family) task when that fits, so the row recomputation runs in one pass.
+__host__ __device__ inline int families(int sym) { return sym ? 2 : 4; }
+
 // Byte offsets of the per-search shared-memory arrays of the search kernels.  The
 // matrices are u8 rows of RS bytes: D, D^T, and G = F[p][p] (the flows seen from the
 // locations under the current permutation p), G^T; only D and G when F and D are
 // both symmetric.
 struct Smem {
-    int d, dt, g, gt, acbe, rpr, rps, kc, perm, bestp, pinv, ten, red, total;
+    int d, dt, g, gt, acbe, rpr, rps, kc, perm, bestp, pinv, ten, red, tb, ring, xd, total;
 };
+
+// Compact tabu state of the wide streamed kernel: moves of the last TABU_RING iterations
+// (one int each: key u << 9 | v, tenure << 18), so tenures up to TABU_RING - 1.
+constexpr int TABU_RING = 1024;
 
 // dglobal: D and D^T are read from global memory (the streamed kernels), not staged;
 // gglobal: so are G and G^T (the wide streamed kernel, n above WIDE_N).
@@ -84,13 +92,19 @@ __host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym, boo
     s.pinv = take(np * 4);
     s.ten = take(lanes * 4);
     s.red = take(16 * 8);
+    // (gglobal) compact tabu state: a bit per slot, one word per 8 x 4 tile position of
+    // the padded grid, and the ring of recent moves
+    s.tb = s.ring = s.xd = -1;
+    if (gglobal) {
+        s.tb = take((np / 8) * (np / TILE_COLS) * 4);
+        s.ring = take(TABU_RING * 4);
+        // the two row dot products of every (index, family) task, made by whole waves
+        s.xd = take(families(sym) * np * 8);
+    }
     s.total = o;
     return s;
 }
 
-// Lanes a search workgroup needs: one per register tile, and at least one per (index,
-// dot family) task when that fits, so the row recomputation runs in one pass.
-__host__ __device__ inline int families(int sym) { return sym ? 2 : 4; }
 
 // Arguments of the cost and neighbourhood-table kernels.
 struct TableArgs {

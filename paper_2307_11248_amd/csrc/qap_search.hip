@@ -319,8 +319,12 @@ __device__ inline void dot_rows2_64(const uint8_t *a, const uint8_t *b1, const u
 // (for kernels held to 128 VGPRs, where the wider steps spill).  FREQ: tabu keeps the
 // frequency memory in a.freq (compiled only into the kernels that need it).
 template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool SYM, bool NARROW, bool FREQ = false,
-          bool GGLOB = false>
+          bool GGLOB = false, bool CTB = false>
 __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsigned char *sm) {
+    // CTB: compact tabu state (wide streamed tabu searches without the frequency memory,
+    // run whole): a bit per slot in LDS and a ring of recent moves instead of an
+    // "until" word per slot streamed with the deltas
+    static_assert(!CTB || (TABU && STREAM && GGLOB && !FREQ && !RESUME && ROWS == 8), "compact tabu state");
     __shared__ int s_bad;
     __shared__ int s_chunk_end;   // chunked runs: set by thread 0 once the clock budget is spent
     __shared__ long long s_red2[FREQ ? 16 : 1];   // diversification: wave minima of (count, key)
@@ -368,6 +372,18 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     int *pinv = reinterpret_cast<int *>(sm + S.pinv);
     int *ten = reinterpret_cast<int *>(sm + S.ten);
     long long *red = reinterpret_cast<long long *>(sm + S.red);
+    // compact tabu state: tbits[g * nbw + b] holds the tabu bits of the 8 x 4 slots at
+    // tile position (g, b), bit (u % 8) * 4 + v % 4; ring[i % TABU_RING] the move of
+    // iteration i; untl[pidx(u, v)] (the tile scratch the until words would take) the
+    // iteration until which the latest move of the pair is tabu
+    unsigned *tbits = CTB ? reinterpret_cast<unsigned *>(sm + S.tb) : nullptr;
+    int *ring = CTB ? reinterpret_cast<int *>(sm + S.ring) : nullptr;
+    int *untl = CTB ? reinterpret_cast<int *>(a.tile_u) : nullptr;
+    const int nbw = np / TILE_COLS;
+    auto tbit_word = [&](int u, int v) -> unsigned * { return tbits + (u >> 3) * nbw + (v >> 2); };
+    auto tbit = [&](int u, int v) -> unsigned { return 1u << (((u & 7) << 2) | (v & 3)); };
+    // (wide kernel) the two row dot products of task (u, family q) at xd[q * np + u]
+    int2 *xd = GGLOB ? reinterpret_cast<int2 *>(sm + S.xd) : nullptr;
 
     // ---- stage D, D^T; read and check the start
     if (!STREAM) {
@@ -601,6 +617,26 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         const int th = aspiration();
         return th < -(1 << 26) ? INT32_MIN : th * (1 << KSB);
     };
+    // tile_min for the compact tabu state: bit j * 4 + e of tw set = slot (j, e) tabu
+    auto tile_min_bits = [&](const int (&d)[ROWS][4], unsigned tw, int tu0, int tv0, int thr) -> long long {
+        constexpr int LIM = (1 << 26) - 1;
+        int best = INT32_MAX;
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = d[j][e];
+                const bool adm = ((tw >> (j * 4 + e)) & 1u) == 0 || x < thr;
+                best = min(best, (adm ? x : LIM) * (1 << KSB) + (j * 4 + e));
+            }
+        int bd = best >> KSB, bs = best & ((1 << KSB) - 1);
+        if (bd == LIM) {
+            bd = INT32_MAX;
+            bs = -1;
+        }
+        const int key = bs < 0 ? KEY_NONE : (((tu0 + (bs >> 2)) << 9) | (tv0 + (bs & 3)));
+        return ((long long)bd << 32) | (unsigned)key;
+    };
     const int npass = STREAM ? (a.ntiles + L - 1) / L : 1;
     auto tile_of = [&](int tix, int &g, int &b) {
         const int tv = a.tiles[tix];
@@ -643,8 +679,23 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
 #pragma unroll
                 for (int j = 0; j < ROWS; ++j) {
                     a.tile_d[tile_addr(q, j)] = make_int4(d[j][0], d[j][1], d[j][2], d[j][3]);
-                    if (TABU) a.tile_u[tile_addr(q, j)] = make_int4(u_[j][0], u_[j][1], u_[j][2], u_[j][3]);
+                    if (TABU && !CTB) a.tile_u[tile_addr(q, j)] = make_int4(u_[j][0], u_[j][1], u_[j][2], u_[j][3]);
                 }
+            }
+            if constexpr (CTB) {
+                // slots that are not moves (diagonal, padding) stay tabu for good
+                unsigned w = 0;
+#pragma unroll
+                for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int u = tg * ROWS + j, v = tb * TILE_COLS + e;
+                        if (u >= n || v >= n || u == v) w |= 1u << (j * 4 + e);
+                    }
+                tbits[tg * nbw + tb] = w;
+                const long long c = tile_min_bits(d, w, tg * ROWS, tb * TILE_COLS, thr);
+                sel = c < sel ? c : sel;
+                continue;
             }
             const long long c = tile_min(d, u_, tg * ROWS, tb * TILE_COLS, it, thr);
             sel = c < sel ? c : sel;
@@ -804,6 +855,67 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             swt_r = reinterpret_cast<const unsigned *>(GmT + r * rs)[swl];
             swt_s = reinterpret_cast<const unsigned *>(GmT + s * rs)[swl];
         }
+        // ---- X, wide kernel: the row dot products of every task first, by whole waves.
+        //      The rows live in global memory, where one lane walking a row of its own
+        //      waits for every step; here eight lanes share a row (64 bytes each, so a
+        //      row is read in one contiguous stretch), a wave takes eight rows a step
+        //      (two steps in flight), family by family with the two side rows held in
+        //      registers, and the octet sums go to LDS for the task lanes.
+        if constexpr (GGLOB) {
+            const int oc = lane >> 3, kb = (lane & 7) * 64;
+            for (int q = 0; q < nq; ++q) {
+                const int f = sym ? 2 * q : q;
+                const uint8_t *Gf = (f & 1) ? GmT : Gm, *Df = (f & 1) ? DmT : Dm;
+                const uint8_t *s1 = f < 2 ? Df + r * rs : Gf + s * rs;
+                const uint8_t *s2 = f < 2 ? Df + s * rs : Gf + r * rs;
+                uint4 a1[4], a2[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int o = kb + 16 * c;
+                    const bool in = o < nb16;   // bytes past nb16 are padding or the next row
+                    a1[c] = in ? *reinterpret_cast<const uint4 *>(s1 + o) : make_uint4(0, 0, 0, 0);
+                    a2[c] = in ? *reinterpret_cast<const uint4 *>(s2 + o) : make_uint4(0, 0, 0, 0);
+                }
+                for (int ub = wid * 8; ub < n; ub += 2 * W * 8) {   // uniform per wave
+                    unsigned c1[2] = {0, 0}, c2[2] = {0, 0};
+                    uint4 x[2][4];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int u = ub + h * W * 8 + oc;
+                        const int su = u == r ? s : (u == s ? r : u);
+                        const uint8_t *row = f < 2 ? Gf + su * rs : Df + u * rs;
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const int o = kb + 16 * c;
+                            x[h][c] = u < n && o < nb16 ? *reinterpret_cast<const uint4 *>(row + o)
+                                                        : make_uint4(0, 0, 0, 0);
+                        }
+                    }
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            c1[h] = __builtin_amdgcn_udot4(x[h][c].x, a1[c].x, c1[h], false);
+                            c1[h] = __builtin_amdgcn_udot4(x[h][c].y, a1[c].y, c1[h], false);
+                            c1[h] = __builtin_amdgcn_udot4(x[h][c].z, a1[c].z, c1[h], false);
+                            c1[h] = __builtin_amdgcn_udot4(x[h][c].w, a1[c].w, c1[h], false);
+                            c2[h] = __builtin_amdgcn_udot4(x[h][c].x, a2[c].x, c2[h], false);
+                            c2[h] = __builtin_amdgcn_udot4(x[h][c].y, a2[c].y, c2[h], false);
+                            c2[h] = __builtin_amdgcn_udot4(x[h][c].z, a2[c].z, c2[h], false);
+                            c2[h] = __builtin_amdgcn_udot4(x[h][c].w, a2[c].w, c2[h], false);
+                        }
+                        // octet sums: quad_perm [1,0,3,2], [2,3,0,1], then the mirrored half row
+                        int v1 = (int)c1[h], v2 = (int)c2[h];
+                        v1 += dpp<0xB1>(v1); v2 += dpp<0xB1>(v2);
+                        v1 += dpp<0x4E>(v1); v2 += dpp<0x4E>(v2);
+                        v1 += dpp<0x141>(v1); v2 += dpp<0x141>(v2);
+                        const int u = ub + h * W * 8 + oc;
+                        if ((lane & 7) == 0 && u < n) xd[q * np + u] = make_int2(v1, v2);
+                    }
+                }
+            }
+            __syncthreads();  // the task lanes read xd
+        }
         // ---- X: one (u, family) task per lane: the update vectors of u, and the deltas
         //      of (u, r) and (u, s) under p'
         int colw_addr[MAXT], colw_val[MAXT];
@@ -848,7 +960,11 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             constexpr bool ONE_SHOT = MAXT == 1 && !FREQ && (!NARROW || ROWS <= 2);
             // (rows of n <= WIDE_N bytes: every step unrolled, offsets in the instructions;
             // the kernels with the frequency memory keep the loop, their registers are full)
-            if (ONE_SHOT && nb32 == 64) {
+            if constexpr (GGLOB) {
+                const int2 v = xd[q * np + u];   // made by the waves above
+                d1 = (unsigned)v.x;
+                d2 = (unsigned)v.y;
+            } else if (ONE_SHOT && nb32 == 64) {
                 dot_rows2_64(shared, side1, side2, d1, d2);
             } else if constexpr (NARROW) {
                 dot_rows2_u<1, WIDE_N>(shared, side1, side2, nb16, d1, d2);
@@ -993,6 +1109,39 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                     __hip_atomic_store(a.uloc + (size_t)ps_old * n + s, tt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
+        // compact tabu state, for the select of iteration it + 1 (made after B2): the moves
+        // of iterations i that expire now (i + t_i == it + 1, so i = it + 1 - t_i with t_i
+        // in [lo, hi]) leave the tabu list unless their pair has been made tabu again
+        // since (its latest until, a device-scope word, decides); then this move enters it
+        // (thread 0 drew ten[0] itself when tpos is 0).  A pair's slot and its mirror
+        // change together.
+        if constexpr (CTB) {
+            const int nxt = it + 1;
+            for (int q = t; q <= a.hi - a.lo; q += L) {
+                const int i = nxt - a.lo - q;
+                if (i < 1 || i >= it) continue;
+                const int e = ring[i & (TABU_RING - 1)];
+                if (i + (e >> 18) != nxt) continue;
+                const int u = (e >> 9) & 511, v = e & 511;
+                if ((u == r && v == s) ||
+                    __hip_atomic_load(untl + pidx(n, u, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != nxt)
+                    continue;
+                atomicAnd(tbit_word(u, v), ~tbit(u, v));
+                atomicAnd(tbit_word(v, u), ~tbit(v, u));
+            }
+            if (t == 0) {
+                const int tc = ten[tpos];
+                ring[it & (TABU_RING - 1)] = (tc << 18) | (r << 9) | s;
+                __hip_atomic_store(untl + pidx(n, r, s), it + tc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (tc >= 2) {   // tabu at it + 1
+                    atomicOr(tbit_word(r, s), tbit(r, s));
+                    atomicOr(tbit_word(s, r), tbit(s, r));
+                } else {         // admissible again at it + 1, whatever an earlier move left
+                    atomicAnd(tbit_word(r, s), ~tbit(r, s));
+                    atomicAnd(tbit_word(s, r), ~tbit(s, r));
+                }
+            }
+        }
         __syncthreads();  // B2
 
         // ---- C: G, G^T and p follow the move
@@ -1237,7 +1386,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                         }
                     tabu_set = true;
                 }
-            } else if (TABU) {
+            } else if (TABU && !CTB) {
                 // the move and its mirror become tabu until iteration it + t
                 tabu_set = (g == r / ROWS && b == (s >> 2)) || (g == s / ROWS && b == (r >> 2));
                 if (g == r / ROWS && b == (s >> 2)) {
@@ -1286,7 +1435,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 for (int j = 0; j < ROWS; ++j) {
                     const int4 x = a.tile_d[tile_addr(q, j)];
                     d[j][0] = x.x; d[j][1] = x.y; d[j][2] = x.z; d[j][3] = x.w;
-                    if (TABU) {
+                    if (TABU && !CTB) {
                         const int4 y = a.tile_u[tile_addr(q, j)];
                         u_[j][0] = y.x; u_[j][1] = y.y; u_[j][2] = y.z; u_[j][3] = y.w;
                     }
@@ -1295,9 +1444,11 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
 #pragma unroll
                 for (int j = 0; j < ROWS; ++j) {
                     a.tile_d[tile_addr(q, j)] = make_int4(d[j][0], d[j][1], d[j][2], d[j][3]);
-                    if (TABU && changed) a.tile_u[tile_addr(q, j)] = make_int4(u_[j][0], u_[j][1], u_[j][2], u_[j][3]);
+                    if (TABU && !CTB && changed)
+                        a.tile_u[tile_addr(q, j)] = make_int4(u_[j][0], u_[j][1], u_[j][2], u_[j][3]);
                 }
-                const long long c = tile_min(d, u_, tg * ROWS, tb * TILE_COLS, it + 1, thr);
+                const long long c = CTB ? tile_min_bits(d, tbits[tg * nbw + tb], tg * ROWS, tb * TILE_COLS, thr)
+                                        : tile_min(d, u_, tg * ROWS, tb * TILE_COLS, it + 1, thr);
                 sel = c < sel ? c : sel;
             }
         }
@@ -1353,9 +1504,22 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
 }
 
 // The search body for both symmetric and general instances (one uniform branch).
+// CT: the compact tabu state (wide streamed tabu searches without the frequency memory,
+// run whole): 0 never, 1 when the tenures fit its ring (a uniform branch), 2 always (the
+// caller checked a.hi < TABU_RING).
 template <int ROWS, bool TABU, int MAXT, bool RESUME, bool STREAM, bool NARROW, bool FREQ = false,
-          bool GGLOB = false>
+          bool GGLOB = false, int CT = 0>
 __device__ __attribute__((always_inline)) void search_body(const Item &a, unsigned char *sm) {
+    if constexpr (TABU && STREAM && GGLOB && !FREQ && !RESUME && CT > 0) {
+        if (CT == 2 || a.hi < TABU_RING) {
+            if (a.sym)
+                search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, true, NARROW, FREQ, GGLOB, true>(a, sm);
+            else
+                search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, false, NARROW, FREQ, GGLOB, true>(a, sm);
+            return;
+        }
+        if constexpr (CT == 2) return;
+    }
     if (a.sym)
         search_body_t<ROWS, TABU, MAXT, RESUME, STREAM, true, NARROW, FREQ, GGLOB>(a, sm);
     else
@@ -1423,7 +1587,7 @@ batch_group_kernel(BatchArgs b) {
     }
     if constexpr (WIDE) {
         it.gmat = b.gwork + it.g_off;
-        search_body<STREAM_ROWS, true, WIDE_MAXT, false, true, false, false, true>(it, sm);
+        search_body<STREAM_ROWS, true, WIDE_MAXT, false, true, false, false, true, 1>(it, sm);
     } else {
         search_body<ROWS, true, MAXT, false, STREAM, ROWS <= 4>(it, sm);
     }
@@ -1496,7 +1660,9 @@ __global__ void __launch_bounds__(BATCH_LANES) resume_wide_kernel(const Item *it
 
 // Streamed search, one per workgroup: block b runs search job0 + b of the launch.  WIDE
 // (n above WIDE_N): G and G^T in global scratch, up to four (index, family) tasks a lane.
-template <bool TABU, bool FREQ = false, bool WIDE = false>
+// CT (wide tabu searches without the frequency memory): the compact tabu state, for
+// tenures below TABU_RING
+template <bool TABU, bool FREQ = false, bool WIDE = false, bool CT = false>
 __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char sm[];
     const int job = a.job0 + blockIdx.x;
@@ -1530,7 +1696,7 @@ __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     it.tile_u = it.tile_d + a.tile_stride / 2;
     if constexpr (WIDE) {
         it.gmat = a.gwork + (size_t)blockIdx.x * a.gstride;
-        search_body<STREAM_ROWS, TABU, WIDE_MAXT, false, true, false, FREQ, true>(it, sm);
+        search_body<STREAM_ROWS, TABU, WIDE_MAXT, false, true, false, FREQ, true, CT ? 2 : 0>(it, sm);
     } else {
         search_body<STREAM_ROWS, TABU, 1024 / BATCH_LANES, false, true, false, FREQ>(it, sm);
     }
@@ -1690,6 +1856,8 @@ hipError_t launch_stream(bool tabu, const SearchArgs &a, int grid, hipStream_t s
         if (!a.gwork) return hipErrorInvalidValue;
         if (tabu && a.freq)
             hipLaunchKernelGGL((stream_kernel<true, true, true>), dim3(grid), dim3(BATCH_LANES), smem, st, a);
+        else if (tabu && a.hi < TABU_RING)
+            hipLaunchKernelGGL((stream_kernel<true, false, true, true>), dim3(grid), dim3(BATCH_LANES), smem, st, a);
         else if (tabu)
             hipLaunchKernelGGL((stream_kernel<true, false, true>), dim3(grid), dim3(BATCH_LANES), smem, st, a);
         else

@@ -4,10 +4,11 @@ Beyond n = 256 the permuted flows G = F[p][p] and G^T no longer fit in LDS besid
 rest of a search, so the wide kernel keeps them, like D and D^T, in global scratch (the
 move exchanges two of their rows and columns in place, between the workgroup barriers),
 runs up to four (index, family) tasks per lane, and the
-starting neighbourhood is evaluated entry by entry from Eq. (2).  Every case is compared
-bit for bit with the oracle (the frequency memory and tabu attributes on this kernel are
-covered with the other tile shapes).  The batched and served paths stop at n = 256 and
-say so.
+starting neighbourhood comes from the blocked matrix-core table kernel.  Tabu searches
+without the frequency memory keep a compact tabu state (a bit per slot in LDS and a ring
+of recent moves) while the tenures fit the ring, and the per-slot tenure words beyond
+that.  Every case is compared bit for bit with the oracle (the frequency memory and tabu
+attributes on this kernel are covered with the other tile shapes).
 """
 import os
 import sys
@@ -245,3 +246,35 @@ def test_wide_table_taking_entry_points_and_full_descent():
     res = pmap(lambda j: oracle.two_opt(F, D, perms[j]), range(2))
     for j, r in enumerate(res):
         assert (q[j] == r[0]).all() and qc[j] == r[1] and qs[j] == r[2], j
+
+
+@pytest.mark.parametrize("sym,lo,hi", [(False, 0, 2), (True, 1, 3), (False, 5, 40)])
+def test_wide_compact_tabu_state_short_tenures(sym, lo, hi):
+    """Tenures of 0 and 1 (the move is admissible again at once), pairs made tabu again
+    before they expire, and many expiries an iteration: the compact tabu state of the
+    wide kernel against oracle.tabu."""
+    n, k, iters = 300, 3, 400
+    rng = np.random.default_rng(9500 + lo + hi)
+    F, D = W.random_instance(rng, n, 0, 99, symmetric=sym)
+    perms = W.starts(rng, n, k)
+    note("wide compact tabu n=%d sym=%d tenure [%d, %d] iters=%d" % (n, sym, lo, hi, iters))
+    with qap.Handle(F, D) as h:
+        p, c, d = h.tabu(perms, iters, lo, hi, 31)
+    res = pmap(lambda j: oracle.tabu(F, D, perms[j], iters, lo, hi, 31, j), range(k))
+    for j, r in enumerate(res):
+        assert (p[j] == r[0]).all() and c[j] == r[1] and d[j] == r[2], j
+
+
+def test_wide_tenures_past_the_compact_ring():
+    """Tenures of 1024 and more do not fit the compact state's ring of moves: such searches
+    keep a tenure word per slot, against oracle.tabu."""
+    n, k, iters, lo, hi = 260, 2, 120, 1020, 1100
+    rng = np.random.default_rng(9600)
+    F, D = W.random_instance(rng, n, 0, 99)
+    perms = W.starts(rng, n, k)
+    note("wide per-slot tenure words n=%d tenure [%d, %d]" % (n, lo, hi))
+    with qap.Handle(F, D) as h:
+        p, c, d = h.tabu(perms, iters, lo, hi, 41)
+    res = pmap(lambda j: oracle.tabu(F, D, perms[j], iters, lo, hi, 41, j), range(k))
+    for j, r in enumerate(res):
+        assert (p[j] == r[0]).all() and c[j] == r[1] and d[j] == r[2], j
