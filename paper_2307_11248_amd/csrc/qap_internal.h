@@ -98,9 +98,10 @@ __host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym, boo
     if (gglobal) {
         s.tb = take((np / 8) * (np / TILE_COLS) * 4);
         s.ring = take(TABU_RING * 4);
-        // the two row dot products of every (index, family) task, made by whole waves
-        s.xd = take(families(sym) * np * 8);
     }
+    // (streamed kernels) the two row dot products of every (index, family) task, made by
+    // whole waves (at n = 256 not symmetric the plan still fits: 156 880 bytes)
+    if (dglobal) s.xd = take(families(sym) * np * 8);
     s.total = o;
     return s;
 }

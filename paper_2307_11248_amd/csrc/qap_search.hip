@@ -382,8 +382,12 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     const int nbw = np / TILE_COLS;
     auto tbit_word = [&](int u, int v) -> unsigned * { return tbits + (u >> 3) * nbw + (v >> 2); };
     auto tbit = [&](int u, int v) -> unsigned { return 1u << (((u & 7) << 2) | (v & 3)); };
-    // (wide kernel) the two row dot products of task (u, family q) at xd[q * np + u]
-    int2 *xd = GGLOB ? reinterpret_cast<int2 *>(sm + S.xd) : nullptr;
+    // (streamed kernels run whole, and the wide one) the two row dot products of task
+    // (u, family q) at xd[q * np + u], made by whole waves.  The chunked runs of the
+    // server keep the per-lane walk: their kernel carries every tile shape and is held to
+    // its registers, and the wave-made products measured slower there.
+    constexpr bool XW = STREAM && (GGLOB || !RESUME);
+    int2 *xd = XW ? reinterpret_cast<int2 *>(sm + S.xd) : nullptr;
 
     // ---- stage D, D^T; read and check the start
     if (!STREAM) {
@@ -855,13 +859,14 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             swt_r = reinterpret_cast<const unsigned *>(GmT + r * rs)[swl];
             swt_s = reinterpret_cast<const unsigned *>(GmT + s * rs)[swl];
         }
-        // ---- X, wide kernel: the row dot products of every task first, by whole waves.
-        //      The rows live in global memory, where one lane walking a row of its own
-        //      waits for every step; here eight lanes share a row (64 bytes each, so a
-        //      row is read in one contiguous stretch), a wave takes eight rows a step
-        //      (two steps in flight), family by family with the two side rows held in
-        //      registers, and the octet sums go to LDS for the task lanes.
-        if constexpr (GGLOB) {
+        // ---- X, streamed kernels: the row dot products of every task first, by whole
+        //      waves.  Rows of D (and in the wide kernel of G) live in global memory, where
+        //      one lane walking a row of its own waits for every step; here eight lanes
+        //      share a row (64 bytes each, so a row is read in one contiguous stretch), a
+        //      wave takes eight rows a step (two steps in flight), family by family with
+        //      the two side rows held in registers, and the octet sums go to LDS for the
+        //      task lanes.
+        if constexpr (XW) {
             const int oc = lane >> 3, kb = (lane & 7) * 64;
             for (int q = 0; q < nq; ++q) {
                 const int f = sym ? 2 * q : q;
@@ -960,7 +965,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             constexpr bool ONE_SHOT = MAXT == 1 && !FREQ && (!NARROW || ROWS <= 2);
             // (rows of n <= WIDE_N bytes: every step unrolled, offsets in the instructions;
             // the kernels with the frequency memory keep the loop, their registers are full)
-            if constexpr (GGLOB) {
+            if constexpr (XW) {
                 const int2 v = xd[q * np + u];   // made by the waves above
                 d1 = (unsigned)v.x;
                 d2 = (unsigned)v.y;
