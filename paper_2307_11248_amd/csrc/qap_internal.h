@@ -52,7 +52,7 @@ __host__ __device__ inline int families(int sym) { return sym ? 2 : 4; }
 // locations under the current permutation p), G^T; only D and G when F and D are
 // both symmetric.
 struct Smem {
-    int d, dt, g, gt, acbe, rpr, rps, kc, perm, bestp, pinv, ten, red, tb, ring, xd, total;
+    int d, dt, g, gt, acbe, rpr, rps, kc, perm, bestp, pinv, ten, red, tb, ring, xd, sv, total;
 };
 
 // Compact tabu state of the wide streamed kernel: moves of the last TABU_RING iterations
@@ -60,7 +60,8 @@ struct Smem {
 constexpr int TABU_RING = 1024;
 
 // dglobal: D and D^T are read from global memory (the streamed kernels), not staged;
-// gglobal: so are G and G^T (the wide streamed kernel, n above WIDE_N).
+// gglobal: the wide streamed kernel (n above WIDE_N), which keeps no G and G^T: it reads
+// F and F^T in global memory through the permutation.
 __host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym, bool dglobal = false,
                                           bool gglobal = false) {
     const int rs = row_stride(n);
@@ -94,10 +95,12 @@ __host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym, boo
     s.red = take(16 * 8);
     // (gglobal) compact tabu state: a bit per slot, one word per 8 x 4 tile position of
     // the padded grid, and the ring of recent moves
-    s.tb = s.ring = s.xd = -1;
+    s.tb = s.ring = s.xd = s.sv = -1;
     if (gglobal) {
         s.tb = take((np / 8) * (np / TILE_COLS) * 4);
         s.ring = take(TABU_RING * 4);
+        // the permuted side rows of the row recomputation, two per family, RS bytes each
+        s.sv = take(families(sym) * 2 * rs);
     }
     // (streamed kernels) the two row dot products of every (index, family) task, made by
     // whole waves (at n = 256 not symmetric the plan still fits: 156 880 bytes)

@@ -354,15 +354,13 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     // D and D^T: staged in LDS, or (streamed kernels) read in place from global memory
     const uint8_t *Dm = STREAM ? a.mats + 2 * n * rs : sm + S.d;
     const uint8_t *DmT = STREAM ? a.mats + 3 * n * rs : sm + S.dt;
-    // G and G^T: in LDS, or (wide kernel) in the search's global scratch, where a byte's
-    // offset is counted from a.gmat instead of from the LDS base
-    uint8_t *const gbase = GGLOB ? a.gmat : sm;
-    const int g_off = GGLOB ? 0 : S.g, gt_off = GGLOB ? (sym ? 0 : n * rs) : S.gt;
-    uint8_t *Gm = gbase + g_off, *GmT = gbase + gt_off;
-    // (wide kernel: G in global memory is written by some lanes and read by others; the
-    // waves of a workgroup share one compute unit's write-through vector L1, so the
-    // workgroup barriers order those accesses as they do in LDS.  Device-scope fences
-    // would write back and invalidate the whole L2 twice per iteration.)
+    // G and G^T in LDS; the wide kernel keeps none: F and F^T in global memory are shared
+    // by every search of the instance, and G[x][y] = F[p_x][p_y] is read through the
+    // permutation where it is needed
+    uint8_t *const gbase = sm;
+    const int g_off = S.g, gt_off = S.gt;
+    uint8_t *Gm = GGLOB ? nullptr : gbase + g_off, *GmT = GGLOB ? nullptr : gbase + gt_off;
+    const uint8_t *FgW = a.mats, *FgWT = a.mats + (size_t)n * rs;
     int *rpr = reinterpret_cast<int *>(sm + S.rpr);
     int *rps = reinterpret_cast<int *>(sm + S.rps);
     int *kc = reinterpret_cast<int *>(sm + S.kc);
@@ -370,6 +368,8 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     int *perm = reinterpret_cast<int *>(sm + S.perm);
     int *bestp = reinterpret_cast<int *>(sm + S.bestp);
     int *pinv = reinterpret_cast<int *>(sm + S.pinv);
+    // (wide kernel) G[x][y] under the current permutation
+    auto gF = [&](int x, int y) -> int { return FgW[perm[x] * rs + perm[y]]; };
     int *ten = reinterpret_cast<int *>(sm + S.ten);
     long long *red = reinterpret_cast<long long *>(sm + S.red);
     // compact tabu state: tbits[g * nbw + b] holds the tabu bits of the 8 x 4 slots at
@@ -426,8 +426,9 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         return;
     }
 
-    // ---- G = F[p][p] and G^T, gathered from the global u8 copies of F and F^T
-    {
+    // ---- G = F[p][p] and G^T, gathered from the global u8 copies of F and F^T (the wide
+    //      kernel keeps no G: it reads F through the permutation where G is needed)
+    if constexpr (!GGLOB) {
         const int wpr = rs / 4;  // words per row
         const uint8_t *Fg = a.mats, *FgT = a.mats + (size_t)n * rs;
         for (int i = t; i < n * wpr; i += L) {
@@ -452,9 +453,22 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     // ---- RD_u = sum_k D[u][k] G[u][k], CD_u = sum_k D[k][u] G[k][u]; cost (Eq. 1) = sum RD_u
     long long part = 0;
     for (int u = t; u < n; u += L) {
-        const int rd = (int)dot_rows(Dm + u * rs, Gm + u * rs, nb16);
+        int rd, cd;
+        if constexpr (GGLOB) {
+            // G[u][k] = F[p_u][p_k] and G^T[u][k] = F^T[p_u][p_k], byte by byte (once)
+            rd = cd = 0;
+            const int pu = perm[u];
+            for (int k = 0; k < n; ++k) {
+                const int pk = perm[k];
+                rd += (int)Dm[u * rs + k] * (int)FgW[pu * rs + pk];
+                if (!sym) cd += (int)DmT[u * rs + k] * (int)FgWT[pu * rs + pk];
+            }
+        } else {
+            rd = (int)dot_rows(Dm + u * rs, Gm + u * rs, nb16);
+            cd = sym ? rd : (int)dot_rows(DmT + u * rs, GmT + u * rs, nb16);
+        }
         rpr[u] = rd;
-        rps[u] = sym ? rd : (int)dot_rows(DmT + u * rs, GmT + u * rs, nb16);
+        rps[u] = sym ? rd : cd;
         part += rd;
     }
     part = wave_sum64(part);
@@ -475,7 +489,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             rdv[i] = rpr[u];
             cdv[i] = rps[u];
             duv[i] = Dm[u * rs + u];
-            guv[i] = Gm[u * rs + u];
+            guv[i] = GGLOB ? gF(u, u) : Gm[u * rs + u];
         }
     }
 
@@ -847,10 +861,10 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         }
 
         // words of rows r and s of G and G^T for the exchange in C (read now, G is not
-        // written before B2); lanes 0 .. 63 of wave 0 (the bytes of n <= 256), or in the
-        // wide kernel lanes 0 .. RS/4-1, all of which hold task 0
-        const int swl = GGLOB ? t : lane;
-        const bool swap_lane = GGLOB ? t < rs / 4 : (wid == 0 && lane < rs / 4);
+        // written before B2); lanes 0 .. 63 of wave 0 (the bytes of n <= 256), all of
+        // which hold task 0 (the wide kernel keeps no G, so nothing to exchange)
+        const int swl = lane;
+        const bool swap_lane = !GGLOB && wid == 0 && lane < rs / 4;
         unsigned sw_r = 0, sw_s = 0, swt_r = 0, swt_s = 0;
         int sw_grr = 0, sw_grs = 0, sw_gsr = 0, sw_gss = 0;
         if (swap_lane) {
@@ -868,11 +882,37 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         //      task lanes.
         if constexpr (XW) {
             const int oc = lane >> 3, kb = (lane & 7) * 64;
+            // wide kernel, no G: with j = p_k, the four families become
+            //   f = 0: sum_k G[su][k] D[b][k]     = sum_j F[p_su][j]   D[b][pinv_j]
+            //   f = 1: sum_k G^T[su][k] D^T[b][k] = sum_j F^T[p_su][j] D^T[b][pinv_j]
+            //   f = 2: sum_k D[u][k] G[b][k]      with G[b][k]   = F[p_b][p_k]
+            //   f = 3: sum_k D^T[u][k] G^T[b][k]  with G^T[b][k] = F^T[p_b][p_k]
+            // so the rows each task walks are rows of F, F^T, D, D^T (shared by every
+            // search of the instance), and only the two side rows of each family are
+            // permuted: gathered here into LDS once per iteration (zero past n)
+            uint8_t *svb = GGLOB ? sm + S.sv : nullptr;
+            if constexpr (GGLOB) {
+                const int per = 2 * nb16;
+                for (int idx = t; idx < nq * per; idx += L) {
+                    const int q = idx / per, rem = idx - q * per, h = rem >= nb16 ? 1 : 0, j = rem - h * nb16;
+                    const int f = sym ? 2 * q : q;
+                    int v = 0;
+                    if (j < n) {
+                        const int b = (f < 2) == (h == 0) ? r : s;   // side 1: row r (f < 2) or s
+                        v = f == 0   ? Dm[b * rs + pinv[j]]
+                            : f == 1 ? DmT[b * rs + pinv[j]]
+                            : f == 2 ? FgW[perm[b] * rs + perm[j]]
+                                     : FgWT[perm[b] * rs + perm[j]];
+                    }
+                    svb[(q * 2 + h) * rs + j] = (uint8_t)v;
+                }
+                __syncthreads();   // the side rows are complete
+            }
             for (int q = 0; q < nq; ++q) {
                 const int f = sym ? 2 * q : q;
                 const uint8_t *Gf = (f & 1) ? GmT : Gm, *Df = (f & 1) ? DmT : Dm;
-                const uint8_t *s1 = f < 2 ? Df + r * rs : Gf + s * rs;
-                const uint8_t *s2 = f < 2 ? Df + s * rs : Gf + r * rs;
+                const uint8_t *s1 = GGLOB ? svb + (q * 2) * rs : (f < 2 ? Df + r * rs : Gf + s * rs);
+                const uint8_t *s2 = GGLOB ? svb + (q * 2 + 1) * rs : (f < 2 ? Df + s * rs : Gf + r * rs);
                 uint4 a1[4], a2[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
@@ -888,7 +928,13 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                     for (int h = 0; h < 2; ++h) {
                         const int u = ub + h * W * 8 + oc;
                         const int su = u == r ? s : (u == s ? r : u);
-                        const uint8_t *row = f < 2 ? Gf + su * rs : Df + u * rs;
+                        const uint8_t *row;
+                        if constexpr (GGLOB) {
+                            const int psu = u < n ? perm[su] : 0;
+                            row = f == 0 ? FgW + psu * rs : (f == 1 ? FgWT + psu * rs : Df + u * rs);
+                        } else {
+                            row = f < 2 ? Gf + su * rs : Df + u * rs;
+                        }
 #pragma unroll
                         for (int c = 0; c < 4; ++c) {
                             const int o = kb + 16 * c;
@@ -940,13 +986,16 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             //   q=0: d_ur d_us D_rr D_rs   q=1: d_ru d_su D_sr D_ss
             //   q=2: g_ur g_us G_rr G_rs   q=3: g_ru g_su G_sr G_ss   (g = G under p)
             // (symmetric: q=0 the D bytes, q=1 the G bytes, plus D_ss / G_ss).
-            const uint8_t *M = (sym ? q == 0 : q < 2) ? Dm : Gm;
+            const bool gfam = !(sym ? q == 0 : q < 2);
+            const uint8_t *M = gfam ? Gm : Dm;
             const bool tr = !sym && (q & 1);
-            const unsigned rec = (unsigned)M[tr ? r * rs + u : u * rs + r] |
-                                 ((unsigned)M[tr ? s * rs + u : u * rs + s] << 8) |
-                                 ((unsigned)M[tr ? s * rs + r : r * rs + r] << 16) |
-                                 ((unsigned)M[tr ? s * rs + s : r * rs + s] << 24);
-            const int ex = sym ? M[s * rs + s] : 0;
+            // entry (x, y) of D or G (the wide kernel reads G through F and p)
+            auto mat = [&](int x, int y) -> unsigned {
+                return GGLOB && gfam ? (unsigned)gF(x, y) : (unsigned)M[x * rs + y];
+            };
+            const unsigned rec = mat(tr ? r : u, tr ? u : r) | (mat(tr ? s : u, tr ? u : s) << 8) |
+                                 (mat(tr ? s : r, r) << 16) | (mat(tr ? s : r, s) << 24);
+            const int ex = sym ? (int)mat(s, s) : 0;
 
             // dot products with the O(1) correction sum_k a[sigma k] c[k] = a.c + (a_s - a_r)(c_r - c_s),
             // a a row of G or G^T, c a row of D or D^T:
@@ -1078,7 +1127,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             if (u == r) guv[i] = G_ss;
             if (u == s) guv[i] = G_rr;
             // this lane's share of exchanging columns r and s of G (and G^T) in row u
-            if (u != r && u != s) {
+            if (!GGLOB && u != r && u != s) {
                 if (sym) {
                     colw_addr[i] = g_off + u * rs + (q == 0 ? r : s);
                     colw_val[i] = q == 0 ? g_us : g_ur;
@@ -1184,6 +1233,10 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             const int pr = perm[r], ps = perm[s];
             perm[r] = ps;
             perm[s] = pr;
+            if (GGLOB) {   // the wide kernel's gathers read p^-1 too
+                pinv[ps] = r;
+                pinv[pr] = s;
+            }
         }
         // ---- C: the tiles follow the move
         const int2 kk = *reinterpret_cast<const int2 *>(kc);
