@@ -45,14 +45,14 @@ BYTES_PER_EVAL = 8   # an int32 delta read and written per entry per step if kep
 # valid only for the kernel sources they were taken with.
 KERNEL_SOURCES = ["paper_2307_11248_amd/csrc/qap_search.hip", "paper_2307_11248_amd/csrc/qap_internal.h"]
 TRAFFIC = {
-    "c2_n64_dense_tabu": {"bytes": int((2 * 724.5 + 40.0) * 1024), "sources": "d89d9a58df8ed529"},
-    "c3_n128_euclid_tabu": {"bytes": int((2 * 4416.5 + 144.0) * 1024), "sources": "d89d9a58df8ed529"},
-    # sum over the kernels of one launch (tiles of 2 rows on 128 and 256 lanes, of 4 rows on
-    # 256, 512 and 768)
-    "c4_batched_uneven_tabu": {"bytes": int((2 * (65183.0 + 43360.6 + 7930.35 + 3354.875 + 1979.125)
-                                             + (872.5 + 408.453 + 207.875 + 92.625 + 76.875)) * 1024),
-                               "sources": "d89d9a58df8ed529"},
-    "n512_dense_tabu": {"bytes": int((2 * 311668000.0 + 299234000.0) * 1024), "sources": "d89d9a58df8ed529"},
+    "c2_n64_dense_tabu": {"bytes": int((2 * 730.5 + 40.0) * 1024), "sources": "3e59f07b5699b9eb"},
+    "c3_n128_euclid_tabu": {"bytes": int((2 * 4407.5 + 144.0) * 1024), "sources": "3e59f07b5699b9eb"},
+    # per dispatch, summed over the kernels of one launch (tiles of 2 rows on 128 and 256
+    # lanes, of 4 rows on 256, 512 and 768)
+    "c4_batched_uneven_tabu": {"bytes": int((2 * (65159.33 + 43349.67 + 8010.6 + 3258.5 + 1972.37)
+                                             + (872.58 + 408.77 + 208.94 + 92.625 + 75.81)) * 1024),
+                               "sources": "3e59f07b5699b9eb"},
+    "n512_dense_tabu": {"bytes": int((2 * 143175000.0 + 266390000.0) * 1024), "sources": "3e59f07b5699b9eb"},
 }
 
 

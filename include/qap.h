@@ -73,11 +73,9 @@ const char *qap_strerror(int code);
  * Every entry point serves every n <= QAP_NMAX: the searches hold the neighbourhood in
  * registers and F, F^T, D, D^T in LDS while that fits one workgroup (n <= 176 in the
  * batched kernels), and above that run the streamed kernel (neighbourhood in global
- * memory, only G = F[p][p] in LDS).  Above n = 256 they run its wide form, which keeps G
- * and G^T in global memory too (2 n RS bytes of scratch per search, RS = n rounded up to
- * 32, plus 16: stream-ordered for the single-instance calls, owned by the plan in a
- * batch, in the pool for a served request), and the neighbourhood table is evaluated
- * entry by entry from Eq. (2).  QAP_E_UNSUPPORTED is left for a device whose LDS is
+ * memory, only G = F[p][p] in LDS).  Above n = 256 they run its wide form, which keeps no
+ * G (it reads F and F^T through the permutation), and the neighbourhood table is built by
+ * a blocked matrix-core kernel.  QAP_E_UNSUPPORTED is left for a device whose LDS is
  * smaller than the streamed kernel needs.
  */
 int qap_create(const int32_t *F, const int32_t *D, int32_t n, qap_handle *out);
@@ -204,7 +202,7 @@ int qap_tabu_trace_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t iter
  * serving loops, harnesses that forbid hipMalloc): qap_tabu_async with the same
  * arguments, semantics and results, which calls no allocating routine.  Its scratch (the
  * neighbourhood tables, int32[k][n(n-1)/2] rounded up to 256 bytes, and for the streamed
- * kernels the tile state of every search, plus G and G^T above n = 256) is carved
+ * kernels the tile state of every search) is carved
  * from one fixed array of QAP_NOALLOC_SCRATCH_BYTES per GPU, which the library holds
  * from the first qap_create on that GPU until the process ends.  A call that would need
  * more returns QAP_E_SCRATCH and enqueues nothing.  Every call on one GPU shares that

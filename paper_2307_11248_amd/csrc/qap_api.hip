@@ -232,11 +232,10 @@ int make_tables(qap_ctx *h, const int32_t *d_perms, int k, int32_t **d_table, hi
     return QAP_OK;
 }
 
-// Scratch buffers of the streamed kernels supplied by the caller (the entry point that
-// allocates nothing): tile state of every search of the launch, and G, G^T above WIDE_N.
+// Scratch buffer of the streamed kernels supplied by the caller (the entry point that
+// allocates nothing): tile state of every search of the launch.
 struct StreamScratch {
     int4 *tile_work;
-    uint8_t *gwork;
 };
 
 hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipStream_t st, bool plain,
@@ -287,10 +286,6 @@ hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipS
     if (ri == kStream && pre) {
         a.tile_stride = stream_tile_int4(a.ntiles);
         a.tile_work = pre->tile_work;
-        if (h->n > WIDE_N) {
-            a.gstride = wide_g_bytes(h->n, h->sym);
-            a.gwork = pre->gwork;
-        }
         a.job0 = 0;
         return launch_stream(algo == 0, a, k, st);
     }
@@ -301,14 +296,6 @@ hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipS
         e = report(hipMallocAsync((void **)&a.tile_work, (size_t)per_launch * a.tile_stride * sizeof(int4), st),
                    "hipMallocAsync");
         if (e != hipSuccess) return e;
-        if (h->n > WIDE_N) {   // G and G^T of every search of a launch
-            a.gstride = wide_g_bytes(h->n, h->sym);
-            e = report(hipMallocAsync((void **)&a.gwork, (size_t)per_launch * a.gstride, st), "hipMallocAsync");
-            if (e != hipSuccess) {
-                (void)hipFreeAsync(a.tile_work, st);
-                return e;
-            }
-        }
         if (plain) {
             for (int j = 0; j < k && e == hipSuccess; ++j) {
                 a.job0 = j;
@@ -318,11 +305,7 @@ hipError_t launch_shaped(qap_ctx *h, int algo, int ri, SearchArgs a, int k, hipS
             a.job0 = 0;
             e = launch_stream(algo == 0, a, k, st);
         }
-        hipError_t e2 = hipFreeAsync(a.tile_work, st);
-        if (a.gwork) {
-            const hipError_t e3 = hipFreeAsync(a.gwork, st);
-            if (e2 == hipSuccess) e2 = e3;
-        }
+        const hipError_t e2 = hipFreeAsync(a.tile_work, st);
         return e != hipSuccess ? e : e2;
     }
     const int rows = kRowsChoices[ri];
@@ -419,7 +402,6 @@ struct qap_batch {
     Item *d_items = nullptr;
     int32_t *d_table = nullptr;
     int4 *d_tile_work = nullptr;    // tile state of the streamed searches
-    uint8_t *d_gwork = nullptr;     // G and G^T of the searches above WIDE_N
     size_t table_smem = 0;
     // starting neighbourhoods of instances above WIDE_N: one Eq. (2) launch per instance
     // (offsets into the run's starts and the plan's tables); the matrix-core table kernel
@@ -764,16 +746,14 @@ int qap_tabu_noalloc_async(qap_handle h, int32_t *d_perms, int32_t k, int32_t it
     const int ri = launch_shape(h, 0, k);
     if (ri < 0) return QAP_E_UNSUPPORTED;
     const size_t table_bytes = align256((size_t)k * h->m * sizeof(int32_t));
-    size_t tile_bytes = 0, g_bytes = 0;
-    if (ri == kStream) {
+    size_t tile_bytes = 0;
+    if (ri == kStream)
         tile_bytes = align256((size_t)k * stream_tile_int4(shape_tiles(h, ri).ntiles) * sizeof(int4));
-        if (h->n > WIDE_N) g_bytes = (size_t)k * wide_g_bytes(h->n, h->sym);
-    }
-    if (table_bytes + tile_bytes + g_bytes > (size_t)QAP_NOALLOC_SCRATCH_BYTES) return QAP_E_SCRATCH;
+    if (table_bytes + tile_bytes > (size_t)QAP_NOALLOC_SCRATCH_BYTES) return QAP_E_SCRATCH;
     // every byte used is written before it is read (tables by the table kernel, tile state
-    // and G when each search starts), so nothing needs clearing
+    // when each search starts), so nothing needs clearing
     int32_t *d_table = reinterpret_cast<int32_t *>(base);
-    StreamScratch pre{reinterpret_cast<int4 *>(base + table_bytes), base + table_bytes + tile_bytes};
+    StreamScratch pre{reinterpret_cast<int4 *>(base + table_bytes)};
     const hipStream_t st = (hipStream_t)stream;
     TableArgs ta{h->d_mats, d_perms, nullptr, d_table, h->n, h->m, k, h->sym};
     hipError_t e = launch_table(ta, st);
@@ -884,7 +864,7 @@ int batch_create_impl(const qap_handle *hs, int32_t m, const int32_t *k_per, int
     *out = nullptr;
     std::vector<Item> items;
     std::vector<WideTable> wide_tables;
-    long long perm_off = 0, out_off = 0, table_off = 0, tile_off = 0, freq_off = 0, uloc_off = 0, g_off = 0;
+    long long perm_off = 0, out_off = 0, table_off = 0, tile_off = 0, freq_off = 0, uloc_off = 0;
     size_t gsmem[BV_COUNT] = {}, tsmem = 0, fsmem = 0;
     for (int i = 0; i < m; ++i) {
         qap_ctx *h = hs[i];
@@ -933,10 +913,6 @@ int batch_create_impl(const qap_handle *hs, int32_t m, const int32_t *k_per, int
             if (streamed) {
                 it.tile_off = tile_off;
                 tile_off += stream_tile_int4(ts.ntiles);
-            }
-            if (wide) {
-                it.g_off = g_off;
-                g_off += wide_g_bytes(h->n, h->sym);
             }
             it.iters = iters;
             it.lo = lo_per[i];
@@ -1032,7 +1008,6 @@ int batch_create_impl(const qap_handle *hs, int32_t m, const int32_t *k_per, int
         if (e == hipSuccess) e = hipMalloc((void **)&b->d_items, items.size() * sizeof(Item));
         if (e == hipSuccess) e = hipMalloc((void **)&b->d_table, (size_t)table_off * sizeof(int32_t) + 16);
         if (e == hipSuccess && tile_off > 0) e = hipMalloc((void **)&b->d_tile_work, (size_t)tile_off * sizeof(int4));
-        if (e == hipSuccess && g_off > 0) e = hipMalloc((void **)&b->d_gwork, (size_t)g_off);
         if (e == hipSuccess && freq) e = hipMalloc((void **)&b->d_freq, (size_t)freq_off * sizeof(int32_t) + 16);
         if (e == hipSuccess && uloc_off > 0)
             e = hipMalloc((void **)&b->d_uloc, (size_t)uloc_off * sizeof(int32_t) + 16);
@@ -1108,8 +1083,7 @@ extern "C" int qap_batch_tables_async(qap_batch_handle b, const int32_t *d_perms
     const hipStream_t st = (hipStream_t)stream;
     // the searches above WIDE_N come last (their variant is the last one)
     const int narrow = b->count - (b->freq_mode ? 0 : b->group_count[BV_WIDE]);
-    BatchArgs a{b->d_items, narrow, const_cast<int32_t *>(d_perms), nullptr, nullptr, b->d_table, b->d_tile_work,
-                b->d_gwork};
+    BatchArgs a{b->d_items, narrow, const_cast<int32_t *>(d_perms), nullptr, nullptr, b->d_table, b->d_tile_work};
     hipError_t e = launch_table_batch(a, b->table_smem, st);
     for (size_t i = 0; i < b->wide_tables.size() && e == hipSuccess; ++i) {
         const WideTable &w = b->wide_tables[i];
@@ -1125,7 +1099,7 @@ extern "C" int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int6
     if (b->count == 0) return QAP_OK;
     hipStream_t st = (hipStream_t)stream;
     if (b->freq_mode) {
-        BatchArgs a{b->d_items, b->count, d_perms, d_best, d_done, b->d_table, b->d_tile_work, b->d_gwork};
+        BatchArgs a{b->d_items, b->count, d_perms, d_best, d_done, b->d_table, b->d_tile_work};
         return dev_err(launch_batch_freq(a, b->freq_smem, st));
     }
     const bool fork = b->nlanes > 1;
@@ -1136,7 +1110,7 @@ extern "C" int qap_batch_search_async(qap_batch_handle b, int32_t *d_perms, int6
         for (int g = b->lane_begin[l]; g < b->lane_begin[l + 1] && e == hipSuccess; ++g) {
             const int v = b->lane_groups[g];
             BatchArgs a{b->d_items + b->group_begin[v], b->group_count[v], d_perms, d_best, d_done, b->d_table,
-                        b->d_tile_work, b->d_gwork};
+                        b->d_tile_work};
             e = launch_batch_group(v, a, b->group_smem[v], ls);
         }
         if (fork && e == hipSuccess) e = hipEventRecord(b->ev_join[l], ls);
@@ -1158,7 +1132,6 @@ extern "C" int qap_batch_destroy(qap_batch_handle b) {
     if (b->d_items) (void)hipFree(b->d_items);
     if (b->d_table) (void)hipFree(b->d_table);
     if (b->d_tile_work) (void)hipFree(b->d_tile_work);
-    if (b->d_gwork) (void)hipFree(b->d_gwork);
     if (b->d_freq) (void)hipFree(b->d_freq);
     if (b->d_uloc) (void)hipFree(b->d_uloc);
     for (int v = 0; v < BV_COUNT; ++v) {

@@ -142,8 +142,6 @@ struct SearchArgs {
     int div;                 // with freq: diversification patience (0: none)
     int attr;                // with freq: tabu attribute, 0 pairs of locations, 1 units, 2 unit-locations
     int32_t *uloc;           // attr 2: [k][n][n] per search, until when a unit may not return to a location
-    uint8_t *gwork;          // wide streamed kernel: per search, gstride bytes holding G and G^T
-    long long gstride;
     long long *trace;        // with freq: [k][trace_cap][4] (r, s, delta, cost after) per move, or null
     int trace_cap;
 };
@@ -219,9 +217,6 @@ struct Item {
     // batched plans that keep the frequency memory: offsets of freq and uloc in the
     // plan's buffers (host side, while the plan is built)
     long long freq_off, uloc_off;
-    // batched launches, n above WIDE_N: offset of gmat in the launch's G scratch
-    long long g_off;
-    uint8_t *gmat;            // wide streamed kernel: G, then G^T (unless symmetric), rows of RS bytes
     // with freq: the first trace_cap moves as (r, s, delta, cost after), or null
     long long *trace;
     int trace_cap;
@@ -237,7 +232,6 @@ struct BatchArgs {
     int32_t *done;     // or null
     int32_t *table;    // neighbourhood of every start
     int4 *tile_work;   // tile state of the searches that run streamed
-    uint8_t *gwork;    // G and G^T of the searches above WIDE_N (Item::g_off)
 };
 
 hipError_t launch_cost(const TableArgs &a, hipStream_t st);
@@ -280,16 +274,12 @@ int search_max_lanes(int rows);
 int search_blocks_per_cu(int n, int rows, bool tabu, int lanes, int sym);
 // Streamed kernels (any n up to 256): tiles of STREAM_ROWS x 4 slots kept in global memory
 // between passes, D read from global memory, BATCH_LANES lanes per search.  The wide form
-// (n above WIDE_N, up to 512, single-instance searches only) also keeps G and G^T in
-// global memory (Item::gmat, wide_g_bytes(n, sym) per search) and runs up to four
-// (index, family) tasks per lane.
+// (n above WIDE_N, up to 512) keeps no G and G^T (it reads F and F^T through the
+// permutation) and runs up to four (index, family) tasks per lane.
 constexpr int STREAM_ROWS = 8;
 constexpr int WIDE_MAXN = 512;
 constexpr int WIDE_MAXT = 4 * WIDE_MAXN / BATCH_LANES;   // tasks a lane, n = 512 not symmetric
 int stream_shape_ok(int n, int sym, size_t max_smem);
-__host__ __device__ inline long long wide_g_bytes(int n, int sym) {
-    return (((long long)(sym ? 1 : 2) * n * row_stride(n)) + 255) & ~255LL;
-}
 // int4 of tile state one streamed search needs (deltas, then tabu-until values)
 __host__ __device__ inline long long stream_tile_int4(int ntiles) {
     const long long passes = (ntiles + BATCH_LANES - 1) / BATCH_LANES;
@@ -303,7 +293,7 @@ hipError_t launch_table_items(const Item *d_items, int count, size_t smem, hipSt
 hipError_t launch_resume(const Item *d_items, int count, size_t smem, hipStream_t st);
 // The same for items that keep the frequency memory (n up to WIDE_N).
 hipError_t launch_resume_freq(const Item *d_items, int count, size_t smem, hipStream_t st);
-// The same for items above WIDE_N (the wide streamed form; Item::gmat set).
+// The same for items above WIDE_N (the wide streamed form).
 hipError_t launch_resume_wide(const Item *d_items, int count, size_t smem, hipStream_t st);
 // Lanes of a search workgroup for a tile shape, or 0 if the shape cannot serve n.
 int search_lanes(int n, int rows, int ntiles, int sym);

@@ -1644,7 +1644,6 @@ batch_group_kernel(BatchArgs b) {
         it.tile_u = it.tile_d + stream_tile_int4(it.ntiles) / 2;
     }
     if constexpr (WIDE) {
-        it.gmat = b.gwork + it.g_off;
         search_body<STREAM_ROWS, true, WIDE_MAXT, false, true, false, false, true, 1>(it, sm);
     } else {
         search_body<ROWS, true, MAXT, false, STREAM, ROWS <= 4>(it, sm);
@@ -1709,7 +1708,7 @@ __global__ void __launch_bounds__(BATCH_LANES) resume_freq_kernel(const Item *it
 }
 
 // Chunked runs of searches above WIDE_N: block i runs one chunk of items[i] (the wide
-// streamed form, G and G^T at items[i].gmat).
+// streamed form).
 __global__ void __launch_bounds__(BATCH_LANES) resume_wide_kernel(const Item *items) {
     extern __shared__ __align__(16) unsigned char sm[];
     const Item it = items[blockIdx.x];
@@ -1753,7 +1752,6 @@ __global__ void __launch_bounds__(BATCH_LANES) stream_kernel(SearchArgs a) {
     it.tile_d = a.tile_work + (size_t)blockIdx.x * a.tile_stride;
     it.tile_u = it.tile_d + a.tile_stride / 2;
     if constexpr (WIDE) {
-        it.gmat = a.gwork + (size_t)blockIdx.x * a.gstride;
         search_body<STREAM_ROWS, TABU, WIDE_MAXT, false, true, false, FREQ, true, CT ? 2 : 0>(it, sm);
     } else {
         search_body<STREAM_ROWS, TABU, 1024 / BATCH_LANES, false, true, false, FREQ>(it, sm);
@@ -1863,7 +1861,6 @@ hipError_t launch_batch_group(int variant, const BatchArgs &b, size_t smem, hipS
             hipLaunchKernelGGL((batch_group_kernel<STREAM_ROWS, L, T, true>), dim3(b.count), dim3(L), smem, st, b);
             break;
         case BV_WIDE:
-            if (!b.gwork) return hipErrorInvalidValue;
             hipLaunchKernelGGL((batch_group_kernel<STREAM_ROWS, L, WIDE_MAXT, true, true>), dim3(b.count), dim3(L),
                                smem, st, b);
             break;
@@ -1910,8 +1907,7 @@ int stream_shape_ok(int n, int sym, size_t max_smem) {
 hipError_t launch_stream(bool tabu, const SearchArgs &a, int grid, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
     const size_t smem = stream_smem_bytes(a.n, a.sym);
-    if (a.n > WIDE_N) {   // G in a.gwork
-        if (!a.gwork) return hipErrorInvalidValue;
+    if (a.n > WIDE_N) {   // the wide form
         if (tabu && a.freq)
             hipLaunchKernelGGL((stream_kernel<true, true, true>), dim3(grid), dim3(BATCH_LANES), smem, st, a);
         else if (tabu && a.hi < TABU_RING)

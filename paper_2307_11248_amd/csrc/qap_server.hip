@@ -87,17 +87,16 @@ private:
 
 // Byte layout of one request's device state inside the pool.  Register-tile searches
 // save their neighbourhood as (delta, tabu until) pairs between chunks (st_du); streamed
-// searches keep their tiles in tile_work throughout, and above WIDE_N also G and G^T in
-// gwork (rebuilt from the saved permutation at the start of every chunk).
+// searches keep their tiles in tile_work throughout.
 struct Layout {
-    size_t mats, perm, st_perm, st_bestp, table, st_du, tile_work, gwork, freq, uloc, st_mark, total;
+    size_t mats, perm, st_perm, st_bestp, table, st_du, tile_work, freq, uloc, st_mark, total;
 };
 
 // own_mats: the request brought its own F and D (a copy lives in the pool); otherwise it
 // runs on an existing handle's device matrices.
 // freq: the request keeps the frequency memory (counts per packed pair), and with attr 2
 // the unit-location table, with attr 1 the unit marks between chunks.
-Layout layout_for(int n, int sym, bool streamed, int ntiles, bool own_mats = true, bool freq = false, int attr = 0) {
+Layout layout_for(int n, bool streamed, int ntiles, bool own_mats = true, bool freq = false, int attr = 0) {
     const size_t m = (size_t)n * (n - 1) / 2;
     Layout L{};
     size_t o = 0;
@@ -108,7 +107,6 @@ Layout layout_for(int n, int sym, bool streamed, int ntiles, bool own_mats = tru
     L.table = o;    o += up(m * 4 + 16);
     L.st_du = o;    if (!streamed) o += up(m * 8 + 16);
     L.tile_work = o; if (streamed) o += up((size_t)stream_tile_int4(ntiles) * sizeof(int4));
-    L.gwork = o;    if (n > WIDE_N) o += up((size_t)wide_g_bytes(n, sym));
     L.freq = o;     if (freq) o += up(m * 4 + 16);
     L.uloc = o;     if (freq && attr == 2) o += up((size_t)n * n * 4);
     L.st_mark = o;  if (freq && attr == 1) o += up((size_t)n * 4);
@@ -253,7 +251,6 @@ Item make_item(qap_server *s, const Request *r) {
         it.tile_d = reinterpret_cast<int4 *>(base + r->lay.tile_work);
         it.tile_u = it.tile_d + stream_tile_int4(ts.ntiles) / 2;
     }
-    if (r->n > WIDE_N) it.gmat = base + r->lay.gwork;
     if (r->freq) {
         it.freq = reinterpret_cast<int32_t *>(base + r->lay.freq);
         it.div = r->div;
@@ -311,7 +308,7 @@ int plan_request(qap_server *s, Request *r, int n) {
     if (rc != QAP_OK) return rc;
     r->streamed = r->rows < 0;
     const Tiles &ts = s->tiles[n * 16 + (r->streamed ? STREAM_ROWS : r->rows)];
-    r->lay = layout_for(n, r->sym, r->streamed, ts.ntiles, r->ext_mats == nullptr, r->freq, r->attr);
+    r->lay = layout_for(n, r->streamed, ts.ntiles, r->ext_mats == nullptr, r->freq, r->attr);
     if (up(r->lay.total) > s->pool_bytes) return QAP_E_NOMEM;   // could never be admitted
     return QAP_OK;
 }
@@ -561,7 +558,7 @@ int64_t qap_server_footprint(qap_server_handle s, int32_t n, int32_t sym) {
     if (rc != QAP_OK) return rc;
     int ninner = 0;
     const int nt = (int)enumerate_tiles(n, rows < 0 ? STREAM_ROWS : rows, &ninner).size();
-    return (int64_t)layout_for(n, sym ? 1 : 0, rows < 0, nt).total;
+    return (int64_t)layout_for(n, rows < 0, nt).total;
 }
 
 int qap_server_submit_matrices(qap_server_handle s, const int32_t *F, const int32_t *D, int32_t n,
