@@ -279,13 +279,6 @@ __device__ inline void dot_rows2_carry(const uint8_t *a, const uint8_t *b1, cons
     o2 = c2;
 }
 
-// 16 bytes a step (half the registers of the 32-byte form; for kernels held to 128 VGPRs,
-// where the wider steps spill)
-__device__ inline void dot_rows2_16(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, int rs, unsigned &o1,
-                                    unsigned &o2) {
-    dot_rows2_t<1>(a, b1, b2, rs, o1, o2);
-}
-
 // dot_rows2 for rows of exactly 64 bytes with every load in flight at once: one memory
 // latency instead of two (used where the kernel has registers to spare).
 __device__ inline void dot_rows2_64(const uint8_t *a, const uint8_t *b1, const uint8_t *b2, unsigned &o1,
@@ -1024,7 +1017,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 dot_rows2_u<1, WIDE_N>(shared, side1, side2, nb16, d1, d2);
             } else if constexpr (!TABU) {
                 dot_rows2_carry(shared, side1, side2, nb32, d1, d2);
-            } else if constexpr (!GGLOB && !FREQ) {
+            } else if constexpr (!FREQ) {
                 dot_rows2_u<2, WIDE_N>(shared, side1, side2, nb32, d1, d2);
             } else {
                 dot_rows2(shared, side1, side2, nb32, d1, d2);

@@ -114,6 +114,59 @@ def test_batch_every_kernel_variant_equals_oracle():
         h.close()
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 3, 5])
+def test_batch_side_stream_plan_does_not_change_results(lanes, monkeypatch):
+    """The batched launch deals its kernel variants to side streams (QAP_BATCH_LANES
+    overrides how many, read when the plan is made); one lane runs them all back to back,
+    five is more lanes than there are variants here.  Every count gives the oracle's
+    results, eagerly and from a captured graph replayed twice."""
+    import torch
+    monkeypatch.setenv("QAP_BATCH_LANES", str(lanes))
+    sizes = [30, 60, 50, 100, 130, 140]
+    rows = [2, 2, 4, 4, 4, 4]
+    k = [2, 2, 2, 2, 1, 2]
+    iters = 200
+    insts, lohi, seeds = mixed_batch(31 + sum(sizes), sizes, k)
+    note("batch side-stream lanes=%d sizes=%s" % (lanes, sizes))
+    hs = [qap.Handle(F, D) for F, D, _ in insts]
+    for h, r in zip(hs, rows):
+        h.set_tile_rows("batch", r)
+    starts = torch.from_numpy(np.concatenate([P.reshape(-1) for _, _, P in insts]).astype(np.int32)).cuda()
+    jobs, res = oracle_rows(insts, k, iters, lohi, seeds)
+    with qap.Batch(hs, k, iters, [a for a, _ in lohi], [b for _, b in lohi], seeds) as b:
+        want = {variant_of(n, r, t % 3 == 1) for t, (n, r) in enumerate(zip(sizes, rows))}
+        assert b.groups() == len(want) == 5, want   # r2 on 128/256 lanes, r4 on 256/512/768
+        stream = torch.cuda.Stream()
+        work = torch.empty_like(starts)
+        best = torch.empty(sum(k), dtype=torch.int64, device="cuda")
+        done = torch.empty(sum(k), dtype=torch.int32, device="cuda")
+        outs = []
+        with torch.cuda.stream(stream):
+            work.copy_(starts)
+            b.run_async(work, best, done, stream=stream)
+        torch.cuda.synchronize()
+        outs.append((work.cpu().numpy(), best.cpu().numpy(), done.cpu().numpy()))
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            work.copy_(starts)
+            b.run_async(work, best, done, stream=stream)
+        for _ in range(2):
+            work.fill_(0)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            outs.append((work.cpu().numpy(), best.cpu().numpy(), done.cpu().numpy()))
+    for p, c, d in outs:
+        off = 0
+        for (i, j), r in zip(jobs, res):
+            n = insts[i][0].shape[0]
+            row = sum(k[:i]) + j
+            assert (p[off:off + n] == r[0]).all() and c[row] == r[1] and d[row] == r[2], (lanes, i, j, n)
+            off += n
+    for h in hs:
+        h.close()
+
+
 def test_batch_invariance_against_single_instance_searches():
     w = W.c4_batch(m=24, k=4, iters=1200)
     note("batch invariance: 24 instances of the uneven workload, 4 starts x 1200 iterations")
@@ -229,7 +282,7 @@ def variant_of(n, rows, sym):
     if rows == 2:
         return "r2_128" if need <= 128 else ("r2_256" if need <= 256 else "r2")
     if rows == 4:
-        return "r4_256" if need <= 256 else ("r4" if nt <= 512 else "r4_768")
+        return "r4_256" if need <= 256 else ("r4" if need <= 512 else "r4_768")
     return "r8"
 
 
