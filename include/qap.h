@@ -251,7 +251,12 @@ int qap_tabu_with_table_async(qap_handle h, int32_t *d_perms, const int32_t *d_t
  * be run any number of times, one run at a time.  It is qap_batch_tables_async (every
  * start's neighbourhood table, Eq. (2), into the plan's scratch) followed by
  * qap_batch_search_async (every search, from those tables); the two halves may be
- * enqueued separately, in that order, on one stream.  qap_batch_size reports the number
+ * enqueued separately, in that order, on one stream.  The search half runs one kernel
+ * per tile-shape variant in use; with more than one, they run on side streams of the
+ * plan forked from and joined back to `stream` by events (one fewer side streams than
+ * the hardware queues HIP gives the process, GPU_MAX_HW_QUEUES, unless the environment
+ * variable QAP_BATCH_LANES, read by qap_batch_create, sets the count); results do not
+ * depend on it.  qap_batch_size reports the number
  * of starts and of permutation entries.  A device-side row that is not a permutation is
  * left as it is, with best cost INT64_MIN and moves QAP_E_NOT_PERM.
  * Blocking host forms (rows of perms are checked; QAP_E_NOT_PERM otherwise):
