@@ -103,8 +103,10 @@ __host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym, boo
         s.sv = take(families(sym) * 2 * rs);
     }
     // (streamed kernels) the two row dot products of every (index, family) task, made by
-    // whole waves (at n = 256 not symmetric the plan still fits: 156 880 bytes)
+    // whole waves, and below WIDE_N the side rows r and s of D and D^T, staged for them
+    // (at n = 256 not symmetric the plan still fits: 157 968 bytes)
     if (dglobal) s.xd = take(families(sym) * np * 8);
+    if (dglobal && !gglobal) s.sv = take((sym ? 2 : 4) * rs);
     s.total = o;
     return s;
 }

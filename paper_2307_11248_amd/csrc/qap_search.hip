@@ -375,11 +375,9 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     const int nbw = np / TILE_COLS;
     auto tbit_word = [&](int u, int v) -> unsigned * { return tbits + (u >> 3) * nbw + (v >> 2); };
     auto tbit = [&](int u, int v) -> unsigned { return 1u << (((u & 7) << 2) | (v & 3)); };
-    // (streamed kernels run whole, and the wide one) the two row dot products of task
-    // (u, family q) at xd[q * np + u], made by whole waves.  The chunked runs of the
-    // server keep the per-lane walk: their kernel carries every tile shape and is held to
-    // its registers, and the wave-made products measured slower there.
-    constexpr bool XW = STREAM && (GGLOB || !RESUME);
+    // (streamed kernels) the two row dot products of task (u, family q) at
+    // xd[q * np + u], made by whole waves
+    constexpr bool XW = STREAM;
     int2 *xd = XW ? reinterpret_cast<int2 *>(sm + S.xd) : nullptr;
 
     // ---- stage D, D^T; read and check the start
@@ -866,14 +864,46 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             swt_r = reinterpret_cast<const unsigned *>(GmT + r * rs)[swl];
             swt_s = reinterpret_cast<const unsigned *>(GmT + s * rs)[swl];
         }
+        // The lanes of task u split the bytes they all need and share them by DPP:
+        //   q=0: d_ur d_us D_rr D_rs   q=1: d_ru d_su D_sr D_ss
+        //   q=2: g_ur g_us G_rr G_rs   q=3: g_ru g_su G_sr G_ss   (g = G under p)
+        // (symmetric: q=0 the D bytes, q=1 the G bytes, plus D_ss / G_ss).  Register-tile
+        // kernels read them (from LDS) in the task loop below, streamed kernels here.
+        auto task_bytes = [&](int u, int q, unsigned (&b)[5]) {
+            const bool gfam = !(sym ? q == 0 : q < 2);
+            const uint8_t *M = gfam ? Gm : Dm;
+            const bool tr = !sym && (q & 1);
+            // entry (x, y) of D or G (the wide kernel reads G through F and p)
+            auto mat = [&](int x, int y) -> unsigned {
+                return GGLOB && gfam ? (unsigned)gF(x, y) : (unsigned)M[x * rs + y];
+            };
+            b[0] = mat(tr ? r : u, tr ? u : r);
+            b[1] = mat(tr ? s : u, tr ? u : s);
+            b[2] = mat(tr ? s : r, r);
+            b[3] = mat(tr ? s : r, s);
+            b[4] = sym ? mat(s, s) : 0;
+        };
+        // streamed kernels read those bytes of D (the wide kernel also of F) from global
+        // memory: all of them before the waves' dot products, each into a register of its
+        // own (lanes past the last task read task 0's), so that their latency hides there
+        unsigned rbv[XW ? MAXT : 1][5];
+        if constexpr (XW) {
+#pragma unroll
+            for (int i = 0; i < MAXT; ++i) {
+                const int tk = t + i * L;
+                const bool ok = tk < nq * n;
+                task_bytes(ok ? tk >> lq : 0, ok ? tk & (nq - 1) : 0, rbv[i]);
+            }
+        }
         // ---- X, streamed kernels: the row dot products of every task first, by whole
         //      waves.  Rows of D (and in the wide kernel of G) live in global memory, where
-        //      one lane walking a row of its own waits for every step; here eight lanes
-        //      share a row (64 bytes each, so a row is read in one contiguous stretch), a
-        //      wave takes eight rows a step (two steps in flight), family by family with
-        //      the two side rows held in registers, and the octet sums go to LDS for the
-        //      task lanes.
-        if constexpr (XW) {
+        //      one lane walking a row of its own waits for every step; here a few lanes
+        //      share a row (64 bytes each, so a row is read in one contiguous stretch):
+        //      eight in the wide kernel, a wave taking eight rows a step (two steps in
+        //      flight), family by family with the two side rows held in registers; four
+        //      below, with the global operands of two families in flight.  The partial
+        //      sums are added by DPP and go to LDS for the task lanes.
+        if constexpr (XW && GGLOB) {
             const int oc = lane >> 3, kb = (lane & 7) * 64;
             // wide kernel, no G: with j = p_k, the four families become
             //   f = 0: sum_k G[su][k] D[b][k]     = sum_j F[p_su][j]   D[b][pinv_j]
@@ -959,6 +989,105 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 }
             }
             __syncthreads();  // the task lanes read xd
+        } else if constexpr (XW) {
+            // n <= WIDE_N: a row is at most 256 bytes, so four lanes share a row (64 bytes
+            // each) and a wave takes 16 rows a step; the two steps of a wave cover every
+            // row of a family (2 * 8 waves * 16 rows = 256: streamed kernels run BATCH_LANES
+            // lanes).  The side rows r and s of D and D^T (families 0, 1), which every lane
+            // needs, are staged in LDS once; the rows of D and D^T that families 2, 3 walk
+            // are loaded into registers before that barrier, so a search waits about one
+            // memory round trip here.  G and G^T are read from LDS.  Every lane loads from
+            // an address inside a row; the bytes past nb16 (a lane's last chunks, for n
+            // below 256) are zeroed in the operand read from LDS, and the sums of rows
+            // u >= n are not stored.
+            const int oc = lane >> 2, kb = (lane & 3) * 64;
+            const uint4 z4 = make_uint4(0, 0, 0, 0);
+            auto dot16 = [](const uint4 &x, const uint4 &y, unsigned c) {
+                c = __builtin_amdgcn_udot4(x.x, y.x, c, false);
+                c = __builtin_amdgcn_udot4(x.y, y.y, c, false);
+                c = __builtin_amdgcn_udot4(x.z, y.z, c, false);
+                return __builtin_amdgcn_udot4(x.w, y.w, c, false);
+            };
+            // rows u of D or D^T (family q >= nq / 2) for the wave's two steps (rows past n
+            // read row 0; chunks past nb16 read the row's first bytes)
+            auto load_rows = [&](int q, uint4 (&b)[2][4]) {
+                const int f = sym ? 2 * q : q;
+                const uint8_t *Df = (f & 1) ? DmT : Dm;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int u = wid * 16 + h * W * 16 + oc;
+                    const uint8_t *row = Df + (u < n ? u : 0) * rs;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int o = kb + 16 * c;
+                        b[h][c] = *reinterpret_cast<const uint4 *>(row + (o < nb16 ? o : 0));
+                    }
+                }
+            };
+            constexpr int nh = nq / 2;   // families with the side rows in D (f < 2)
+            uint4 gp[nh][2][4];
+#pragma unroll
+            for (int q = 0; q < nh; ++q) load_rows(nh + q, gp[q]);
+            // side rows [f][r, s] into LDS, 16 bytes a lane
+            uint8_t *svd = sm + S.sv;
+            const int per = nb16 / 16;
+            for (int idx = t; idx < nh * 2 * per; idx += L) {
+                const int g = idx / per, c = idx - g * per;
+                const uint8_t *Df = (g >> 1) ? DmT : Dm;
+                *reinterpret_cast<uint4 *>(svd + g * rs + c * 16) =
+                    *reinterpret_cast<const uint4 *>(Df + ((g & 1) ? s : r) * rs + c * 16);
+            }
+            __syncthreads();   // the side rows are staged
+#pragma unroll
+            for (int q = 0; q < nq; ++q) {
+                const int f = sym ? 2 * q : q;
+                const uint8_t *Gf = (f & 1) ? GmT : Gm;
+                unsigned c1[2] = {0, 0}, c2[2] = {0, 0};
+                if (f < 2) {
+                    // rows su of G (or G^T) against the staged side rows r, s of D (or D^T)
+                    const uint8_t *sr = svd + (2 * q) * rs, *ss = svd + (2 * q + 1) * rs;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int o = kb + 16 * c, oo = o < nb16 ? o : 0;
+                        const uint4 v1 = *reinterpret_cast<const uint4 *>(sr + oo);
+                        const uint4 v2 = *reinterpret_cast<const uint4 *>(ss + oo);
+                        const uint4 a1 = o < nb16 ? v1 : z4, a2 = o < nb16 ? v2 : z4;
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int u = wid * 16 + h * W * 16 + oc;
+                            const int su = u >= n ? 0 : (u == r ? s : (u == s ? r : u));
+                            const uint4 x = *reinterpret_cast<const uint4 *>(Gf + su * rs + oo);
+                            c1[h] = dot16(x, a1, c1[h]);
+                            c2[h] = dot16(x, a2, c2[h]);
+                        }
+                    }
+                } else {
+                    // rows u of D (or D^T) against the side rows s, r of G (or G^T)
+                    uint4 (&b)[2][4] = gp[q - nh];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int o = kb + 16 * c, oo = o < nb16 ? o : 0;
+                        const uint4 v1 = *reinterpret_cast<const uint4 *>(Gf + s * rs + oo);
+                        const uint4 v2 = *reinterpret_cast<const uint4 *>(Gf + r * rs + oo);
+                        const uint4 a1 = o < nb16 ? v1 : z4, a2 = o < nb16 ? v2 : z4;
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            c1[h] = dot16(b[h][c], a1, c1[h]);
+                            c2[h] = dot16(b[h][c], a2, c2[h]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    // quad sums: quad_perm [1,0,3,2], then [2,3,0,1]
+                    int v1 = (int)c1[h], v2 = (int)c2[h];
+                    v1 += dpp<0xB1>(v1); v2 += dpp<0xB1>(v2);
+                    v1 += dpp<0x4E>(v1); v2 += dpp<0x4E>(v2);
+                    const int u = wid * 16 + h * W * 16 + oc;
+                    if ((lane & 3) == 0 && u < n) xd[q * np + u] = make_int2(v1, v2);
+                }
+            }
+            __syncthreads();  // the task lanes read xd
         }
         // ---- X: one (u, family) task per lane: the update vectors of u, and the deltas
         //      of (u, r) and (u, s) under p'
@@ -970,25 +1099,29 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         }
 #pragma unroll
         for (int i = 0; i < MAXT; ++i) {
-            const int tk = t + i * L;
+            int tk = t + i * L;
+            // streamed kernels: an opaque copy, so that the LDS addresses made from the task
+            // are made here each iteration rather than kept through the search (their
+            // registers are full, and spilled addresses cost a memory round trip to reload)
+            if constexpr (STREAM) asm volatile("" : "+v"(tk));
             if (tk >= nq * n) break;
             const int u = tk >> lq, q = tk & (nq - 1);
             const int f = sym ? 2 * q : q;   // 0 G.D, 1 G^T.D^T, 2 D.G, 3 D^T.G^T
             const int su = u == r ? s : (u == s ? r : u);
-            // The lanes of u split the bytes they all need and share them by DPP:
-            //   q=0: d_ur d_us D_rr D_rs   q=1: d_ru d_su D_sr D_ss
-            //   q=2: g_ur g_us G_rr G_rs   q=3: g_ru g_su G_sr G_ss   (g = G under p)
-            // (symmetric: q=0 the D bytes, q=1 the G bytes, plus D_ss / G_ss).
-            const bool gfam = !(sym ? q == 0 : q < 2);
-            const uint8_t *M = gfam ? Gm : Dm;
-            const bool tr = !sym && (q & 1);
-            // entry (x, y) of D or G (the wide kernel reads G through F and p)
-            auto mat = [&](int x, int y) -> unsigned {
-                return GGLOB && gfam ? (unsigned)gF(x, y) : (unsigned)M[x * rs + y];
-            };
-            const unsigned rec = mat(tr ? r : u, tr ? u : r) | (mat(tr ? s : u, tr ? u : s) << 8) |
-                                 (mat(tr ? s : r, r) << 16) | (mat(tr ? s : r, s) << 24);
-            const int ex = sym ? (int)mat(s, s) : 0;
+            unsigned rec;
+            int ex;
+            if constexpr (XW) {
+                rec = rbv[i][0] | (rbv[i][1] << 8) | (rbv[i][2] << 16) | (rbv[i][3] << 24);
+                ex = (int)rbv[i][4];
+            } else {
+                const bool gfam = !(sym ? q == 0 : q < 2);
+                const uint8_t *M = gfam ? Gm : Dm;
+                const bool tr = !sym && (q & 1);
+                auto mat = [&](int x, int y) -> unsigned { return (unsigned)M[x * rs + y]; };
+                rec = mat(tr ? r : u, tr ? u : r) | (mat(tr ? s : u, tr ? u : s) << 8) |
+                      (mat(tr ? s : r, r) << 16) | (mat(tr ? s : r, s) << 24);
+                ex = sym ? (int)mat(s, s) : 0;
+            }
 
             // dot products with the O(1) correction sum_k a[sigma k] c[k] = a.c + (a_s - a_r)(c_r - c_s),
             // a a row of G or G^T, c a row of D or D^T:
