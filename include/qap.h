@@ -280,7 +280,10 @@ int qap_batch_create(const qap_handle *hs, int32_t m, const int32_t *k_per, int3
  * every such search (n_i * n_i int32).  All searches of such a plan run in one launch of
  * 512-lane workgroups with tiles of 2, 4 or 8 rows or the streamed form (rows_per as for
  * qap_batch_create; by default the library's shape, or the next larger tile that fits 512
- * lanes).  QAP_E_INVALID for div < 0 or attr outside 0..2, otherwise as qap_batch_create.
+ * lanes).  QAP_E_INVALID for div < 0 or attr outside 0..2; QAP_E_UNSUPPORTED also for
+ * an instance whose shape leaves that kernel (which carries every shape and holds LDS
+ * of its own) too little LDS (general instances of n above about 245); otherwise as
+ * qap_batch_create.
  * qap_batch_run_async, qap_batch_tables_async and qap_batch_search_async run such plans
  * as any other; qap_batch_groups returns 1 and counts the searches per tile shape in the
  * slots of the 512-lane kernels and the streamed form.
@@ -387,7 +390,9 @@ int qap_server_set_queue_limit(qap_server_handle s, int32_t max_queued);
  * table, with attr 1 its unit marks between chunks, n (n - 1) / 2 + n^2 or + n int32 more),
  * and its result equals qap_tabu_freq_async on the handle with start_base 0, however it
  * was chunked.  Such requests run in a launch of their own each step.  On a handle only;
- * QAP_E_UNSUPPORTED above n = 256; otherwise as qap_server_submit.
+ * QAP_E_UNSUPPORTED above n = 256, and where that launch's kernel, which carries every
+ * tile shape, has too little LDS left for the request's (general, not symmetric,
+ * instances of n above about 245); otherwise as qap_server_submit.
  * qap_server_poll_freq is qap_server_poll that also copies the counts into freq_out (host
  * int32[n (n - 1) / 2], packed pair order; may be NULL); QAP_E_INVALID, leaving the
  * request alone, if freq_out is not NULL and the request was not submitted this way.

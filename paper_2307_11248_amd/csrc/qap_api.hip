@@ -849,12 +849,15 @@ namespace {
 // rows 2, 4, 8 or the streamed form).
 bool batch_freq_fits(const qap_ctx *h, int ri) {
     if (h->n > WIDE_N) return false;
-    if (ri == kStream) return h->stream_ok != 0;
+    // that kernel's own LDS (its marks and reductions, for every shape) comes on top
+    const size_t fs = freq_static_lds();
+    if (fs >= h->max_smem) return false;
+    if (ri == kStream) return h->stream_ok != 0 && stream_smem_bytes(h->n, h->sym) <= h->max_smem - fs;
     if (ri < kBatchFirst || ri > kBatchFirst + 2) return false;
     const TileSet &ts = h->tiles[ri];
     const int rows = kRowsChoices[ri];
     return ts.d_tiles && batch_shape_ok(h->n, rows, ts.ntiles, h->sym) &&
-           search_smem_bytes(h->n, rows, BATCH_LANES, h->sym) <= h->max_smem;
+           search_smem_bytes(h->n, rows, BATCH_LANES, h->sym) <= h->max_smem - fs;
 }
 
 int batch_create_impl(const qap_handle *hs, int32_t m, const int32_t *k_per, int32_t iters, const int32_t *lo_per,

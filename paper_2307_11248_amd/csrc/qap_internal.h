@@ -52,7 +52,7 @@ __host__ __device__ inline int families(int sym) { return sym ? 2 : 4; }
 // locations under the current permutation p), G^T; only D and G when F and D are
 // both symmetric.
 struct Smem {
-    int d, dt, g, gt, acbe, rpr, rps, kc, perm, bestp, pinv, ten, red, tb, ring, xd, sv, total;
+    int d, dt, g, gt, acbe, rpr, rps, kc, perm, bestp, pinv, ten, red, tb, ring, xd, sv, tv, total;
 };
 
 // Compact tabu state of the wide streamed kernel: moves of the last TABU_RING iterations
@@ -103,10 +103,15 @@ __host__ __device__ inline Smem smem_plan(int n, int np, int lanes, int sym, boo
         s.sv = take(families(sym) * 2 * rs);
     }
     // (streamed kernels) the two row dot products of every (index, family) task, made by
-    // whole waves, and below WIDE_N the side rows r and s of D and D^T, staged for them
-    // (at n = 256 not symmetric the plan still fits: 157 968 bytes)
+    // whole waves; below WIDE_N also the side rows r and s of D and D^T, staged for them,
+    // and RD_u, CD_u (ints) and d_uu (bytes) of every index (at n = 256 not symmetric the
+    // plan takes 160 272 bytes, and the kernels' static LDS, at most 9.6 KB, the rest)
+    s.tv = -1;
     if (dglobal) s.xd = take(families(sym) * np * 8);
-    if (dglobal && !gglobal) s.sv = take((sym ? 2 : 4) * rs);
+    if (dglobal && !gglobal) {
+        s.sv = take((sym ? 2 : 4) * rs);
+        s.tv = take(2 * np * 4 + np);
+    }
     s.total = o;
     return s;
 }
@@ -270,6 +275,10 @@ hipError_t launch_batch_group(int variant, const BatchArgs &b, size_t smem, hipS
 // Item::uloc): one launch of BATCH_LANES lanes over items of tile rows 2, 4, 8 and the
 // streamed form.
 hipError_t launch_batch_freq(const BatchArgs &b, size_t smem, hipStream_t st);
+// Static LDS of the kernels that run searches with the frequency memory for every tile
+// shape (batch_freq_kernel, resume_freq_kernel): a plan's dynamic LDS must leave room
+// for it (0 if the query fails).
+size_t freq_static_lds();
 int search_max_lanes(int rows);
 // Workgroups of the register-tile search kernel for this shape that fit on one compute
 // unit at once (HIP's occupancy query; 0 if it fails).

@@ -469,18 +469,32 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
     for (int w = 0; w < W; ++w) cur += red[w];
     long long best = cur;
     if (resume) best = st->best;   // cur is recomputed from the saved permutation
-    // per task: RD_u, CD_u, d_uu and g_uu of its u, kept in registers
-    int rdv[MAXT], cdv[MAXT], duv[MAXT], guv[MAXT];
+    // per task: RD_u, CD_u, d_uu and g_uu of its u, kept in registers; the streamed kernels
+    // below WIDE_N, whose registers are full, keep RD_u and CD_u in LDS (tv: np ints each,
+    // written by the lane of family 0 of u) and d_uu there too (tvd, np bytes), and read
+    // g_uu from G in LDS
+    constexpr bool TVL = STREAM && !GGLOB;
+    int *tv = TVL ? reinterpret_cast<int *>(sm + S.tv) : nullptr;
+    uint8_t *tvd = TVL ? sm + S.tv + 2 * np * 4 : nullptr;
+    int rdv[TVL ? 1 : MAXT], cdv[TVL ? 1 : MAXT], duv[TVL ? 1 : MAXT], guv[TVL ? 1 : MAXT];
+    if constexpr (TVL) {
+        for (int u = t; u < n; u += L) {
+            tv[u] = rpr[u];
+            tv[np + u] = rps[u];
+            tvd[u] = Dm[u * rs + u];
+        }
+    } else {
 #pragma unroll
-    for (int i = 0; i < MAXT; ++i) {
-        const int tk = t + i * L;
-        rdv[i] = cdv[i] = duv[i] = guv[i] = 0;
-        if (tk < nq * n) {
-            const int u = tk >> lq;
-            rdv[i] = rpr[u];
-            cdv[i] = rps[u];
-            duv[i] = Dm[u * rs + u];
-            guv[i] = GGLOB ? gF(u, u) : Gm[u * rs + u];
+        for (int i = 0; i < MAXT; ++i) {
+            const int tk = t + i * L;
+            rdv[i] = cdv[i] = duv[i] = guv[i] = 0;
+            if (tk < nq * n) {
+                const int u = tk >> lq;
+                rdv[i] = rpr[u];
+                cdv[i] = rps[u];
+                duv[i] = Dm[u * rs + u];
+                guv[i] = GGLOB ? gF(u, u) : Gm[u * rs + u];
+            }
         }
     }
 
@@ -1000,7 +1014,11 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             // an address inside a row; the bytes past nb16 (a lane's last chunks, for n
             // below 256) are zeroed in the operand read from LDS, and the sums of rows
             // u >= n are not stored.
-            const int oc = lane >> 2, kb = (lane & 3) * 64;
+            // (an opaque copy of the lane's row: the row and LDS addresses are made here each
+            // iteration, not kept through the search in registers the kernel does not have)
+            int oc = lane >> 2;
+            asm volatile("" : "+v"(oc));
+            const int kb = (lane & 3) * 64;
             const uint4 z4 = make_uint4(0, 0, 0, 0);
             auto dot16 = [](const uint4 &x, const uint4 &y, unsigned c) {
                 c = __builtin_amdgcn_udot4(x.x, y.x, c, false);
@@ -1212,12 +1230,24 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
             } else if (u == s) {
                 rdn = yf[2];
                 cdn = yf[3];
+            } else if constexpr (TVL) {
+                rdn = tv[u] - mul8(A, B);
+                cdn = tv[np + u] - mul8(C, E);
             } else {
                 rdn = rdv[i] - mul8(A, B);
                 cdn = cdv[i] - mul8(C, E);
             }
-            rdv[i] = rdn;
-            cdv[i] = cdn;
+            if constexpr (TVL) {
+                // after every lane of u has read them (the lanes of u are one quad of a
+                // wave, whose LDS reads and writes take effect in program order)
+                if (q == 0) {
+                    tv[u] = rdn;
+                    tv[np + u] = cdn;
+                }
+            } else {
+                rdv[i] = rdn;
+                cdv[i] = cdn;
+            }
             // (key-valued tiles: A and C scaled by 2^KSB, |A|, |C| <= 255, so every
             // difference of two still fits 16 bits)
             if (q == 0)
@@ -1241,7 +1271,7 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 // delta'(u, b) + RD'_b + CD'_b for b = r (q == 0) or b = s (q == 1)
                 const int X = q == 0 ? xf[0] : yf[0], Y = q == 0 ? xf[1] : yf[1];
                 const int Z = q == 0 ? xf[2] : yf[2], Wv = q == 0 ? xf[3] : yf[3];
-                const int duu = duv[i], guu = guv[i];
+                const int duu = TVL ? (int)tvd[u] : duv[i], guu = TVL ? (int)Gm[u * rs + u] : guv[i];
                 const int dbb = q == 0 ? D_rr : D_ss, gbb = q == 0 ? G_ss : G_rr;
                 const int dub = q == 0 ? d_ur : d_us, dbu = q == 0 ? d_ru : d_su;
                 const int gub = q == 0 ? g_us : g_ur, gbu = q == 0 ? g_su : g_ru;
@@ -1250,8 +1280,10 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
                 const int diag = mul8(dbb - duu, guu - gbb) + mul8(dbu - dub, gub - gbu);
                 (q == 0 ? rpr : rps)[u] = X + Y + Z + Wv - rdn - cdn - rowex - colex + diag;
             }
-            if (u == r) guv[i] = G_ss;
-            if (u == s) guv[i] = G_rr;
+            if constexpr (!TVL) {
+                if (u == r) guv[i] = G_ss;
+                if (u == s) guv[i] = G_rr;
+            }
             // this lane's share of exchanging columns r and s of G (and G^T) in row u
             if (!GGLOB && u != r && u != s) {
                 if (sym) {
@@ -2000,6 +2032,19 @@ hipError_t launch_batch_freq(const BatchArgs &b, size_t smem, hipStream_t st) {
     if (b.count <= 0) return hipSuccess;
     hipLaunchKernelGGL(batch_freq_kernel, dim3(b.count), dim3(BATCH_LANES), smem, st, b);
     return report(hipGetLastError(), "batch kernel launch");
+}
+
+size_t freq_static_lds() {
+    static const size_t bytes = [] {
+        size_t m = 0;
+        hipFuncAttributes fa{};
+        if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(batch_freq_kernel)) == hipSuccess)
+            m = fa.sharedSizeBytes > m ? fa.sharedSizeBytes : m;
+        if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(resume_freq_kernel)) == hipSuccess)
+            m = fa.sharedSizeBytes > m ? fa.sharedSizeBytes : m;
+        return m;
+    }();
+    return bytes;
 }
 
 hipError_t launch_resume_freq(const Item *d_items, int count, size_t smem, hipStream_t st) {

@@ -216,17 +216,20 @@ const Tiles *tiles_for(qap_server *s, int n, int rows, int *rc) {
 
 // The tile shape a request runs with: the smallest of 2, 4, 8 rows that fits the
 // register-tile kernel, else the streamed kernel (rows = -STREAM_ROWS; its wide form
-// above WIDE_N); -1 if none.
-int server_rows(qap_server *s, int n, int sym, int *rc) {
+// above WIDE_N); -1 if none.  freq: the request keeps the frequency memory, whose kernel
+// holds LDS of its own beside the plan's.
+int server_rows(qap_server *s, int n, int sym, int *rc, bool freq = false) {
     *rc = QAP_OK;
+    const size_t fs = freq ? freq_static_lds() : 0;
+    const size_t room = fs < s->max_smem ? s->max_smem - fs : 0;
     for (int rows : {2, 4, 8}) {
         if (n > WIDE_N) break;
         int ninner = 0;
         const int nt = (int)enumerate_tiles(n, rows, &ninner).size();
-        if (batch_shape_ok(n, rows, nt, sym) && search_smem_bytes(n, rows, BATCH_LANES, sym) <= s->max_smem)
+        if (batch_shape_ok(n, rows, nt, sym) && search_smem_bytes(n, rows, BATCH_LANES, sym) <= room)
             return tiles_for(s, n, rows, rc) ? rows : -1;
     }
-    if (stream_shape_ok(n, sym, s->max_smem)) return tiles_for(s, n, STREAM_ROWS, rc) ? -STREAM_ROWS : -1;
+    if (stream_shape_ok(n, sym, room)) return tiles_for(s, n, STREAM_ROWS, rc) ? -STREAM_ROWS : -1;
     *rc = QAP_E_UNSUPPORTED;
     return -1;
 }
@@ -304,7 +307,7 @@ int enqueue(qap_server *s, Request *r, int32_t n, const int32_t *start, int32_t 
 // Tile shape and layout of a request (s->mu held); QAP_OK or an error code.
 int plan_request(qap_server *s, Request *r, int n) {
     int rc = QAP_OK;
-    r->rows = server_rows(s, n, r->sym, &rc);
+    r->rows = server_rows(s, n, r->sym, &rc, r->freq);
     if (rc != QAP_OK) return rc;
     r->streamed = r->rows < 0;
     const Tiles &ts = s->tiles[n * 16 + (r->streamed ? STREAM_ROWS : r->rows)];

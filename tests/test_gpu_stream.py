@@ -113,3 +113,48 @@ def test_large_n_served_alone_and_in_mix():
         bp, bc, done, _ = oracle.tabu(F, D, p, it, lo, hi, seed, 0)
         got = res[t]
         assert (got[0] == bp).all() and got[1] == bc and got[2] == done
+
+
+def test_frequency_memory_next_to_the_lds_limit():
+    """Searches that keep the frequency memory at n = 256, where the streamed plan nearly
+    fills the 160 KB of LDS: one run alone (its kernel holds little LDS of its own) equals
+    the oracle; batched or served, a general instance is refused with QAP_E_UNSUPPORTED
+    (the kernel that carries every tile shape holds more LDS of its own, and the plan does
+    not fit beside it) rather than failing at launch, and a symmetric one (half the
+    matrices in LDS) is served and equals the oracle."""
+    import torch
+    rng = np.random.default_rng(7300)
+    n, iters = 256, 120
+    lo, hi = W.tabu_tenure_range(n)
+    F, D = W.random_instance(rng, n, 0, 99)
+    P = W.starts(rng, n, 1)
+    note("frequency memory at n=256: alone, batched and served")
+    with qap.Handle(F, D) as h:
+        dp = torch.from_numpy(P).cuda()
+        db = torch.zeros(1, dtype=torch.int64, device="cuda")
+        dd = torch.zeros(1, dtype=torch.int32, device="cuda")
+        df = torch.zeros((1, n * (n - 1) // 2), dtype=torch.int32, device="cuda")
+        h.tabu_freq_async(dp, iters, lo, hi, 5, db, df, dd, div=20)
+        torch.cuda.synchronize()
+        bp, bc, done, freq, _ = oracle.tabu_freq(F, D, P[0], iters, lo, hi, 5, 0, div=20)
+        assert (dp.cpu().numpy()[0] == bp).all() and int(db[0]) == bc and int(dd[0]) == done
+        assert (df.cpu().numpy()[0] == freq).all()
+        with pytest.raises(qap.QapError) as ei:
+            qap.Batch([h], [1], iters, [lo], [hi], [5], freq=True)
+        assert ei.value.code == qap.QAP_E_UNSUPPORTED
+        with qap.Server(1 << 28, 4, 0.2) as s:
+            with pytest.raises(qap.QapError) as ei:
+                s.submit_freq(h, P[0], iters, lo, hi, 5, div=20)
+            assert ei.value.code == qap.QAP_E_UNSUPPORTED
+    Fs, Ds = W.random_instance(rng, n, 0, 99, symmetric=True)
+    with qap.Handle(Fs, Ds) as h, qap.Server(1 << 28, 4, 0.2) as s:
+        t = s.submit_freq(h, P[0], iters, lo, hi, 9, div=20)
+        r = None
+        for _ in range(100000):
+            s.step()
+            r = s.poll_freq(t)
+            if r is not None:
+                break
+        assert r is not None, "server made no progress"
+    bp, bc, done, freq, _ = oracle.tabu_freq(Fs, Ds, P[0], iters, lo, hi, 9, 0, div=20)
+    assert (r[0] == bp).all() and r[1] == bc and (r[-1] == freq).all()
