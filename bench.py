@@ -8,7 +8,8 @@ The default workload is the uneven batch (--workload c4: 512 instances, n from 2
 150, 8 starts each, 5000 tabu iterations): every start of every instance runs in one
 launch of the batched kernels, and the step is a captured HIP graph (reset, tables,
 searches) replayed once per step.  Other workloads: c1, c2, c3-2opt, c3-tabu (single
-instances), c5 (the serving stream), wide (n = 512, the wide streamed kernel).
+instances), c5 (the serving stream), stream (n = 256, the streamed kernel), wide (n = 512,
+the wide streamed kernel).
 
 The roofline is priced in HBM bytes: a swap-delta eval (one neighbourhood entry made
 current for one step of one search) is an int32 read and write, 8 bytes, against the
@@ -52,6 +53,7 @@ TRAFFIC = {
     "c4_batched_uneven_tabu": {"bytes": int((2 * (65156.0 + 43345.67 + 8637.87 + 2649.54 + 1970.87)
                                              + (874.563 + 408.78 + 223.25 + 92.625 + 61.5)) * 1024),
                                "sources": "e7e3748223b9bbf6"},
+    "n256_dense_tabu": {"bytes": int((2 * 68646900.0 + 67775000.0) * 1024), "sources": "e7e3748223b9bbf6"},
     "n512_dense_tabu": {"bytes": int((2 * 141803000.0 + 266390000.0) * 1024), "sources": "e7e3748223b9bbf6"},
 }
 
@@ -87,7 +89,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3-2opt", "c3-tabu", "c4", "c5", "wide"])
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3-2opt", "c3-tabu", "c4", "c5", "stream", "wide"])
     ap.add_argument("--tile-rows", type=int, default=0,
                     help="tile rows of the searches (uneven batch: for every instance it fits, else the tuner's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -116,6 +118,8 @@ def load_workload(name):
         return W.c3_euclid128_2opt()
     if name == "c4":
         return W.c4_batch()
+    if name == "stream":
+        return W.stream_dense256()
     if name == "wide":
         return W.wide_dense512()
     return W.c3_euclid128_tabu()

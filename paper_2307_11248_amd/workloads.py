@@ -152,6 +152,17 @@ def wide_dense512(k: int = 256, iters: int = 2000) -> Workload:
     return Workload("n512_dense_tabu", "tabu", [Instance(F, D, starts(rng, n, k), 6, "wide")], iters)
 
 
+def stream_dense256(k: int = 256, iters: int = 2000) -> Workload:
+    """n=256 asymmetric dense (the largest n of the streamed kernel, as in the serving
+    stream's largest requests): F, D uniform [0,99]; tabu, k starts x iters, the tenure
+    range of the other tabu workloads."""
+    rng = rng_for(7)
+    n = 256
+    F = uniform_matrix(rng, n, 0, 99)
+    D = uniform_matrix(rng, n, 0, 99)
+    return Workload("n256_dense_tabu", "tabu", [Instance(F, D, starts(rng, n, k), 7, "stream")], iters)
+
+
 def c4_batch(m: int = 512, k: int = 8, iters: int = 5000, nmin: int = 20, nmax: int = 150) -> Workload:
     """m instances, n uniform in [nmin, nmax]; even index dense uniform, odd index sparse
     flow (80% zero) with grid-Manhattan distances; tabu with k starts each."""
