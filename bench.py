@@ -46,15 +46,15 @@ BYTES_PER_EVAL = 8   # an int32 delta read and written per entry per step if kep
 # valid only for the kernel sources they were taken with.
 KERNEL_SOURCES = ["paper_2307_11248_amd/csrc/qap_search.hip", "paper_2307_11248_amd/csrc/qap_internal.h"]
 TRAFFIC = {
-    "c2_n64_dense_tabu": {"bytes": int((2 * 725.5 + 40.0) * 1024), "sources": "e7e3748223b9bbf6"},
-    "c3_n128_euclid_tabu": {"bytes": int((2 * 4415.5 + 144.0) * 1024), "sources": "e7e3748223b9bbf6"},
+    "c2_n64_dense_tabu": {"bytes": int((2 * 725.5 + 40.0) * 1024), "sources": "c0b7ca82fda47dff"},
+    "c3_n128_euclid_tabu": {"bytes": int((2 * 4415.5 + 144.0) * 1024), "sources": "c0b7ca82fda47dff"},
     # per dispatch, summed over the kernels of one launch (tiles of 2 rows on 128 and 256
     # lanes, of 4 rows on 256, 512 and 768)
     "c4_batched_uneven_tabu": {"bytes": int((2 * (65156.0 + 43345.67 + 8637.87 + 2649.54 + 1970.87)
                                              + (874.563 + 408.78 + 223.25 + 92.625 + 61.5)) * 1024),
-                               "sources": "e7e3748223b9bbf6"},
-    "n256_dense_tabu": {"bytes": int((2 * 68646900.0 + 67775000.0) * 1024), "sources": "e7e3748223b9bbf6"},
-    "n512_dense_tabu": {"bytes": int((2 * 141803000.0 + 266390000.0) * 1024), "sources": "e7e3748223b9bbf6"},
+                               "sources": "c0b7ca82fda47dff"},
+    "n256_dense_tabu": {"bytes": int((2 * 68646900.0 + 67775000.0) * 1024), "sources": "c0b7ca82fda47dff"},
+    "n512_dense_tabu": {"bytes": int((2 * 141803000.0 + 266390000.0) * 1024), "sources": "c0b7ca82fda47dff"},
 }
 
 

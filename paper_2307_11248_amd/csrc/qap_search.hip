@@ -915,8 +915,9 @@ __device__ __attribute__((always_inline)) void search_body_t(const Item &a, unsi
         //      share a row (64 bytes each, so a row is read in one contiguous stretch):
         //      eight in the wide kernel, a wave taking eight rows a step (two steps in
         //      flight), family by family with the two side rows held in registers; four
-        //      below, with the global operands of two families in flight.  The partial
-        //      sums are added by DPP and go to LDS for the task lanes.
+        //      below, with the side rows of D staged in LDS and the rows of the D families
+        //      loaded first.  The partial sums are added by DPP and go to LDS for the task
+        //      lanes.
         if constexpr (XW && GGLOB) {
             const int oc = lane >> 3, kb = (lane & 7) * 64;
             // wide kernel, no G: with j = p_k, the four families become
